@@ -1,0 +1,73 @@
+/*
+ * mpsph_oracle.h -- FP64 CPU oracle for one relaxation step of the multi-phase SPH
+ * mesh generator of Ji, Fu, Hu & Adams, "A Consistent Parallel Isotropic Unstructured
+ * Mesh Generation Method based on Multi-phase SPH" (arXiv 1906.07925).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no code, header, table or
+ * helper with the GPU library; the two agree only on the mathematics.
+ *
+ * Conventions: positions are FP64, array-of-structs x[i*dim + a], in domain units.
+ * Particle types: 0 normal, 1 feature surface, 2 feature curve, 3 singularity (fixed)
+ * (paper §3.5).  All functions return 0 on success and a positive code on error.
+ */
+#ifndef MPSPH_ORACLE_H
+#define MPSPH_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_PERIODIC = 0, ORC_BOX = 1, ORC_ANNULUS = 2, ORC_BALL = 3 };
+enum { ORC_UNIFORM = 0, ORC_RADIAL_LINEAR = 1, ORC_SPHERE_DISTANCE = 2, ORC_RBF_EXP = 3 };
+enum { ORC_NORMAL = 0, ORC_SURFACE = 1, ORC_CURVE = 2, ORC_FIXED = 3 };
+enum { ORC_OK = 0, ORC_E_INVALID = 1, ORC_E_NOMEM = 2 };
+
+typedef struct {
+  int32_t dim;          /* 2 or 3 */
+  int32_t geometry;     /* ORC_PERIODIC | ORC_BOX | ORC_ANNULUS | ORC_BALL */
+  double lo[3], hi[3];  /* box (or bounding box) extents, domain units */
+  double centre[3];     /* annulus / ball centre */
+  double r_in, r_out;   /* annulus radii; ball radius is r_out */
+  int32_t field;        /* ORC_UNIFORM | ORC_RADIAL_LINEAR | ORC_SPHERE_DISTANCE | ORC_RBF_EXP */
+  double s0;            /* spacing scale of the size field: rho_t = s(x)^-dim */
+  double fcentre[3];    /* centre used by the radial / sphere-distance fields */
+  double fa, fb;        /* slope and reference radius of the size field */
+  int32_t n_rbf;
+  const double *rbf_centre; /* n_rbf*dim */
+  const double *rbf_coeff;  /* n_rbf */
+  double rbf_width;
+  double tau, kappa, p0, sigma0;
+  int64_t t0, t1;       /* surface-tension ramp (step index); t0 < 0: sigma constant */
+  double nu_coeff, c_acc, c_vel, c_visc;
+  int32_t search;       /* 0: cell grid, 1: brute force over all pairs */
+  int32_t pad_;
+} orc_params;
+
+typedef struct {
+  /* per-particle outputs, each may be NULL; vectors are n*dim */
+  double *rho, *rho_t, *h, *a, *a_abs, *vt, *at, *at_abs, *v, *dr, *nn;
+  /* scalars of the step */
+  double dt1, dt2, sigma, residual_l2, residual_linf, kinetic;
+  double elr_mean, elr_std, elr_min, elr_max;
+  int64_t pairs, interface_pairs, band_pairs, n_normal, n_elr, nonfinite;
+} orc_out;
+
+double orc_kernel_w(double r, double h, int32_t dim);
+double orc_kernel_dw(double r, double h, int32_t dim);
+double orc_sigma(const orc_params *p, int64_t step);
+double orc_spacing(const orc_params *p, const double *x);
+double orc_level_set(const orc_params *p, const double *x);
+int orc_field(const orc_params *p, int64_t n, const double *x, double *rho_t, double *h);
+double orc_field_integral(const orc_params *p, int32_t nq);
+int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, int32_t *type,
+             int64_t step, orc_out *out);
+int orc_pairs(const orc_params *p, int64_t n, const double *x, int64_t cap,
+              int64_t *pi, int64_t *pj, int64_t *count);
+int orc_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
