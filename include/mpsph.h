@@ -1,0 +1,187 @@
+/*
+ * mpsph.h -- C ABI of the MI355X (gfx950) relaxation-step library for the multi-phase SPH
+ * mesh generator of Ji, Fu, Hu & Adams, "A Consistent Parallel Isotropic Unstructured Mesh
+ * Generation Method based on Multi-phase SPH" (arXiv 1906.07925).
+ *
+ * One call of mpsph_step(ctx, 1) performs one pass of the main loop of the paper's
+ * Algorithm 1 on the GPU:
+ *   target density and scale at the particles           (§2.3 Eq. 1-2, §3.2 Eq. 15-16)
+ *   cell-linked neighbour structure                      (the neighbour-list line of Alg. 1)
+ *   density summation                                    (§3.3 Eq. 17)
+ *   pressure + surface-tension acceleration, gamma = 2   (§3.3 Eq. 18-19, 23-25)
+ *   force mapping of feature particles                   (§3.5 Eq. 30-31)
+ *   time step, mid-point velocity                        (§3.4 Eq. 29, 26)
+ *   viscous acceleration with rho = rho_t                (§3.3 Eq. 20-22)
+ *   time step, velocity, drift                           (§3.4 Eq. 29, 27-28)
+ *   feature projection / re-tagging                      (§3.5 Eq. 32, last line of Alg. 1)
+ *   FP64 global reductions of the step metrics
+ *
+ * Conventions shared by every entry point
+ *  - Status: every int-returning function returns MPSPH_OK (0) or a positive MPSPH_E_* code.
+ *    No exception crosses the ABI.  After a device error the context is poisoned and every
+ *    later call returns MPSPH_E_STATE until mpsph_destroy().
+ *  - Pointers named d_* are device pointers (HIP device memory on the context's device);
+ *    all other pointers are host pointers.  The caller owns every buffer it passes in; the
+ *    library never keeps a caller pointer after the call returns (parameter arrays are
+ *    copied at mpsph_create).
+ *  - Streams: every device operation of a context is enqueued on the hipStream_t given at
+ *    creation (NULL = the default stream).  mpsph_step() is asynchronous (no host sync);
+ *    mpsph_load(), mpsph_metrics(), mpsph_store(), mpsph_debug_*() synchronise that stream.
+ *  - Positions are float32, row-major n x dim (x of particle i at d_pos[i*dim + a]), in the
+ *    units of the domain given in mpsph_params.  Colours and types are int32 per particle.
+ *  - Particle types (§3.5): 0 normal, 1 feature surface, 2 feature curve, 3 singularity
+ *    (never moves).  A particle feels neighbour j only if type_j >= type_i.
+ *  - A context is not thread-safe; use one context per host thread / stream.
+ */
+#ifndef MPSPH_H
+#define MPSPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define MPSPH_API __attribute__((visibility("default")))
+#else
+#define MPSPH_API
+#endif
+
+enum {
+  MPSPH_OK = 0,
+  MPSPH_E_INVALID = 1,     /* bad argument or parameter */
+  MPSPH_E_NOMEM = 2,       /* device allocation failed or workspace too small */
+  MPSPH_E_DEVICE = 3,      /* a HIP call failed */
+  MPSPH_E_STATE = 4,       /* context poisoned by an earlier error, or not loaded */
+  MPSPH_E_NONFINITE = 5,   /* the last step produced a non-finite value */
+  MPSPH_E_UNSUPPORTED = 6  /* valid but unsupported configuration */
+};
+
+/* Meshing region: the positive phase of the level set (§3.1, Eq. 14). */
+enum { MPSPH_BOX = 1, MPSPH_ANNULUS = 2, MPSPH_BALL = 3 };
+
+/* Target size field s(x); rho_t = s^-dim (unit particle mass, Eq. 15), h = tau s (Eq. 16). */
+enum {
+  MPSPH_UNIFORM = 0,         /* s = s0 */
+  MPSPH_RADIAL_LINEAR = 1,   /* s = s0 (1 + fa (|x - fcentre| - fb)) */
+  MPSPH_SPHERE_DISTANCE = 2, /* s = s0 (1 + fa | |x - fcentre| - fb |) */
+  MPSPH_RBF_EXP = 3          /* s = s0 exp(sum_k c_k exp(-|x - mu_k|^2 / (2 w^2))) */
+};
+
+/* Per-particle quantities that mpsph_debug_fields() can export (values of the last step). */
+enum {
+  MPSPH_F_RHO = 0,    /* density summation, Eq. 17 (n) */
+  MPSPH_F_RHO_T = 1,  /* target density (n) */
+  MPSPH_F_H = 2,      /* smoothing length (n) */
+  MPSPH_F_A = 3,      /* pressure + surface-tension acceleration after projection (n x dim) */
+  MPSPH_F_A_ABS = 4,  /* sum over pairs of |pair term| of F_A (n) */
+  MPSPH_F_VT = 5,     /* mid-point velocity v~ (n x dim) */
+  MPSPH_F_AT = 6,     /* viscous acceleration after projection (n x dim) */
+  MPSPH_F_V = 7,      /* velocity v_{n+1/2} (n x dim) */
+  MPSPH_F_DR = 8,     /* displacement of the drift (n x dim) */
+  MPSPH_F_NN = 9,     /* distance to the nearest interacting neighbour, +inf if none (n) */
+  MPSPH_F_X0 = 10     /* start-of-step position (n x dim) */
+};
+
+typedef struct mpsph_ctx mpsph_ctx;
+
+typedef struct {
+  int32_t dim;             /* 2 or 3 */
+  int32_t geometry;        /* MPSPH_BOX | MPSPH_ANNULUS | MPSPH_BALL */
+  double lo[3], hi[3];     /* box, or bounding box of the annulus / ball, domain units */
+  double centre[3];        /* annulus / ball centre */
+  double r_in, r_out;      /* annulus radii; ball radius is r_out */
+  int32_t field;           /* MPSPH_UNIFORM ... MPSPH_RBF_EXP */
+  double s0;               /* field scale; <= 0: normalise so that the integral of rho_t is n */
+  double fcentre[3];
+  double fa, fb;           /* slope and reference radius of the radial fields */
+  int32_t n_rbf;           /* number of RBF terms (<= 64) */
+  const double *rbf_centre;/* host, n_rbf x dim, copied at create */
+  const double *rbf_coeff; /* host, n_rbf, copied at create */
+  double rbf_width;
+  double tau, kappa;       /* h = tau s; cut-off r_c = kappa h (support of the kernel) */
+  double p0, sigma0;       /* EOS constant (Eq. 18); initial surface-tension strength (Eq. 25) */
+  int64_t t0, t1;          /* ramp of sigma over steps (t0, t1]; t0 < 0: sigma constant */
+  double nu_coeff;         /* nu = nu_coeff r_c |v~| (Eq. 21), 0.1 in the paper */
+  double c_acc, c_vel, c_visc; /* constants of Eq. 29: 0.25, 1/40, 0.125 */
+  int32_t cell_log2;       /* cells per axis = 2^cell_log2; -1: chosen from the field */
+  int32_t debug;           /* 1: keep a~, v, dr and the nearest distance of the last step */
+} mpsph_params;
+
+typedef struct {
+  int64_t step;            /* index of the last completed step (steps done - 1), -1 if none */
+  int64_t pairs;           /* ordered pairs (i, j != i), r_ij < kappa h_ij, passing the mask */
+  int64_t interface_pairs; /* unordered pairs with r_ij < kappa h_ij and different colours */
+  int64_t candidates;      /* pair candidates tested by the first pair pass */
+  int64_t n_normal;        /* normal particles at the start of the step */
+  int64_t n_elr;           /* normal particles with at least one neighbour */
+  int64_t nonfinite;       /* particles with a non-finite acceleration or position */
+  int64_t n_feature;       /* particles of type >= 1 after the step */
+  double residual_l2;      /* sqrt(mean over normal particles of (rho/rho_t - 1)^2) */
+  double residual_linf;    /* max over normal particles of |rho/rho_t - 1| */
+  double kinetic;          /* 1/2 sum |v_{n+1/2}|^2, domain units */
+  double dt1, dt2;         /* the two time steps of Eq. 29 */
+  double sigma;            /* sigma(t) used in the step */
+  double elr_mean, elr_std, elr_min, elr_max; /* nearest distance x rho_t^(1/d), normal particles */
+} mpsph_metrics_t;
+
+/* Field scale s0 for which the integral over the meshing region of rho_t = s^-dim equals n
+ * (total mass of Eq. 4 with unit particle mass, used to fix the field constant).  Host-only
+ * quadrature; params->s0 is ignored.  Errors: MPSPH_E_INVALID for bad params or n <= 0. */
+MPSPH_API int mpsph_field_scale(const mpsph_params *params, int64_t n, double *s0_out);
+
+/* Device bytes a context for n particles needs (state, sort buffers, cell table, partials). */
+MPSPH_API size_t mpsph_workspace_bytes(const mpsph_params *params, int64_t n);
+
+/* Create a context for n >= 0 particles.  d_workspace: caller-owned device memory of at least
+ * mpsph_workspace_bytes() bytes that outlives the context, or NULL to let the library
+ * allocate (and free at destroy).  hip_stream: a hipStream_t or NULL.
+ * Errors: MPSPH_E_INVALID (params), MPSPH_E_NOMEM, MPSPH_E_DEVICE, MPSPH_E_UNSUPPORTED
+ * (cell grid too large, or a size field whose slope makes the neighbour bound diverge). */
+MPSPH_API int mpsph_create(const mpsph_params *params, int64_t n, void *d_workspace, size_t workspace_bytes,
+                 void *hip_stream, mpsph_ctx **out);
+
+/* Load the particle set: d_pos (n x dim float32, domain units), d_colour (n int32 in
+ * [0, 2^18)), d_type (n int32 in [0,3], or NULL for all normal).  Resets the step counter.
+ * Every position must lie inside the bounding box [lo, hi] (MPSPH_E_INVALID otherwise). */
+MPSPH_API int mpsph_load(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type);
+
+/* Enqueue nsteps >= 0 relaxation steps on the context's stream; returns without waiting. */
+MPSPH_API int mpsph_step(mpsph_ctx *ctx, int32_t nsteps);
+
+/* Metrics of the last step (synchronises the stream).  Returns MPSPH_E_NONFINITE (with the
+ * metrics still written) when that step produced non-finite values. */
+MPSPH_API int mpsph_metrics(mpsph_ctx *ctx, mpsph_metrics_t *out);
+
+/* Current positions (n x dim float32, domain units) and types (n int32) in the original
+ * particle order of mpsph_load().  Either pointer may be NULL.  Synchronises. */
+MPSPH_API int mpsph_store(mpsph_ctx *ctx, float *d_pos, int32_t *d_type);
+
+/* Copy one per-particle quantity of the last step (MPSPH_F_*) into d_out (float32, n or
+ * n x dim values, original particle order, domain units).  MPSPH_F_AT, MPSPH_F_V, MPSPH_F_DR
+ * and MPSPH_F_NN need params.debug = 1.  Synchronises.  Errors: MPSPH_E_INVALID (unknown field), MPSPH_E_STATE. */
+MPSPH_API int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out);
+
+/* Cell structure of the last step: d_key (n uint32, the cell key of each particle in
+ * original order: cx + 2^k cy + 4^k cz), d_cell_start (ncells + 1 uint32: index of the first
+ * sorted particle of each cell, last entry n) -- either may be NULL -- and the host values
+ * ncells and cell_log2.  Synchronises. */
+MPSPH_API int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cell_start, int64_t *ncells,
+                      int32_t *cell_log2);
+
+/* Per-kernel timing with HIP events on the context's stream.  enable = 1 starts recording
+ * (resets the accumulators), 0 stops.  mpsph_profile_read() synchronises and returns, for up
+ * to cap kernels, the name, the number of launches and the summed milliseconds. */
+MPSPH_API int mpsph_profile(mpsph_ctx *ctx, int32_t enable);
+MPSPH_API int mpsph_profile_read(mpsph_ctx *ctx, int32_t cap, const char **names, int64_t *launches,
+                       double *ms, int32_t *count);
+
+MPSPH_API void mpsph_destroy(mpsph_ctx *ctx);
+MPSPH_API const char *mpsph_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPSPH_H */

@@ -1,0 +1,1358 @@
+// Relaxation step of the multi-phase SPH mesh generator (Ji, Fu, Hu & Adams, arXiv 1906.07925)
+// on MI355X / gfx950.  The C ABI is declared in include/mpsph.h.
+//
+// Data layout (HBM, structure of arrays, n particles):
+//   state  (order of the previous step's sort): key u32, off float4 (cell offsets), ct u32
+//          (type | colour << 2), id u32 (index at load)
+//   work   (order of this step's sort): key u32, pos float4 (offsets, h), jaux u32
+//          (cx | type << 12 | colour << 14), id u32
+//   per step: acc float4 (a, sum|term|), rho f32, vt float4 (v~, eta), cell table u32[ncells+1]
+// Positions are an integer cell coordinate per axis (packed in the key, row-major, x fastest)
+// plus a float offset in [0, 1) in cell units, so pair separations are formed from exact
+// integer differences plus differences of numbers below one.  Lengths inside the kernels are
+// in cell units; accelerations and velocities are the domain values divided by the cell size
+// (time is unchanged; the EOS constant is scaled by cs^(d-2) to make this exact).
+//
+// Launch sequence of one step (all on the context stream, no host synchronisation):
+//   radix sort of the keys (3 kernels per 8-bit digit)
+//   reorder_field   gather the state in key order, evaluate the target field (Eq. 1-2, 16), fill
+//                   the cell table
+//   pass_density_force  density (Eq. 17), pressure + surface tension (Eq. 18-19, 23-25),
+//                   projection (Eq. 30-31), first time-step candidate (Eq. 29)
+//   kick            mid-point velocity (Eq. 26), viscosity (Eq. 21-22), second time step (Eq. 29)
+//   pass_viscous_integrate  viscous acceleration (Eq. 20), velocity (Eq. 27), drift (Eq. 28),
+//                   feature projection and re-tagging (Eq. 32)
+//   finalize        FP64 reduction of the per-block partials in a fixed order
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mpsph.h"
+#include "mpsph_device.h"
+#include "sort.h"
+
+using namespace mpsph;
+
+namespace {
+
+// ------------------------------------------------------------------------------------------
+// Kernels
+// ------------------------------------------------------------------------------------------
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void load_kernel(const float *__restrict__ pos, const int32_t *__restrict__ colour,
+                                                      const int32_t *__restrict__ type, int n, double lo0,
+                                                      double lo1, double lo2, double inv_cs, int k, int gmax,
+                                                      uint32_t *__restrict__ key, float4 *__restrict__ off,
+                                                      uint32_t *__restrict__ ct, uint32_t *__restrict__ id,
+                                                      int *__restrict__ bad) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double lo[3] = {lo0, lo1, lo2};
+  int c[3] = {0, 0, 0};
+  float o[3] = {0.f, 0.f, 0.f};
+  bool ok = true;
+  for (int a = 0; a < D; ++a) {
+    double X = ((double)pos[(size_t)i * D + a] - lo[a]) * inv_cs;
+    double f = floor(X);
+    float fo = (float)(X - f);
+    if (fo >= 1.0f) {
+      fo = 0.0f;
+      f += 1.0;
+    }
+    if (!(f >= 0.0 && f <= (double)gmax)) ok = false;
+    c[a] = ok ? (int)f : 0;
+    o[a] = ok ? fo : 0.f;
+  }
+  int col = colour[i];
+  int t = type ? type[i] : 0;
+  if (col < 0 || col >= (1 << 18) || t < 0 || t > 3) ok = false;
+  if (!ok) atomicOr(bad, 1);
+  key[i] = pack_key<D>(c, k);
+  off[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
+  ct[i] = (uint32_t)(t & 3) | ((uint32_t)col << 2);
+  id[i] = (uint32_t)i;
+}
+
+// Gather the state in sorted order, evaluate the size field (h = tau s, Eq. 16) and build the
+// cell table: cstart[c] = first sorted index with key >= c, cstart[ncells] = n.
+template <int D>
+__global__ __launch_bounds__(kBlock) void reorder_field(
+    int n, uint32_t ncells, GridDev g, FieldDev f, float tau, const uint32_t *__restrict__ skey,
+    const uint32_t *__restrict__ perm, const float4 *__restrict__ soff, const uint32_t *__restrict__ sct,
+    const uint32_t *__restrict__ sid, uint32_t *__restrict__ wkey, float4 *__restrict__ wpos,
+    uint32_t *__restrict__ wjaux, uint32_t *__restrict__ wid, uint32_t *__restrict__ cstart,
+    uint32_t *__restrict__ dtcells) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i == 0) {
+    dtcells[0] = kInfBits;
+    dtcells[1] = kInfBits;
+  }
+  if (i > n) return;
+  // cells (key[i-1], key[i]] start at sorted index i; the sentinel thread i = n closes the table
+  const uint32_t lo = i == 0 ? 0u : skey[i - 1] + 1u;
+  const uint32_t hi = i == n ? ncells : min(skey[i], ncells);
+  for (uint32_t c = lo; c <= hi; ++c) cstart[c] = (uint32_t)i;
+  if (i == n) return;
+  uint32_t s = perm[i];
+  uint32_t key = skey[i];
+  float4 o4 = soff[s];
+  uint32_t ct = sct[s];
+  int c[3];
+  unpack_key<D>(key, g.k, g.xmask, c);
+  float o[3] = {o4.x, o4.y, o4.z};
+  float sp = field_spacing<D>(f, c, o);
+  wkey[i] = key;
+  wpos[i] = make_float4(o4.x, o4.y, o4.z, tau * sp);
+  wjaux[i] = (uint32_t)c[0] | ((ct & 3u) << 12) | ((ct >> 2) << 14);
+  wid[i] = sid[s];
+}
+
+// Iterate over the neighbour candidates of particle i: every x-run of cells (fixed y, z) that
+// intersects the ball of radius rs around the particle is one contiguous range of the sorted
+// arrays.  body(j, cy, cz) is called for each candidate j != i.
+template <int D, typename F>
+__device__ __forceinline__ void for_candidates(int i, const int *ci, const float *oi, float rs, const GridDev &g,
+                                               const uint32_t *__restrict__ cstart, F &&body) {
+  // a finite, non-negative radius keeps every cell range inside [0, gmax] (NaN -> 0)
+  rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
+  const float rs2 = rs * rs;
+  const int z0 = D == 3 ? max(0, ci[2] + (int)floorf(oi[2] - rs)) : 0;
+  const int z1 = D == 3 ? min(g.gmax, ci[2] + (int)floorf(oi[2] + rs)) : 0;
+  const int y0 = max(0, ci[1] + (int)floorf(oi[1] - rs));
+  const int y1 = min(g.gmax, ci[1] + (int)floorf(oi[1] + rs));
+  for (int cz = z0; cz <= z1; ++cz) {
+    float ez = 0.f;
+    if constexpr (D == 3) {
+      float lo = (float)(cz - ci[2]) - oi[2], hi = lo + 1.f;
+      ez = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
+    }
+    for (int cy = y0; cy <= y1; ++cy) {
+      float lo = (float)(cy - ci[1]) - oi[1], hi = lo + 1.f;
+      float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
+      float d2 = ey * ey + ez * ez;
+      if (d2 >= rs2) continue;
+      float wx = sqrtf(rs2 - d2);
+      int x0 = max(0, ci[0] + (int)floorf(oi[0] - wx));
+      int x1 = min(g.gmax, ci[0] + (int)floorf(oi[0] + wx));
+      uint32_t kb = (uint32_t)x0 | ((uint32_t)cy << g.k);
+      if constexpr (D == 3) kb |= (uint32_t)cz << (2 * g.k);
+      const uint32_t j0 = cstart[kb], j1 = min(cstart[kb + (uint32_t)(x1 - x0) + 1u], (uint32_t)g.n);
+      for (uint32_t j = j0; j < j1; ++j) {
+        if ((int)j == i) continue;
+        body((int)j, cy, cz);
+      }
+    }
+  }
+}
+
+// Pass 1: density (Eq. 17, self term included, radius kappa h_i) and
+//   a_i = -sum_j (1 + beta_ij) (P_i + P_j) dW(r_ij, h_ij)/dr e_ij   (Eq. 18, 23; gamma = 2, Eq. 19)
+// with e_ij = r_ij / |r_ij|, r_ij = r_i - r_j, beta_ij = sigma for different colours (Eq. 24),
+// P = p0 / rho_t^2, h_ij = (h_i + h_j)/2, over j with r_ij < kappa h_ij that particle i feels.
+template <int D>
+__global__ __launch_bounds__(kBlock) void pass_density_force(
+    int n, GridDev g, StepDev sp, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
+    const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ cstart, float4 *__restrict__ acc,
+    float *__restrict__ rho_out, float *__restrict__ nn_out, uint32_t *__restrict__ dtcells,
+    double *__restrict__ partials) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int i = lb * kBlock + threadIdx.x;
+  const bool active = i < n;
+  double part[12];
+  const int ops[12] = {0, 2, 0, 0, 0, 1, 2, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < 12; ++s) part[s] = 0.0;
+  part[5] = INFINITY;
+  float dtc = INFINITY;
+  if (active) {
+    int ci[3];
+    unpack_key<D>(wkey[i], g.k, g.xmask, ci);
+    const float4 pi = wpos[i];
+    const float oi[3] = {pi.x, pi.y, pi.z};
+    const uint32_t ai = wjaux[i];
+    const int ti = (ai >> 12) & 3;
+    const uint32_t coli = ai >> 14;
+    const float hi = pi.w;
+    const float si = hi * sp.inv_tau;                 // target spacing, rho_t = s^-d
+    const float si2 = si * si;
+    const float Pi = sp.p0c * powd<D>(si2);           // p0 / rho_t^2 = p0 s^(2d)
+    const float ihi = fast_rcp(hi);
+    const float rci = sp.kappa * hi, rci2 = rci * rci;
+    const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
+    const float kh = 0.5f * sp.kappa;
+    float wsum = 0.f, ax = 0.f, ay = 0.f, az = 0.f, A = 0.f, nn2 = INFINITY;
+    uint32_t npair = 0, nifc = 0, ncand = 0;
+    for_candidates<D>(i, ci, oi, rs, g, cstart, [&](int j, int cy, int cz) {
+      const float4 pj = wpos[j];
+      const uint32_t aj = wjaux[j];
+      const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+      const float dy = (float)(ci[1] - cy) + (oi[1] - pj.y);
+      float r2 = dx * dx + dy * dy;
+      float dz = 0.f;
+      if constexpr (D == 3) {
+        dz = (float)(ci[2] - cz) + (oi[2] - pj.z);
+        r2 += dz * dz;
+      }
+      ++ncand;
+      const float hij = kh * (hi + pj.w);             // kappa h_ij
+      const float rcij2 = hij * hij;
+      const bool dens = r2 < rci2;
+      const bool inter = r2 < rcij2;
+      if (!(dens || inter)) return;
+      const float rinv = fast_rsq(r2);
+      const float r = r2 * rinv;
+      if (dens) {
+        const float q = r * ihi, u = 1.f - 0.5f * q, u2 = u * u;
+        wsum += u2 * u2 * (1.f + 2.f * q);
+      }
+      if (!inter) return;
+      nn2 = fminf(nn2, r2);
+      const uint32_t colj = aj >> 14;
+      const int tj = (aj >> 12) & 3;
+      if (colj != coli) ++nifc;
+      if (tj < ti) return;
+      ++npair;
+      if (!(r2 > 0.f)) return;
+      const float ih = sp.kappa * fast_rcp(hij);      // 1 / h_ij
+      const float q = r * ih, u = 1.f - 0.5f * q;
+      float ihp = ih * ih * ih;                       // h_ij^-(d+1)
+      if constexpr (D == 3) ihp *= ih;
+      const float sj = pj.w * sp.inv_tau, sj2 = sj * sj;
+      const float Pj = sp.p0c * powd<D>(sj2);
+      const float beta = colj != coli ? sp.sigma : 0.f;
+      // dW/dr = alpha h^-(d+1) (-5 q) (1 - q/2)^3
+      const float s = (1.f + beta) * (Pi + Pj) * sp.alpha * ihp * 5.f * q * u * u * u * rinv;
+      ax += s * dx;
+      ay += s * dy;
+      az += s * dz;
+      A += s * r;
+    });
+    const float ihd = D == 3 ? ihi * ihi * ihi : ihi * ihi;
+    const float rho = sp.alpha * ihd * (1.f + wsum);
+    float a[3] = {ax, ay, az};
+    project_feature<D>(g, ti, ci, oi, a);
+    acc[i] = make_float4(a[0], a[1], D == 3 ? a[2] : 0.f, A);
+    rho_out[i] = rho;
+    if (nn_out) nn_out[i] = sqrtf(nn2);
+    float am2 = a[0] * a[0] + a[1] * a[1] + (D == 3 ? a[2] * a[2] : 0.f);
+    if (ti != 3 && am2 > 0.f) dtc = sp.c_acc * sqrtf(rci * fast_rsq(am2));
+    bool fin = isfinite(am2) && isfinite(rho);
+    if (ti == 0) {
+      double e = (double)(rho * powd<D>(si)) - 1.0;   // rho / rho_t - 1
+      part[0] = e * e;
+      part[1] = fabs(e);
+      part[2] = 1.0;
+      if (nn2 < INFINITY) {
+        double elr = (double)sqrtf(nn2) / (double)si;
+        part[3] = elr;
+        part[4] = elr * elr;
+        part[5] = elr;
+        part[6] = elr;
+        part[7] = 1.0;
+      }
+    }
+    part[8] = (double)npair;
+    part[9] = (double)nifc;
+    part[10] = (double)ncand;
+    part[11] = fin ? 0.0 : 1.0;
+  }
+  // time-step candidate: wave min then one atomic per wave (order-free)
+  for (int off = kWave / 2; off > 0; off >>= 1) dtc = fminf(dtc, __shfl_xor(dtc, off, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0 && dtc < INFINITY) atomic_min_pos(&dtcells[0], dtc);
+  block_reduce_write<12>(part, ops, partials + (size_t)lb * kNumPartials);
+}
+
+// Mid-point velocity v~ = a dt1 / 2 (Eq. 26 with the velocity reset v_n = 0), viscosity
+// nu = nu_coeff r_c |v~| (Eq. 21), eta = rho_t nu (Eq. 22), and the second time-step
+// candidate: min of the three criteria of Eq. 29.
+template <int D>
+__global__ __launch_bounds__(kBlock) void kick(int n, StepDev sp, const float4 *__restrict__ wpos,
+                                               const uint32_t *__restrict__ wjaux, const float4 *__restrict__ acc,
+                                               float4 *__restrict__ vt, uint32_t *__restrict__ dtcells) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  float dtc = INFINITY;
+  if (i < n) {
+    float dt1 = __uint_as_float(dtcells[0]);
+    if (!(dt1 < INFINITY)) dt1 = 0.f;
+    const float4 a = acc[i];
+    const int t = (wjaux[i] >> 12) & 3;
+    const float h = wpos[i].w;
+    const float rc = sp.kappa * h;
+    const float s = h * sp.inv_tau;
+    const float hd = 0.5f * dt1;
+    float v[3] = {a.x * hd, a.y * hd, a.z * hd};
+    if (t == 3) v[0] = v[1] = v[2] = 0.f;
+    const float vm = sqrtf(v[0] * v[0] + v[1] * v[1] + (D == 3 ? v[2] * v[2] : 0.f));
+    const float nu = sp.nu_coeff * rc * vm;
+    const float eta = nu / powd<D>(s);               // rho_t nu, rho_t = s^-d
+    vt[i] = make_float4(v[0], v[1], v[2], eta);
+    if (t != 3) {
+      const float am2 = a.x * a.x + a.y * a.y + (D == 3 ? a.z * a.z : 0.f);
+      if (am2 > 0.f) dtc = fminf(dtc, sp.c_acc * sqrtf(rc * fast_rsq(am2)));
+      if (vm > 0.f) dtc = fminf(dtc, sp.c_vel * rc / vm);
+      if (nu > 0.f) dtc = fminf(dtc, sp.c_visc * rc * rc / nu);
+    }
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) dtc = fminf(dtc, __shfl_xor(dtc, off, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0 && dtc < INFINITY) atomic_min_pos(&dtcells[1], dtc);
+}
+
+// Box type from the number of faces a particle lies on.
+__device__ __forceinline__ int type_from_faces(int nf, int d) {
+  return nf <= 0 ? 0 : (nf == 1 ? 1 : (nf == 2 ? (d == 3 ? 2 : 3) : 3));
+}
+
+// Pass 2: viscous acceleration (Eq. 20 with rho = rho_t, Eq. 22)
+//   a~_i = sum_j [2 eta_i eta_j / (eta_i + eta_j)] (1/rho_t,i^2 + 1/rho_t,j^2) dW(r_ij,h_ij)/dr v~_ij / r_ij
+// over the same pairs as pass 1, then per particle: projection, v = v~ + a~ dt2 / 2 (Eq. 27),
+// drift r += v dt2 (Eq. 28), feature projection / re-tagging (Eq. 32); the new state is
+// written in this step's sorted order.
+template <int D>
+__global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
+    int n, GridDev g, StepDev sp, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
+    const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ wid, const uint32_t *__restrict__ cstart,
+    const float4 *__restrict__ vt, const uint32_t *__restrict__ dtcells, uint32_t *__restrict__ skey,
+    float4 *__restrict__ soff, uint32_t *__restrict__ sct, uint32_t *__restrict__ sid, float4 *__restrict__ at_out,
+    float4 *__restrict__ v_out, float4 *__restrict__ dr_out, double *__restrict__ partials) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int i = lb * kBlock + threadIdx.x;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  const int ops[4] = {0, 0, 0, 0};
+  if (i < n) {
+    int ci[3];
+    unpack_key<D>(wkey[i], g.k, g.xmask, ci);
+    const float4 pi = wpos[i];
+    float oi[3] = {pi.x, pi.y, pi.z};
+    const uint32_t ai = wjaux[i];
+    int ti = (ai >> 12) & 3;
+    const float hi = pi.w;
+    const float si = hi * sp.inv_tau, si2 = si * si;
+    const float invi = powd<D>(si2);                  // 1 / rho_t,i^2
+    const float4 vi = vt[i];
+    const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
+    const float kh = 0.5f * sp.kappa;
+    float bx = 0.f, by = 0.f, bz = 0.f;
+    // with eta_i = 0 every harmonic-mean viscosity of particle i vanishes: nothing to sum
+    if (vi.w > 0.f) {
+      for_candidates<D>(i, ci, oi, rs, g, cstart, [&](int j, int cy, int cz) {
+        const float4 pj = wpos[j];
+        const uint32_t aj = wjaux[j];
+        const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+        const float dy = (float)(ci[1] - cy) + (oi[1] - pj.y);
+        float r2 = dx * dx + dy * dy;
+        if constexpr (D == 3) {
+          const float dz = (float)(ci[2] - cz) + (oi[2] - pj.z);
+          r2 += dz * dz;
+        }
+        const float hij = kh * (hi + pj.w);
+        if (!(r2 < hij * hij)) return;
+        if ((int)((aj >> 12) & 3) < ti || !(r2 > 0.f)) return;
+        const float4 vj = vt[j];
+        const float esum = vi.w + vj.w;
+        if (!(esum > 0.f)) return;
+        const float rinv = fast_rsq(r2);
+        const float r = r2 * rinv;
+        const float ih = sp.kappa * fast_rcp(hij);
+        const float q = r * ih, u = 1.f - 0.5f * q;
+        float ihp = ih * ih * ih;
+        if constexpr (D == 3) ihp *= ih;
+        const float sj = pj.w * sp.inv_tau, sj2 = sj * sj;
+        const float etaij = 2.f * vi.w * vj.w / esum;
+        const float inv2 = invi + powd<D>(sj2);
+        // dW/dr / r = -5 alpha h^-(d+1) q (1 - q/2)^3 / r
+        const float s = -etaij * inv2 * sp.alpha * ihp * 5.f * q * u * u * u * rinv;
+        bx += s * (vi.x - vj.x);
+        by += s * (vi.y - vj.y);
+        if constexpr (D == 3) bz += s * (vi.z - vj.z);
+      });
+    }
+    float b[3] = {bx, by, bz};
+    project_feature<D>(g, ti, ci, oi, b);
+    float dt2 = __uint_as_float(dtcells[1]);
+    if (!(dt2 < INFINITY)) dt2 = 0.f;
+    float v[3] = {vi.x + 0.5f * b[0] * dt2, vi.y + 0.5f * b[1] * dt2, vi.z + 0.5f * b[2] * dt2};
+    if (ti == 3) v[0] = v[1] = v[2] = 0.f;
+    float dr[3] = {v[0] * dt2, v[1] * dt2, v[2] * dt2};
+    float ke = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ke += 0.5f * v[a] * v[a];
+    bool fin = isfinite(b[0]) && isfinite(b[1]) && isfinite(b[2]) && isfinite(dr[0]) && isfinite(dr[1]) &&
+               isfinite(dr[2]);
+    // drift in (cell, offset) form with carry
+    int c[3] = {ci[0], ci[1], D == 3 ? ci[2] : 0};
+    float o[3] = {oi[0], oi[1], D == 3 ? oi[2] : 0.f};
+    if (ti != 3 && fin) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        float x = o[a] + dr[a];
+        float fl = floorf(x);
+        c[a] += (int)fl;
+        o[a] = x - fl;
+        if (o[a] >= 1.f) {
+          o[a] = 0.f;
+          c[a] += 1;
+        }
+      }
+      if (g.geometry == 1) {
+        // box: closest-point projection is a clamp to the walls; type from the faces touched
+        int nf = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          if (c[a] < 0) {
+            c[a] = 0;
+            o[a] = 0.f;
+          }
+          if (c[a] > g.whi_c[a] || (c[a] == g.whi_c[a] && o[a] > g.whi_o[a])) {
+            c[a] = g.whi_c[a];
+            o[a] = g.whi_o[a];
+          }
+          if ((c[a] == 0 && o[a] == 0.f) || (c[a] == g.whi_c[a] && o[a] == g.whi_o[a])) ++nf;
+        }
+        ti = max(ti, type_from_faces(nf, D));
+      } else {
+        // annulus / ball: radial projection onto the nearest boundary circle / sphere
+        float rel[3], r2 = 0.f;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          rel[a] = (float)(c[a] - g.gc_c[a]) + (o[a] - g.gc_o[a]);
+          r2 += rel[a] * rel[a];
+        }
+        const float rr = sqrtf(r2);
+        const float phi = g.geometry == 2 ? fminf(rr - g.r_in, g.r_out - rr) : g.r_out - rr;
+        if (ti != 0 || phi < 0.f) {
+          float rb = g.r_out;
+          if (g.geometry == 2 && (rr - g.r_in) < (g.r_out - rr)) rb = g.r_in;
+          const float sc = rb / rr;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            // new coordinate relative to the origin of cell c[a]: centre + rel * rb / |rel|
+            const float x = (float)(g.gc_c[a] - c[a]) + g.gc_o[a] + rel[a] * sc;
+            const float fl = floorf(x);
+            c[a] += (int)fl;
+            o[a] = x - fl;
+            if (o[a] >= 1.f) {
+              o[a] = 0.f;
+              c[a] += 1;
+            }
+            if (c[a] < 0) {
+              c[a] = 0;
+              o[a] = 0.f;
+            }
+            if (c[a] > g.gmax) {
+              c[a] = g.gmax;
+              o[a] = 0.f;
+            }
+          }
+          ti = max(ti, 1);
+        }
+      }
+    }
+    // keys must stay inside the grid whatever the arithmetic above produced
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      if (!(o[a] >= 0.f && o[a] < 1.f)) o[a] = 0.f;
+      if (c[a] < 0) {
+        c[a] = 0;
+        o[a] = 0.f;
+      }
+      if (c[a] > g.gmax) {
+        c[a] = g.gmax;
+        o[a] = 0.f;
+      }
+    }
+    skey[i] = pack_key<D>(c, g.k);
+    soff[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
+    sct[i] = (uint32_t)ti | ((ai >> 14) << 2);
+    sid[i] = wid[i];
+    if (at_out) at_out[i] = make_float4(b[0], b[1], b[2], 0.f);
+    if (v_out) v_out[i] = make_float4(v[0], v[1], v[2], 0.f);
+    if (dr_out) dr_out[i] = make_float4(dr[0], dr[1], dr[2], 0.f);
+    part[0] = (double)ke;
+    part[1] = fin ? 0.0 : 1.0;
+    part[2] = ti != 0 ? 1.0 : 0.0;
+  }
+  block_reduce_write<4>(part, ops, partials + (size_t)lb * kNumPartials + P_KE);
+}
+
+// Reduce the per-block partials in a fixed order into the metrics block:
+//   m[0..]: e2, emax, nnorm, elr, elr2, elrmin, elrmax, nelr, pairs, ifc, cand, nonfin1, ke,
+//   nonfin2, nfeat, spare, then dt1, dt2 (as stored, +inf -> 0).
+__global__ __launch_bounds__(256) void finalize(int nblocks, const double *__restrict__ partials,
+                                                const uint32_t *__restrict__ dtcells, double *__restrict__ m) {
+  __shared__ double red[256];
+  for (int s = 0; s < kNumPartials; ++s) {
+    const int op = (s == P_EMAX || s == P_ELRMAX) ? 2 : (s == P_ELRMIN ? 1 : 0);
+    double x = op == 1 ? INFINITY : 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
+      double y = partials[(size_t)b * kNumPartials + s];
+      x = op == 0 ? x + y : (op == 1 ? fmin(x, y) : fmax(x, y));
+    }
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        double y = red[threadIdx.x + w];
+        double z = red[threadIdx.x];
+        red[threadIdx.x] = op == 0 ? z + y : (op == 1 ? fmin(z, y) : fmax(z, y));
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) m[s] = red[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    float d1 = __uint_as_float(dtcells[0]), d2 = __uint_as_float(dtcells[1]);
+    m[16] = d1 < INFINITY ? (double)d1 : 0.0;
+    m[17] = d2 < INFINITY ? (double)d2 : 0.0;
+  }
+}
+
+// Positions back to domain units in the load order.
+template <int D>
+__global__ __launch_bounds__(kBlock) void store_kernel(int n, int k, uint32_t mask, double lo0, double lo1, double lo2,
+                                                       double cs, const uint32_t *__restrict__ skey,
+                                                       const float4 *__restrict__ soff, const uint32_t *__restrict__ sct,
+                                                       const uint32_t *__restrict__ sid, float *__restrict__ pos,
+                                                       int32_t *__restrict__ type) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int c[3];
+  unpack_key<D>(skey[i], k, mask, c);
+  const float4 o = soff[i];
+  const float oo[3] = {o.x, o.y, o.z};
+  const double lo[3] = {lo0, lo1, lo2};
+  const uint32_t id = sid[i];
+  if (pos)
+    for (int a = 0; a < D; ++a) pos[(size_t)id * D + a] = (float)(lo[a] + ((double)c[a] + (double)oo[a]) * cs);
+  if (type) type[id] = (int32_t)(sct[i] & 3u);
+}
+
+// Scatter one per-particle quantity of the last step to load order, converted to domain units.
+template <int D>
+__global__ __launch_bounds__(kBlock) void dump_kernel(int n, int which, int k, uint32_t mask, double lo0, double lo1,
+                                                      double lo2, double cs, float tau, const uint32_t *__restrict__ wkey,
+                                                      const float4 *__restrict__ wpos, const uint32_t *__restrict__ wid,
+                                                      const float *__restrict__ rho, const float *__restrict__ nn,
+                                                      const float4 *__restrict__ vec, float *__restrict__ out) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t id = wid[i];
+  const float4 p = wpos[i];
+  const double csd = cs;
+  switch (which) {
+    case MPSPH_F_RHO:
+      out[id] = (float)((double)rho[i] / pow(csd, D));
+      break;
+    case MPSPH_F_RHO_T: {
+      double s = (double)p.w / tau * csd;
+      out[id] = (float)pow(s, -D);
+      break;
+    }
+    case MPSPH_F_H:
+      out[id] = (float)((double)p.w * csd);
+      break;
+    case MPSPH_F_NN:
+      out[id] = (float)((double)nn[i] * csd);
+      break;
+    case MPSPH_F_A_ABS:
+      out[id] = (float)((double)vec[i].w * csd);
+      break;
+    case MPSPH_F_X0: {
+      int c[3];
+      unpack_key<D>(wkey[i], k, mask, c);
+      const float oo[3] = {p.x, p.y, p.z};
+      const double lo[3] = {lo0, lo1, lo2};
+      for (int a = 0; a < D; ++a) out[(size_t)id * D + a] = (float)(lo[a] + ((double)c[a] + (double)oo[a]) * csd);
+      break;
+    }
+    default: {  // vector quantities in cell units per time: scale by cs
+      const float4 v = vec[i];
+      const float vv[3] = {v.x, v.y, v.z};
+      for (int a = 0; a < D; ++a) out[(size_t)id * D + a] = (float)((double)vv[a] * csd);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host side
+// ------------------------------------------------------------------------------------------
+
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  int dim = 0, k = 0;
+  int64_t n = 0;
+  uint32_t ncells = 0;
+  int nblocks = 0;
+  size_t bytes = 0;
+  // offsets
+  size_t s_key, s_off, s_ct, s_id, w_key, w_pos, w_jaux, w_id, k0, v0, k1, v1, hist, cstart, acc, rho, nn, vt, at, v,
+      dr, partials, metrics, dtcells, bad, rbf_c, rbf_o, rbf_k;
+};
+
+struct Derived {
+  int dim, k, gmax;
+  double L, cs, inv_cs, lo[3];
+  double smin, smax, lip;  // spacing bounds (domain units), Lipschitz constant of s
+  double search_fac;
+};
+
+const char *kErr[] = {"ok", "invalid argument", "out of memory", "device error", "bad context state",
+                      "non-finite values", "unsupported configuration"};
+
+bool valid_params(const mpsph_params *p) {
+  if (!p) return false;
+  if (p->dim != 2 && p->dim != 3) return false;
+  if (p->geometry < MPSPH_BOX || p->geometry > MPSPH_BALL) return false;
+  if (p->geometry == MPSPH_ANNULUS && p->dim != 2) return false;
+  for (int a = 0; a < p->dim; ++a)
+    if (!(p->hi[a] > p->lo[a]) || !std::isfinite(p->lo[a]) || !std::isfinite(p->hi[a])) return false;
+  if (p->field < MPSPH_UNIFORM || p->field > MPSPH_RBF_EXP) return false;
+  if (p->field == MPSPH_RBF_EXP && (p->n_rbf < 0 || p->n_rbf > 64 || (p->n_rbf > 0 && (!p->rbf_centre || !p->rbf_coeff)) ||
+                                    !(p->rbf_width > 0)))
+    return false;
+  if (!(p->tau > 0) || !(p->kappa > 0) || !(p->p0 > 0) || !(p->sigma0 >= 0)) return false;
+  if (!(p->nu_coeff >= 0) || !(p->c_acc > 0) || !(p->c_vel > 0) || !(p->c_visc > 0)) return false;
+  if (p->geometry != MPSPH_BOX && !(p->r_out > 0)) return false;
+  if (p->geometry == MPSPH_ANNULUS && !(p->r_in > 0 && p->r_in < p->r_out)) return false;
+  if (p->cell_log2 != -1 && (p->cell_log2 < 1 || p->cell_log2 > 12)) return false;
+  return true;
+}
+
+double box_dist_range(const mpsph_params *p, const double *c, double *dmax) {
+  double dmin2 = 0.0, dmax2 = 0.0;
+  for (int a = 0; a < p->dim; ++a) {
+    double lo = p->lo[a] - c[a], hi = p->hi[a] - c[a];
+    double near = (lo > 0) ? lo : (hi < 0 ? -hi : 0.0);
+    double far = std::max(std::fabs(lo), std::fabs(hi));
+    dmin2 += near * near;
+    dmax2 += far * far;
+  }
+  *dmax = std::sqrt(dmax2);
+  return std::sqrt(dmin2);
+}
+
+// Spacing of the field in domain units at a point (host, FP64), with scale s0.
+double host_spacing(const mpsph_params *p, double s0, const double *x) {
+  auto dist = [&](const double *c) {
+    double s = 0;
+    for (int a = 0; a < p->dim; ++a) s += (x[a] - c[a]) * (x[a] - c[a]);
+    return std::sqrt(s);
+  };
+  switch (p->field) {
+    case MPSPH_UNIFORM:
+      return s0;
+    case MPSPH_RADIAL_LINEAR:
+      return s0 * (1.0 + p->fa * (dist(p->fcentre) - p->fb));
+    case MPSPH_SPHERE_DISTANCE:
+      return s0 * (1.0 + p->fa * std::fabs(dist(p->fcentre) - p->fb));
+    default: {
+      double e = 0;
+      for (int k = 0; k < p->n_rbf; ++k) {
+        double r = dist(p->rbf_centre + k * p->dim);
+        e += p->rbf_coeff[k] * std::exp(-r * r / (2 * p->rbf_width * p->rbf_width));
+      }
+      return s0 * std::exp(e);
+    }
+  }
+}
+
+bool inside_region(const mpsph_params *p, const double *x) {
+  if (p->geometry == MPSPH_BOX) return true;
+  double r = 0;
+  for (int a = 0; a < p->dim; ++a) r += (x[a] - p->centre[a]) * (x[a] - p->centre[a]);
+  r = std::sqrt(r);
+  if (p->geometry == MPSPH_ANNULUS) return r >= p->r_in && r <= p->r_out;
+  return r <= p->r_out;
+}
+
+// Gauss-Legendre nodes on [0,1] (8 points).
+void gauss8(double *xg, double *wg) {
+  static const double t[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+  static const double w[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+  for (int i = 0; i < 4; ++i) {
+    xg[3 - i] = 0.5 * (1 - t[i]);
+    xg[4 + i] = 0.5 * (1 + t[i]);
+    wg[3 - i] = 0.5 * w[i];
+    wg[4 + i] = 0.5 * w[i];
+  }
+}
+
+// Integral of s^-d over the region for s0 = 1: composite 8-point Gauss-Legendre in Cartesian
+// panels (box) or polar / spherical coordinates (annulus, ball).
+double field_integral_unit(const mpsph_params *p) {
+  double xg[8], wg[8];
+  gauss8(xg, wg);
+  const int d = p->dim;
+  double total = 0.0;
+  if (p->geometry == MPSPH_BOX) {
+    const int M = d == 2 ? 256 : 48;
+    const int np = M * 8;
+    std::vector<double> node[3], wt[3];
+    for (int a = 0; a < d; ++a) {
+      double h = (p->hi[a] - p->lo[a]) / M;
+      for (int m = 0; m < M; ++m)
+        for (int q = 0; q < 8; ++q) {
+          node[a].push_back(p->lo[a] + (m + xg[q]) * h);
+          wt[a].push_back(wg[q] * h);
+        }
+    }
+    double x[3];
+    if (d == 2) {
+      for (int i = 0; i < np; ++i)
+        for (int j = 0; j < np; ++j) {
+          x[0] = node[0][i];
+          x[1] = node[1][j];
+          total += wt[0][i] * wt[1][j] * std::pow(host_spacing(p, 1.0, x), -d);
+        }
+    } else {
+      for (int i = 0; i < np; ++i) {
+        double acc = 0;
+        for (int j = 0; j < np; ++j)
+          for (int l = 0; l < np; ++l) {
+            x[0] = node[0][i];
+            x[1] = node[1][j];
+            x[2] = node[2][l];
+            double s = host_spacing(p, 1.0, x);
+            acc += wt[1][j] * wt[2][l] / (s * s * s);
+          }
+        total += wt[0][i] * acc;
+      }
+    }
+    return total;
+  }
+  const double r0 = p->geometry == MPSPH_ANNULUS ? p->r_in : 0.0, r1 = p->r_out;
+  const int MR = 128, MT = d == 2 ? 64 : 32, MP = 64;
+  const double pi = 3.14159265358979323846;
+  for (int mr = 0; mr < MR; ++mr)
+    for (int qr = 0; qr < 8; ++qr) {
+      double r = r0 + (mr + xg[qr]) * (r1 - r0) / MR, wr = wg[qr] * (r1 - r0) / MR;
+      for (int mt = 0; mt < MT; ++mt)
+        for (int qt = 0; qt < 8; ++qt) {
+          double th = (mt + xg[qt]) * (d == 2 ? 2 * pi : pi) / MT, wth = wg[qt] * (d == 2 ? 2 * pi : pi) / MT;
+          if (d == 2) {
+            double x[2] = {p->centre[0] + r * std::cos(th), p->centre[1] + r * std::sin(th)};
+            total += wr * wth * r * std::pow(host_spacing(p, 1.0, x), -2);
+          } else {
+            for (int mp = 0; mp < MP; ++mp)
+              for (int qp = 0; qp < 8; ++qp) {
+                double ph = (mp + xg[qp]) * 2 * pi / MP, wph = wg[qp] * 2 * pi / MP;
+                double x[3] = {p->centre[0] + r * std::sin(th) * std::cos(ph),
+                               p->centre[1] + r * std::sin(th) * std::sin(ph), p->centre[2] + r * std::cos(th)};
+                total += wr * wth * wph * r * r * std::sin(th) * std::pow(host_spacing(p, 1.0, x), -3);
+              }
+          }
+        }
+    }
+  return total;
+}
+
+// Bounds of s over the bounding box, and a Lipschitz constant of s (domain units).
+bool spacing_bounds(const mpsph_params *p, double s0, double *smin, double *smax, double *lip) {
+  switch (p->field) {
+    case MPSPH_UNIFORM:
+      *smin = *smax = s0;
+      *lip = 0;
+      break;
+    case MPSPH_RADIAL_LINEAR: {
+      double rmax, rmin = box_dist_range(p, p->fcentre, &rmax);
+      double a = s0 * (1 + p->fa * (rmin - p->fb)), b = s0 * (1 + p->fa * (rmax - p->fb));
+      *smin = std::min(a, b);
+      *smax = std::max(a, b);
+      *lip = s0 * std::fabs(p->fa);
+      break;
+    }
+    case MPSPH_SPHERE_DISTANCE: {
+      double rmax, rmin = box_dist_range(p, p->fcentre, &rmax);
+      double dlo = (p->fb >= rmin && p->fb <= rmax) ? 0.0 : std::min(std::fabs(rmin - p->fb), std::fabs(rmax - p->fb));
+      double dhi = std::max(std::fabs(rmin - p->fb), std::fabs(rmax - p->fb));
+      double a = s0 * (1 + p->fa * dlo), b = s0 * (1 + p->fa * dhi);
+      *smin = std::min(a, b);
+      *smax = std::max(a, b);
+      *lip = s0 * std::fabs(p->fa);
+      break;
+    }
+    default: {
+      double pos = 0, neg = 0, abs_sum = 0;
+      for (int k = 0; k < p->n_rbf; ++k) {
+        pos += std::max(p->rbf_coeff[k], 0.0);
+        neg += std::min(p->rbf_coeff[k], 0.0);
+        abs_sum += std::fabs(p->rbf_coeff[k]);
+      }
+      *smin = s0 * std::exp(neg);
+      *smax = s0 * std::exp(pos);
+      *lip = *smax * abs_sum / (p->rbf_width * std::exp(0.5));
+    }
+  }
+  return *smin > 0 && std::isfinite(*smax);
+}
+
+int derive(const mpsph_params *p, int64_t n, double s0, Derived *d) {
+  d->dim = p->dim;
+  double L = 0;
+  for (int a = 0; a < p->dim; ++a) L = std::max(L, p->hi[a] - p->lo[a]);
+  d->L = L;
+  for (int a = 0; a < 3; ++a) d->lo[a] = a < p->dim ? p->lo[a] : 0.0;
+  if (!spacing_bounds(p, s0, &d->smin, &d->smax, &d->lip)) return MPSPH_E_INVALID;
+  int k = p->cell_log2;
+  if (k < 0) {
+    // cells of about 0.75 of the smallest cut-off radius; at most 2^24 cells, and not many more
+    // cells than particles
+    double rc_min = p->kappa * p->tau * d->smin;
+    double target = L / (0.75 * rc_min) + 1.0;
+    k = (int)std::lround(std::log2(std::max(target, 2.0)));
+    int kmax = p->dim == 3 ? 8 : 12;
+    while (k > 1 && std::pow(2.0, p->dim * k) > 8.0 * std::max<int64_t>(n, 64)) --k;
+    k = std::min(std::max(k, 1), kmax);
+  }
+  if (p->dim * k > 24) return MPSPH_E_UNSUPPORTED;
+  d->k = k;
+  d->gmax = (1 << k) - 1;
+  d->cs = L / (double)d->gmax;
+  d->inv_cs = (double)d->gmax / L;
+  // neighbour search bound: j interacts only if r < kappa (h_i + h_j)/2 and h_j <= h_i + L_h r
+  // (L_h = tau * Lipschitz(s)), so r < kappa h_i / (1 - kappa L_h / 2).
+  double Lh = p->tau * d->lip;
+  double fac = 1e30;
+  if (p->kappa * Lh / 2 < 0.95) fac = p->kappa / (1.0 - p->kappa * Lh / 2);
+  d->search_fac = std::max(fac, p->kappa) * (1.0 + 1e-4);
+  return MPSPH_OK;
+}
+
+Layout make_layout(int dim, int k, int64_t n, int n_rbf) {
+  Layout L;
+  L.dim = dim;
+  L.k = k;
+  L.n = n;
+  L.ncells = (uint32_t)1u << (dim * k);
+  L.nblocks = (int)std::max<int64_t>(1, (n + kBlock - 1) / kBlock);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(std::max<size_t>(bytes, 4));
+    return at;
+  };
+  size_t nn = (size_t)std::max<int64_t>(n, 1);
+  L.s_key = take(nn * 4);
+  L.s_off = take(nn * 16);
+  L.s_ct = take(nn * 4);
+  L.s_id = take(nn * 4);
+  L.w_key = take(nn * 4);
+  L.w_pos = take(nn * 16);
+  L.w_jaux = take(nn * 4);
+  L.w_id = take(nn * 4);
+  L.k0 = take(nn * 4);
+  L.v0 = take(nn * 4);
+  L.k1 = take(nn * 4);
+  L.v1 = take(nn * 4);
+  L.hist = take(radix_hist_words((int)n) * 4);
+  L.cstart = take(((size_t)L.ncells + 1) * 4);
+  L.acc = take(nn * 16);
+  L.rho = take(nn * 4);
+  L.nn = take(nn * 4);
+  L.vt = take(nn * 16);
+  L.at = take(nn * 16);
+  L.v = take(nn * 16);
+  L.dr = take(nn * 16);
+  L.partials = take((size_t)L.nblocks * kNumPartials * 8);
+  L.metrics = take(32 * 8);
+  L.dtcells = take(2 * 4);
+  L.bad = take(4);
+  L.rbf_c = take((size_t)std::max(n_rbf, 1) * 3 * 4);
+  L.rbf_o = take((size_t)std::max(n_rbf, 1) * 3 * 4);
+  L.rbf_k = take((size_t)std::max(n_rbf, 1) * 4);
+  L.bytes = o;
+  return L;
+}
+
+struct EventHook : LaunchHook {
+  struct Rec {
+    const char *name;
+    hipEvent_t a, b;
+  };
+  hipStream_t stream = nullptr;
+  bool on = false;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::string> names;
+  std::vector<int64_t> launches;
+  std::vector<double> ms;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(const char *name) override {
+    if (!on) return;
+    Rec r{name, get(), get()};
+    (void)hipEventRecord(r.a, stream);
+    pending.push_back(r);
+  }
+  void end() override {
+    if (!on) return;
+    (void)hipEventRecord(pending.back().b, stream);
+  }
+  void collect() {
+    (void)hipStreamSynchronize(stream);
+    for (auto &r : pending) {
+      float t = 0;
+      (void)hipEventElapsedTime(&t, r.a, r.b);
+      size_t k = 0;
+      for (; k < names.size(); ++k)
+        if (names[k] == r.name) break;
+      if (k == names.size()) {
+        names.emplace_back(r.name);
+        launches.push_back(0);
+        ms.push_back(0);
+      }
+      launches[k] += 1;
+      ms[k] += t;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    names.clear();
+    launches.clear();
+    ms.clear();
+  }
+  ~EventHook() override {
+    for (auto &r : pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct mpsph_ctx {
+  mpsph_params p{};
+  std::vector<double> rbf_centre, rbf_coeff;
+  Derived d{};
+  Layout L;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  bool owns = false;
+  bool loaded = false;
+  bool poisoned = false;
+  int64_t steps_done = 0;
+  double s0 = 0;
+  GridDev g{};
+  FieldDev f{};
+  EventHook hook;
+  template <typename T>
+  T *at(size_t off) {
+    return reinterpret_cast<T *>(ws + off);
+  }
+};
+
+namespace {
+
+int fail(mpsph_ctx *c, int code) {
+  if (c && code == MPSPH_E_DEVICE) c->poisoned = true;
+  return code;
+}
+
+#define HIP_OK(expr)                                       \
+  do {                                                     \
+    if ((expr) != hipSuccess) return fail(ctx, MPSPH_E_DEVICE); \
+  } while (0)
+
+void split_cell(double X, int *c, float *o) {
+  double f = std::floor(X);
+  *c = (int)f;
+  *o = (float)(X - f);
+  if (*o >= 1.0f) {
+    *o = 0.0f;
+    *c += 1;
+  }
+}
+
+double sigma_at(const mpsph_params *p, int64_t step) {
+  if (p->t0 < 0) return p->sigma0;
+  double t = (double)step, t0 = (double)p->t0, t1 = (double)p->t1;
+  if (t <= t0) return p->sigma0;
+  if (t <= t1) return p->sigma0 * (1.0 - (t - t0) / (t1 - t0));
+  return 0.0;
+}
+
+template <int D>
+int run_steps(mpsph_ctx *ctx, int nsteps) {
+  const int n = (int)ctx->L.n;
+  const Layout &L = ctx->L;
+  hipStream_t st = ctx->stream;
+  const int nb = L.nblocks;
+  const double cs = ctx->d.cs;
+  StepDev sp;
+  sp.kappa = (float)ctx->p.kappa;
+  sp.tau = (float)ctx->p.tau;
+  sp.inv_tau = (float)(1.0 / ctx->p.tau);
+  sp.p0c = (float)(ctx->p.p0 * std::pow(cs, D - 2));
+  sp.nu_coeff = (float)ctx->p.nu_coeff;
+  sp.c_acc = (float)ctx->p.c_acc;
+  sp.c_vel = (float)ctx->p.c_vel;
+  sp.c_visc = (float)ctx->p.c_visc;
+  sp.search_fac = (float)ctx->d.search_fac;
+  sp.hmax = (float)(ctx->p.tau * ctx->d.smax / cs * (1.0 + 1e-5));
+  sp.alpha = (float)(D == 2 ? 7.0 / (4.0 * M_PI) : 21.0 / (16.0 * M_PI));
+  const bool dbg = ctx->p.debug != 0;
+  EventHook *hk = ctx->hook.on ? &ctx->hook : nullptr;
+  for (int s = 0; s < nsteps; ++s) {
+    sp.sigma = (float)sigma_at(&ctx->p, ctx->steps_done);
+    if (n > 0) {
+      const uint32_t *skeys = nullptr, *perm = nullptr;
+      if (radix_sort(ctx->at<uint32_t>(L.s_key), ctx->at<uint32_t>(L.k0), ctx->at<uint32_t>(L.v0),
+                     ctx->at<uint32_t>(L.k1), ctx->at<uint32_t>(L.v1), ctx->at<uint32_t>(L.hist), n, D * ctx->d.k, st,
+                     &skeys, &perm, hk) != hipSuccess)
+        return fail(ctx, MPSPH_E_DEVICE);
+      if (hk) hk->begin("reorder_field");
+      reorder_field<D><<<(n + 1 + kBlock - 1) / kBlock, kBlock, 0, st>>>(
+          n, L.ncells, ctx->g, ctx->f, (float)ctx->p.tau, skeys, perm, ctx->at<float4>(L.s_off),
+          ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
+          ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart),
+          ctx->at<uint32_t>(L.dtcells));
+      if (hk) hk->end();
+      if (hk) hk->begin("pass_density_force");
+      pass_density_force<D><<<nb, kBlock, 0, st>>>(
+          n, ctx->g, sp, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
+          ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc), ctx->at<float>(L.rho), dbg ? ctx->at<float>(L.nn) : nullptr,
+          ctx->at<uint32_t>(L.dtcells), ctx->at<double>(L.partials));
+      if (hk) hk->end();
+      if (hk) hk->begin("kick");
+      kick<D><<<nb, kBlock, 0, st>>>(n, sp, ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
+                                     ctx->at<float4>(L.acc), ctx->at<float4>(L.vt), ctx->at<uint32_t>(L.dtcells));
+      if (hk) hk->end();
+      if (hk) hk->begin("pass_viscous_integrate");
+      pass_viscous_integrate<D><<<nb, kBlock, 0, st>>>(
+          n, ctx->g, sp, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
+          ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.vt), ctx->at<uint32_t>(L.dtcells),
+          ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id),
+          dbg ? ctx->at<float4>(L.at) : nullptr, dbg ? ctx->at<float4>(L.v) : nullptr, dbg ? ctx->at<float4>(L.dr) : nullptr,
+          ctx->at<double>(L.partials));
+      if (hk) hk->end();
+    }
+    if (hk) hk->begin("finalize");
+    finalize<<<1, 256, 0, st>>>(n > 0 ? nb : 0, ctx->at<double>(L.partials), ctx->at<uint32_t>(L.dtcells),
+                                ctx->at<double>(L.metrics));
+    if (hk) hk->end();
+    if (hipGetLastError() != hipSuccess) return fail(ctx, MPSPH_E_DEVICE);
+    ctx->steps_done += 1;
+  }
+  return MPSPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mpsph_strerror(int status) {
+  if (status < 0 || status > MPSPH_E_UNSUPPORTED) return "unknown status";
+  return kErr[status];
+}
+
+int mpsph_field_scale(const mpsph_params *params, int64_t n, double *s0_out) {
+  if (!valid_params(params) || n <= 0 || !s0_out) return MPSPH_E_INVALID;
+  double I = field_integral_unit(params);
+  if (!(I > 0) || !std::isfinite(I)) return MPSPH_E_INVALID;
+  *s0_out = std::pow(I / (double)n, 1.0 / params->dim);
+  return MPSPH_OK;
+}
+
+size_t mpsph_workspace_bytes(const mpsph_params *params, int64_t n) {
+  if (!valid_params(params) || n < 0 || n > (int64_t)1 << 30) return 0;
+  double s0 = params->s0;
+  if (!(s0 > 0) && mpsph_field_scale(params, std::max<int64_t>(n, 1), &s0) != MPSPH_OK) return 0;
+  Derived d;
+  if (derive(params, n, s0, &d) != MPSPH_OK) return 0;
+  return make_layout(params->dim, d.k, n, params->n_rbf).bytes;
+}
+
+int mpsph_create(const mpsph_params *params, int64_t n, void *d_workspace, size_t workspace_bytes, void *hip_stream,
+                 mpsph_ctx **out) {
+  if (!out) return MPSPH_E_INVALID;
+  *out = nullptr;
+  if (!valid_params(params) || n < 0 || n > (int64_t)1 << 30) return MPSPH_E_INVALID;
+  mpsph_ctx *ctx = new (std::nothrow) mpsph_ctx();
+  if (!ctx) return MPSPH_E_NOMEM;
+  ctx->p = *params;
+  if (params->field == MPSPH_RBF_EXP && params->n_rbf > 0) {
+    ctx->rbf_centre.assign(params->rbf_centre, params->rbf_centre + params->n_rbf * params->dim);
+    ctx->rbf_coeff.assign(params->rbf_coeff, params->rbf_coeff + params->n_rbf);
+    ctx->p.rbf_centre = ctx->rbf_centre.data();
+    ctx->p.rbf_coeff = ctx->rbf_coeff.data();
+  } else {
+    ctx->p.n_rbf = params->field == MPSPH_RBF_EXP ? 0 : params->n_rbf;
+    ctx->p.rbf_centre = nullptr;
+    ctx->p.rbf_coeff = nullptr;
+    if (params->field != MPSPH_RBF_EXP) ctx->p.n_rbf = 0;
+  }
+  double s0 = params->s0;
+  if (!(s0 > 0)) {
+    int rc = mpsph_field_scale(&ctx->p, std::max<int64_t>(n, 1), &s0);
+    if (rc) {
+      delete ctx;
+      return rc;
+    }
+  }
+  ctx->s0 = s0;
+  int rc = derive(&ctx->p, n, s0, &ctx->d);
+  if (rc) {
+    delete ctx;
+    return rc;
+  }
+  ctx->L = make_layout(params->dim, ctx->d.k, n, ctx->p.n_rbf);
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->hook.stream = ctx->stream;
+  if (d_workspace) {
+    if (workspace_bytes < ctx->L.bytes || ((uintptr_t)d_workspace & 255)) {
+      delete ctx;
+      return MPSPH_E_NOMEM;
+    }
+    ctx->ws = (char *)d_workspace;
+  } else {
+    if (hipMalloc((void **)&ctx->ws, ctx->L.bytes) != hipSuccess) {
+      delete ctx;
+      return MPSPH_E_NOMEM;
+    }
+    ctx->owns = true;
+  }
+  // a zeroed workspace keeps every table entry a valid index before its first write
+  if (hipMemset(ctx->ws, 0, ctx->L.bytes) != hipSuccess) {
+    mpsph_destroy(ctx);
+    return MPSPH_E_DEVICE;
+  }
+  // grid and region in cell units
+  const double cs = ctx->d.cs, ics = ctx->d.inv_cs;
+  GridDev &g = ctx->g;
+  g.k = ctx->d.k;
+  g.n = (int)n;
+  g.gmax = ctx->d.gmax;
+  g.xmask = (uint32_t)ctx->d.gmax;
+  g.geometry = params->geometry;
+  for (int a = 0; a < 3; ++a) {
+    double Xhi = a < params->dim ? (params->hi[a] - params->lo[a]) * ics : 0.0;
+    split_cell(Xhi, &g.whi_c[a], &g.whi_o[a]);
+    if (g.whi_c[a] > g.gmax) {
+      g.whi_c[a] = g.gmax;
+      g.whi_o[a] = 0.f;
+    }
+    double Xc = a < params->dim ? (params->centre[a] - params->lo[a]) * ics : 0.0;
+    split_cell(Xc, &g.gc_c[a], &g.gc_o[a]);
+  }
+  g.r_in = (float)(params->r_in * ics);
+  g.r_out = (float)(params->r_out * ics);
+  FieldDev &f = ctx->f;
+  f.kind = params->field;
+  f.s0 = (float)(s0 * ics);
+  f.g = (float)(params->fa * cs);
+  f.b = (float)(params->fb * ics);
+  for (int a = 0; a < 3; ++a) {
+    double Xc = a < params->dim ? (params->fcentre[a] - params->lo[a]) * ics : 0.0;
+    split_cell(Xc, &f.fc_c[a], &f.fc_o[a]);
+  }
+  f.n_rbf = ctx->p.n_rbf;
+  f.e2 = (float)(cs * cs / (2.0 * params->rbf_width * params->rbf_width));
+  f.rbf_c = ctx->at<int>(ctx->L.rbf_c);
+  f.rbf_o = ctx->at<float>(ctx->L.rbf_o);
+  f.rbf_k = ctx->at<float>(ctx->L.rbf_k);
+  if (f.n_rbf > 0) {
+    std::vector<int> rc3(3 * f.n_rbf, 0);
+    std::vector<float> ro3(3 * f.n_rbf, 0.f), rk(f.n_rbf);
+    for (int k2 = 0; k2 < f.n_rbf; ++k2) {
+      for (int a = 0; a < params->dim; ++a)
+        split_cell((ctx->p.rbf_centre[k2 * params->dim + a] - params->lo[a]) * ics, &rc3[k2 * 3 + a], &ro3[k2 * 3 + a]);
+      rk[k2] = (float)ctx->p.rbf_coeff[k2];
+    }
+    if (hipMemcpy(ctx->at<int>(ctx->L.rbf_c), rc3.data(), rc3.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->at<float>(ctx->L.rbf_o), ro3.data(), ro3.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->at<float>(ctx->L.rbf_k), rk.data(), rk.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      mpsph_destroy(ctx);
+      return MPSPH_E_DEVICE;
+    }
+  }
+  *out = ctx;
+  return MPSPH_OK;
+}
+
+int mpsph_load(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type) {
+  if (!ctx) return MPSPH_E_INVALID;
+  if (ctx->poisoned) return MPSPH_E_STATE;
+  const int n = (int)ctx->L.n;
+  if (n > 0 && (!d_pos || !d_colour)) return MPSPH_E_INVALID;
+  const Layout &L = ctx->L;
+  HIP_OK(hipMemsetAsync(ctx->at<int>(L.bad), 0, 4, ctx->stream));
+  HIP_OK(hipMemsetAsync(ctx->at<double>(L.metrics), 0, 32 * 8, ctx->stream));
+  if (n > 0) {
+    auto kern = ctx->p.dim == 2 ? load_kernel<2> : load_kernel<3>;
+    kern<<<(n + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
+        d_pos, d_colour, d_type, n, ctx->d.lo[0], ctx->d.lo[1], ctx->d.lo[2], ctx->d.inv_cs, ctx->d.k, ctx->d.gmax,
+        ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id),
+        ctx->at<int>(L.bad));
+    HIP_OK(hipGetLastError());
+  }
+  int bad = 0;
+  HIP_OK(hipMemcpyAsync(&bad, ctx->at<int>(L.bad), 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  if (bad) {
+    ctx->loaded = false;
+    return MPSPH_E_INVALID;
+  }
+  ctx->loaded = true;
+  ctx->steps_done = 0;
+  return MPSPH_OK;
+}
+
+int mpsph_step(mpsph_ctx *ctx, int32_t nsteps) {
+  if (!ctx || nsteps < 0) return MPSPH_E_INVALID;
+  if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
+  return ctx->p.dim == 2 ? run_steps<2>(ctx, nsteps) : run_steps<3>(ctx, nsteps);
+}
+
+int mpsph_metrics(mpsph_ctx *ctx, mpsph_metrics_t *out) {
+  if (!ctx || !out) return MPSPH_E_INVALID;
+  if (ctx->poisoned) return MPSPH_E_STATE;
+  double m[32];
+  HIP_OK(hipMemcpyAsync(m, ctx->at<double>(ctx->L.metrics), sizeof(m), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  const double cs = ctx->d.cs;
+  std::memset(out, 0, sizeof(*out));
+  out->step = ctx->steps_done - 1;
+  out->pairs = (int64_t)m[P_PAIRS];
+  out->interface_pairs = (int64_t)m[P_IFC] / 2;
+  out->candidates = (int64_t)m[P_CAND];
+  out->n_normal = (int64_t)m[P_NNORM];
+  out->n_elr = (int64_t)m[P_NELR];
+  out->nonfinite = (int64_t)(m[P_NONFIN1] + m[P_NONFIN2]);
+  out->n_feature = (int64_t)m[P_NFEAT];
+  out->residual_l2 = m[P_NNORM] > 0 ? std::sqrt(m[P_E2] / m[P_NNORM]) : 0.0;
+  out->residual_linf = m[P_EMAX];
+  out->kinetic = m[P_KE] * cs * cs;
+  out->dt1 = m[16];
+  out->dt2 = m[17];
+  out->sigma = ctx->steps_done > 0 ? sigma_at(&ctx->p, ctx->steps_done - 1) : sigma_at(&ctx->p, 0);
+  if (m[P_NELR] > 0) {
+    double mean = m[P_ELR] / m[P_NELR];
+    out->elr_mean = mean;
+    out->elr_std = std::sqrt(std::max(0.0, m[P_ELR2] / m[P_NELR] - mean * mean));
+    out->elr_min = m[P_ELRMIN];
+    out->elr_max = m[P_ELRMAX];
+  }
+  return out->nonfinite ? MPSPH_E_NONFINITE : MPSPH_OK;
+}
+
+int mpsph_store(mpsph_ctx *ctx, float *d_pos, int32_t *d_type) {
+  if (!ctx) return MPSPH_E_INVALID;
+  if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
+  const int n = (int)ctx->L.n;
+  const Layout &L = ctx->L;
+  if (n > 0) {
+    auto kern = ctx->p.dim == 2 ? store_kernel<2> : store_kernel<3>;
+    kern<<<(n + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
+        n, ctx->d.k, (uint32_t)ctx->d.gmax, ctx->d.lo[0], ctx->d.lo[1], ctx->d.lo[2], ctx->d.cs,
+        ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id),
+        d_pos, d_type);
+    HIP_OK(hipGetLastError());
+  }
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  return MPSPH_OK;
+}
+
+int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out) {
+  if (!ctx || !d_out || which < 0 || which > MPSPH_F_X0) return MPSPH_E_INVALID;
+  if (ctx->poisoned || !ctx->loaded || ctx->steps_done == 0) return MPSPH_E_STATE;
+  if ((which == MPSPH_F_V || which == MPSPH_F_DR || which == MPSPH_F_AT || which == MPSPH_F_NN) && !ctx->p.debug)
+    return MPSPH_E_STATE;
+  const int n = (int)ctx->L.n;
+  const Layout &L = ctx->L;
+  const float4 *vec = ctx->at<float4>(L.acc);
+  if (which == MPSPH_F_VT) vec = ctx->at<float4>(L.vt);
+  if (which == MPSPH_F_AT) vec = ctx->at<float4>(L.at);
+  if (which == MPSPH_F_V) vec = ctx->at<float4>(L.v);
+  if (which == MPSPH_F_DR) vec = ctx->at<float4>(L.dr);
+  if (n > 0) {
+    auto kern = ctx->p.dim == 2 ? dump_kernel<2> : dump_kernel<3>;
+    kern<<<(n + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
+        n, which, ctx->d.k, (uint32_t)ctx->d.gmax, ctx->d.lo[0], ctx->d.lo[1], ctx->d.lo[2], ctx->d.cs,
+        (float)ctx->p.tau, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_id),
+        ctx->at<float>(L.rho), ctx->at<float>(L.nn), vec, d_out);
+    HIP_OK(hipGetLastError());
+  }
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  return MPSPH_OK;
+}
+
+int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cell_start, int64_t *ncells, int32_t *cell_log2) {
+  if (!ctx) return MPSPH_E_INVALID;
+  if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
+  if (ncells) *ncells = ctx->L.ncells;
+  if (cell_log2) *cell_log2 = ctx->d.k;
+  if ((d_key || d_cell_start) && ctx->steps_done == 0) return MPSPH_E_STATE;
+  const Layout &L = ctx->L;
+  const int n = (int)L.n;
+  if (d_key && n > 0) {
+    // keys of the last step's start in load order: scatter w_key by w_id
+    std::vector<uint32_t> k(n), id(n), outk(n);
+    HIP_OK(hipMemcpyAsync(k.data(), ctx->at<uint32_t>(L.w_key), 4 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipMemcpyAsync(id.data(), ctx->at<uint32_t>(L.w_id), 4 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < n; ++i) outk[id[i]] = k[i];
+    HIP_OK(hipMemcpyAsync(d_key, outk.data(), 4 * (size_t)n, hipMemcpyHostToDevice, ctx->stream));
+  }
+  if (d_cell_start)
+    HIP_OK(hipMemcpyAsync(d_cell_start, ctx->at<uint32_t>(L.cstart), 4 * ((size_t)L.ncells + 1),
+                          hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  return MPSPH_OK;
+}
+
+int mpsph_profile(mpsph_ctx *ctx, int32_t enable) {
+  if (!ctx) return MPSPH_E_INVALID;
+  if (ctx->poisoned) return MPSPH_E_STATE;
+  if (enable) {
+    ctx->hook.collect();
+    ctx->hook.reset();
+    ctx->hook.on = true;
+  } else {
+    ctx->hook.collect();
+    ctx->hook.on = false;
+  }
+  return MPSPH_OK;
+}
+
+int mpsph_profile_read(mpsph_ctx *ctx, int32_t cap, const char **names, int64_t *launches, double *ms, int32_t *count) {
+  if (!ctx || cap < 0 || !count) return MPSPH_E_INVALID;
+  if (ctx->poisoned) return MPSPH_E_STATE;
+  ctx->hook.collect();
+  int m = (int)ctx->hook.names.size();
+  *count = m;
+  for (int i = 0; i < m && i < cap; ++i) {
+    if (names) names[i] = ctx->hook.names[i].c_str();
+    if (launches) launches[i] = ctx->hook.launches[i];
+    if (ms) ms[i] = ctx->hook.ms[i];
+  }
+  return MPSPH_OK;
+}
+
+void mpsph_destroy(mpsph_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->owns && ctx->ws) (void)hipFree(ctx->ws);
+  delete ctx;
+}
+
+}  // extern "C"

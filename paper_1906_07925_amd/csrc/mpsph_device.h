@@ -1,0 +1,202 @@
+// Device-side building blocks shared by the relaxation-step kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpsph {
+
+constexpr int kBlock = 256;       // threads per block of the particle kernels (4 waves)
+constexpr int kWave = 64;
+constexpr int kNumPartials = 16;  // FP64 partial slots per block
+constexpr uint32_t kInfBits = 0x7f800000u;
+
+// Slots of the per-block FP64 partials.
+enum : int {
+  P_E2 = 0,      // sum over normal particles of (rho/rho_t - 1)^2
+  P_EMAX = 1,    // max |rho/rho_t - 1|
+  P_NNORM = 2,   // number of normal particles
+  P_ELR = 3,     // sum of nearest distance / s
+  P_ELR2 = 4,    // sum of its square
+  P_ELRMIN = 5,
+  P_ELRMAX = 6,
+  P_NELR = 7,
+  P_PAIRS = 8,   // ordered interacting pairs passing the type mask
+  P_IFC = 9,     // ordered pairs with different colours (geometric)
+  P_CAND = 10,   // candidates tested
+  P_NONFIN1 = 11,
+  P_KE = 12,     // sum 1/2 |v|^2 (cell units)
+  P_NONFIN2 = 13,
+  P_NFEAT = 14,  // particles of type >= 1 after the step
+  P_SPARE = 15
+};
+
+// Geometry of the cell grid and of the meshing region, in cell units.  Positions are held as
+// an integer cell coordinate per axis plus a float offset in [0, 1).
+struct GridDev {
+  int k;             // cells per axis = 2^k
+  int n;             // particles
+  int gmax;          // 2^k - 1
+  uint32_t xmask;    // 2^k - 1
+  int geometry;      // MPSPH_BOX | MPSPH_ANNULUS | MPSPH_BALL
+  int whi_c[3];      // upper box wall: cell + offset (lower wall is cell 0, offset 0)
+  float whi_o[3];
+  int gc_c[3];       // annulus / ball centre: cell + offset
+  float gc_o[3];
+  float r_in, r_out; // radii in cell units
+};
+
+// Target size field in cell units: s_cell(x) = s(x) / cs.
+struct FieldDev {
+  int kind;
+  float s0;          // s0 / cs
+  float g;           // fa * cs: slope per cell unit of radius
+  float b;           // fb / cs
+  int fc_c[3];
+  float fc_o[3];
+  int n_rbf;
+  float e2;          // cs^2 / (2 w^2)
+  const int *rbf_c;  // n_rbf x 3 cell coordinates of the centres
+  const float *rbf_o;// n_rbf x 3 offsets
+  const float *rbf_k;// n_rbf coefficients
+};
+
+// Constants of one step (cell units; time in the caller's units).
+struct StepDev {
+  float kappa, tau, inv_tau;
+  float p0c;         // p0 cs^(d-2): keeps accelerations in cell units = domain units / cs
+  float sigma;
+  float nu_coeff, c_acc, c_vel, c_visc;
+  float search_fac;  // neighbour search radius bound: search_fac * h_i
+  float hmax;        // upper bound of h over the region (cell units)
+  float alpha;       // kernel normalisation alpha_d
+};
+
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of
+  // logical blocks so that neighbouring particles share that XCD's L2.
+  int q = nb >> 3, r = nb & 7, x = b & 7;
+  int start = x * q + (x < r ? x : r);
+  return start + (b >> 3);
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+template <int D>
+__device__ __forceinline__ float powd(float s) {  // s^D
+  if constexpr (D == 2) return s * s;
+  else return s * s * s;
+}
+
+// Spacing of the size field at a position given as cell + offset (cell units).
+template <int D>
+__device__ __forceinline__ float field_spacing(const FieldDev &f, const int *c, const float *o) {
+  if (f.kind == 0) return f.s0;
+  if (f.kind == 1 || f.kind == 2) {
+    float r2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float d = (float)(c[a] - f.fc_c[a]) + (o[a] - f.fc_o[a]);
+      r2 += d * d;
+    }
+    float t = sqrtf(r2) - f.b;
+    if (f.kind == 2) t = fabsf(t);
+    return f.s0 * (1.f + f.g * t);
+  }
+  float e = 0.f;
+  for (int k2 = 0; k2 < f.n_rbf; ++k2) {
+    float r2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      float d = (float)(c[a] - f.rbf_c[k2 * 3 + a]) + (o[a] - f.rbf_o[k2 * 3 + a]);
+      r2 += d * d;
+    }
+    e += f.rbf_k[k2] * __expf(-r2 * f.e2);
+  }
+  return f.s0 * __expf(e);
+}
+
+template <int D>
+__device__ __forceinline__ void unpack_key(uint32_t key, int k, uint32_t mask, int *c) {
+  c[0] = (int)(key & mask);
+  c[1] = (int)((key >> k) & mask);
+  if constexpr (D == 3) c[2] = (int)(key >> (2 * k));
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t pack_key(const int *c, int k) {
+  uint32_t key = (uint32_t)c[0] | ((uint32_t)c[1] << k);
+  if constexpr (D == 3) key |= (uint32_t)c[2] << (2 * k);
+  return key;
+}
+
+// Remove the components of v along the active constraint normals of a feature particle
+// (force mapping of Eq. 30-31).  Box: faces the particle lies on; annulus / ball: radial.
+template <int D>
+__device__ __forceinline__ void project_feature(const GridDev &g, int type, const int *c,
+                                                const float *o, float *v) {
+  if (type == 0) return;
+  if (type == 3) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = 0.f;
+    return;
+  }
+  if (g.geometry == 1) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      bool lo = c[a] == 0 && o[a] == 0.f;
+      bool hi = c[a] == g.whi_c[a] && o[a] == g.whi_o[a];
+      if (lo || hi) v[a] = 0.f;
+    }
+  } else {
+    float n[3], r2 = 0.f, dot = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      n[a] = (float)(c[a] - g.gc_c[a]) + (o[a] - g.gc_o[a]);
+      r2 += n[a] * n[a];
+    }
+    float inv = fast_rsq(r2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      n[a] *= inv;
+      dot += n[a] * v[a];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] -= dot * n[a];
+  }
+}
+
+// Deterministic block reduction of NP doubles (sum / min / max chosen per slot by op[]).
+// op: 0 sum, 1 min, 2 max.  Writes the block result to out[0..NP).
+template <int NP>
+__device__ __forceinline__ void block_reduce_write(double (&v)[NP], const int (&op)[NP], double *out) {
+  __shared__ double red[kBlock / kWave][NP];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int s = 0; s < NP; ++s) {
+    double x = v[s];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      double y = __shfl_xor(x, off, kWave);
+      x = op[s] == 0 ? x + y : (op[s] == 1 ? fmin(x, y) : fmax(x, y));
+    }
+    if (lane == 0) red[w][s] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NP) {
+    int s = threadIdx.x;
+    double x = red[0][s];
+    for (int ww = 1; ww < kBlock / kWave; ++ww) {
+      double y = red[ww][s];
+      x = op[s] == 0 ? x + y : (op[s] == 1 ? fmin(x, y) : fmax(x, y));
+    }
+    out[s] = x;
+  }
+}
+
+__device__ __forceinline__ void atomic_min_pos(uint32_t *cell, float v) {
+  // order-free minimum of non-negative floats through their bit patterns
+  atomicMin(cell, __float_as_uint(v));
+}
+
+}  // namespace mpsph

@@ -1,0 +1,253 @@
+"""Python binding of the C ABI in ``include/mpsph.h`` (argument marshalling only).
+
+Every step of the relaxation runs in the HIP kernels of ``libmpsph.so``.  PyTorch is used
+for device memory and for the current HIP stream.  There is no CPU path: if the library is
+missing, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpsph.so")
+
+GEOMETRY = {"box": 1, "annulus": 2, "ball": 3}
+FIELD = {"uniform": 0, "radial_linear": 1, "sphere_distance": 2, "rbf_exp": 3}
+FIELDS = {"rho": 0, "rho_t": 1, "h": 2, "a": 3, "a_abs": 4, "vt": 5, "at": 6, "v": 7, "dr": 8, "nn": 9,
+          "x0": 10}
+VECTOR_FIELDS = {"a", "vt", "at", "v", "dr", "x0"}
+ERRORS = {1: "invalid argument", 2: "out of memory", 3: "device error", 4: "bad context state",
+          5: "non-finite values", 6: "unsupported configuration"}
+
+
+class MpsphError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {ERRORS.get(code, 'unknown')} (status {code})")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("geometry", C.c_int32),
+        ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("centre", C.c_double * 3),
+        ("r_in", C.c_double), ("r_out", C.c_double),
+        ("field", C.c_int32), ("s0", C.c_double), ("fcentre", C.c_double * 3),
+        ("fa", C.c_double), ("fb", C.c_double),
+        ("n_rbf", C.c_int32), ("rbf_centre", C.POINTER(C.c_double)),
+        ("rbf_coeff", C.POINTER(C.c_double)), ("rbf_width", C.c_double),
+        ("tau", C.c_double), ("kappa", C.c_double), ("p0", C.c_double), ("sigma0", C.c_double),
+        ("t0", C.c_int64), ("t1", C.c_int64), ("nu_coeff", C.c_double),
+        ("c_acc", C.c_double), ("c_vel", C.c_double), ("c_visc", C.c_double),
+        ("cell_log2", C.c_int32), ("debug", C.c_int32),
+    ]
+
+
+class Metrics(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("step", "pairs", "interface_pairs", "candidates", "n_normal",
+                                         "n_elr", "nonfinite", "n_feature")] + \
+               [(k, C.c_double) for k in ("residual_l2", "residual_linf", "kinetic", "dt1", "dt2", "sigma",
+                                          "elr_mean", "elr_std", "elr_min", "elr_max")]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libmpsph.so``; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1906_07925_amd/build.py "
+                               "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        P, V, I32, I64 = C.POINTER(Params), C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "mpsph_field_scale": (C.c_int, [P, I64, C.POINTER(C.c_double)]),
+            "mpsph_workspace_bytes": (C.c_size_t, [P, I64]),
+            "mpsph_create": (C.c_int, [P, I64, V, C.c_size_t, V, C.POINTER(V)]),
+            "mpsph_load": (C.c_int, [V, V, V, V]),
+            "mpsph_step": (C.c_int, [V, I32]),
+            "mpsph_metrics": (C.c_int, [V, C.POINTER(Metrics)]),
+            "mpsph_store": (C.c_int, [V, V, V]),
+            "mpsph_debug_fields": (C.c_int, [V, I32, V]),
+            "mpsph_debug_cells": (C.c_int, [V, V, V, C.POINTER(I64), C.POINTER(I32)]),
+            "mpsph_profile": (C.c_int, [V, I32]),
+            "mpsph_profile_read": (C.c_int, [V, I32, C.POINTER(C.c_char_p), C.POINTER(I64),
+                                             C.POINTER(C.c_double), C.POINTER(I32)]),
+            "mpsph_destroy": (None, [V]),
+            "mpsph_strerror": (C.c_char_p, [C.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise MpsphError(rc, what)
+
+
+def make_params(spec: dict, s0: float | None = None, cell_log2: int = -1, debug: bool = False):
+    """Build the parameter block from a workload spec.  Returns (Params, keep-alive arrays)."""
+    p = Params()
+    d = int(spec["dim"])
+    p.dim = d
+    geom = spec["geometry"]
+    if geom not in GEOMETRY:
+        raise ValueError(f"geometry {geom!r} is not supported by the GPU library")
+    p.geometry = GEOMETRY[geom]
+    for a in range(3):
+        p.lo[a] = spec["lo"][a] if a < d else 0.0
+        p.hi[a] = spec["hi"][a] if a < d else 0.0
+        p.centre[a] = spec.get("centre", (0.0,) * 3)[a] if a < d else 0.0
+        p.fcentre[a] = spec.get("fcentre", (0.0,) * 3)[a] if a < d else 0.0
+    p.r_in = spec.get("r_in", 0.0)
+    p.r_out = spec.get("r_out", 0.0)
+    p.field = FIELD[spec["field"]]
+    p.fa = spec.get("fa", 0.0)
+    p.fb = spec.get("fb", 0.0)
+    keep = []
+    n_rbf = int(spec.get("n_rbf", 0))
+    p.n_rbf = n_rbf
+    if n_rbf:
+        cen = np.ascontiguousarray(spec["rbf_centre"], dtype=np.float64)
+        coe = np.ascontiguousarray(spec["rbf_coeff"], dtype=np.float64)
+        keep += [cen, coe]
+        p.rbf_centre = cen.ctypes.data_as(C.POINTER(C.c_double))
+        p.rbf_coeff = coe.ctypes.data_as(C.POINTER(C.c_double))
+    p.rbf_width = spec.get("rbf_width", 0.15)
+    p.tau = spec.get("tau", 1.3)
+    p.kappa = spec.get("kappa", 2.0)
+    p.p0 = spec.get("p0", 1.0)
+    p.sigma0 = spec.get("sigma0", 3.0)
+    p.t0 = int(spec.get("t0", -1))
+    p.t1 = int(spec.get("t1", -1))
+    p.nu_coeff = spec.get("nu_coeff", 0.1)
+    p.c_acc = spec.get("c_acc", 0.25)
+    p.c_vel = spec.get("c_vel", 1.0 / 40.0)
+    p.c_visc = spec.get("c_visc", 0.125)
+    if s0 is None:
+        s0 = spec.get("s0")
+    p.s0 = float(s0) if s0 is not None else 0.0
+    p.cell_log2 = int(cell_log2)
+    p.debug = 1 if debug else 0
+    return p, keep
+
+
+def field_scale(spec: dict, n: int) -> float:
+    p, keep = make_params(spec)
+    out = C.c_double(0.0)
+    _check(lib().mpsph_field_scale(C.byref(p), int(n), C.byref(out)), "mpsph_field_scale")
+    return out.value
+
+
+class Relaxer:
+    """One relaxation context on the current CUDA/HIP device and stream."""
+
+    def __init__(self, spec: dict, n: int | None = None, s0: float | None = None, cell_log2: int = -1,
+                 debug: bool = False, stream=None):
+        import torch
+        self._torch = torch
+        self.dim = int(spec["dim"])
+        self.n = int(spec["n"] if n is None else n)
+        self.params, self._keep = make_params(spec, s0=s0, cell_log2=cell_log2, debug=debug)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._ctx = C.c_void_p()
+        _check(lib().mpsph_create(C.byref(self.params), self.n, None, 0, C.c_void_p(stream.cuda_stream),
+                                  C.byref(self._ctx)), "mpsph_create")
+
+    # -- lifecycle
+    def close(self):
+        if self._ctx:
+            lib().mpsph_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, t, dtype):
+        torch = self._torch
+        t = torch.as_tensor(t)
+        if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous():
+            t = t.to(device="cuda", dtype=dtype).contiguous()
+        return t
+
+    def load(self, x, colour, ptype=None):
+        torch = self._torch
+        x = self._dev(x, torch.float32)
+        c = self._dev(colour, torch.int32)
+        assert x.shape == (self.n, self.dim) and c.shape == (self.n,)
+        t = None if ptype is None else self._dev(ptype, torch.int32)
+        self._hold = (x, c, t)
+        _check(lib().mpsph_load(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(c.data_ptr()),
+                                C.c_void_p(t.data_ptr()) if t is not None else None), "mpsph_load")
+
+    def step(self, nsteps: int = 1):
+        _check(lib().mpsph_step(self._ctx, int(nsteps)), "mpsph_step")
+
+    def metrics(self, allow_nonfinite: bool = False) -> dict:
+        m = Metrics()
+        rc = lib().mpsph_metrics(self._ctx, C.byref(m))
+        if rc != 0 and not (allow_nonfinite and rc == 5):
+            raise MpsphError(rc, "mpsph_metrics")
+        return {k: getattr(m, k) for k, _ in Metrics._fields_}
+
+    def store(self):
+        torch = self._torch
+        x = torch.empty((self.n, self.dim), dtype=torch.float32, device="cuda")
+        t = torch.empty((self.n,), dtype=torch.int32, device="cuda")
+        _check(lib().mpsph_store(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr())), "mpsph_store")
+        return x, t
+
+    def field(self, name: str):
+        torch = self._torch
+        shape = (self.n, self.dim) if name in VECTOR_FIELDS else (self.n,)
+        out = torch.empty(shape, dtype=torch.float32, device="cuda")
+        _check(lib().mpsph_debug_fields(self._ctx, FIELDS[name], C.c_void_p(out.data_ptr())),
+               f"mpsph_debug_fields({name})")
+        return out
+
+    def cells(self):
+        torch = self._torch
+        nc = C.c_int64(0)
+        k = C.c_int32(0)
+        _check(lib().mpsph_debug_cells(self._ctx, None, None, C.byref(nc), C.byref(k)), "mpsph_debug_cells")
+        keys = torch.empty((self.n,), dtype=torch.int32, device="cuda")
+        cstart = torch.empty((nc.value + 1,), dtype=torch.int32, device="cuda")
+        _check(lib().mpsph_debug_cells(self._ctx, C.c_void_p(keys.data_ptr()), C.c_void_p(cstart.data_ptr()),
+                                       C.byref(nc), C.byref(k)), "mpsph_debug_cells")
+        return keys, cstart, k.value
+
+    def cell_log2(self) -> int:
+        nc = C.c_int64(0)
+        k = C.c_int32(0)
+        _check(lib().mpsph_debug_cells(self._ctx, None, None, C.byref(nc), C.byref(k)), "mpsph_debug_cells")
+        return k.value
+
+    def profile(self, on: bool):
+        _check(lib().mpsph_profile(self._ctx, 1 if on else 0), "mpsph_profile")
+
+    def profile_read(self) -> dict:
+        cap = 64
+        names = (C.c_char_p * cap)()
+        launches = (C.c_int64 * cap)()
+        ms = (C.c_double * cap)()
+        cnt = C.c_int32(0)
+        _check(lib().mpsph_profile_read(self._ctx, cap, names, launches, ms, C.byref(cnt)), "mpsph_profile_read")
+        return {names[i].decode(): (launches[i], ms[i]) for i in range(min(cnt.value, cap))}
+
+
+def workspace_bytes(spec: dict, n: int, cell_log2: int = -1) -> int:
+    p, keep = make_params(spec, cell_log2=cell_log2)
+    return int(lib().mpsph_workspace_bytes(C.byref(p), int(n)))

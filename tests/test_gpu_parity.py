@@ -1,0 +1,215 @@
+"""HIP path vs the FP64 oracle: single-step parity on every configuration, bit-exact cell
+keys / cell table, invariances that must hold bit for bit, edge cases, and full-size checks.
+
+Tolerances (derived in the design doc): the GPU computes in FP32 from the same FP32 inputs; sums
+of <= ~10^3 terms carry a relative rounding error of at most a few 1e-6 of the sum of the
+absolute terms, so each accumulated quantity is compared against 1e-5 times its own
+condition scale (the oracle's sum of |pair terms|), normwise quantities against 1e-5.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_07925_amd import workloads as W
+from tests import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_07925_amd import mpsph as M
+    M.lib()  # raises when the library is missing: no fallback
+    return torch
+
+
+def _s0(spec):
+    return O.OracleParams(spec).s0
+
+
+CASES = [
+    ("square_4k", 1.0, -1),
+    ("square_4k", 0.3, 3),          # coarse cells: long candidate runs
+    ("annulus_262k", 0.02, -1),      # graded 2D, random init, annulus walls
+    ("annulus_262k", 0.02, 7),
+    ("cube_inclusion_2m", 0.008, -1),  # graded 3D, 32^3 lattice
+    ("rbf_cube_1m", 0.01, -1),
+]
+
+
+@pytest.mark.parametrize("name,scale,k", CASES)
+def test_single_step_parity(torch_cuda, name, scale, k):
+    cfg = W.config(name, scale=scale)
+    spec = cfg["spec"]
+    if spec["field"] == "rbf_exp":
+        rng = np.random.Generator(np.random.PCG64(W.BASE_SEED + 40))
+        spec = dict(spec, rbf_coeff=rng.normal(0.0, 0.1, size=spec["n_rbf"]))
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(spec, n=x32.shape[0])
+    rep = {}
+    errs = PU.check_single_step(spec, _s0(spec), x32, col, typ, cell_log2=k, report=rep)
+    print(name, scale, "k=", rep["k"], {kk: f"{v:.2e}" for kk, v in errs.items()}, rep["counts"])
+
+
+def test_keys_and_cell_table_bit_exact(torch_cuda):
+    """Cell keys of identical inputs are exact by construction: floor((x - lo) (2^k - 1)/L) per
+    axis in FP64, packed row-major; the cell table is the lower bound of each cell in the sorted
+    keys."""
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    for name, scale in (("square_4k", 1.0), ("annulus_262k", 0.01), ("cube_inclusion_2m", 0.004)):
+        cfg = W.config(name, scale=scale)
+        x32, col, typ = PU.state_f32(cfg)
+        spec = dict(cfg["spec"], n=x32.shape[0])
+        R = M.Relaxer(spec, n=x32.shape[0], s0=_s0(spec), debug=True)
+        R.load(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda())
+        R.step(1)
+        keys, cstart, k = R.cells()
+        keys = keys.cpu().numpy().astype(np.uint32)
+        cstart = cstart.cpu().numpy().astype(np.int64)
+        d = spec["dim"]
+        L = max(spec["hi"][a] - spec["lo"][a] for a in range(d))
+        X = (x32.astype(np.float64) - np.asarray(spec["lo"][:d])) * ((2 ** k - 1) / L)
+        c = np.floor(X).astype(np.int64)
+        frac = (X - c).astype(np.float32)
+        c[frac >= 1.0] += 1
+        expect = np.zeros(x32.shape[0], dtype=np.int64)
+        for a in range(d):
+            expect |= c[:, a] << (a * k)
+        assert np.array_equal(keys.astype(np.int64), expect)
+        sk = np.sort(expect)
+        ref = np.searchsorted(sk, np.arange(2 ** (d * k) + 1), side="left")
+        assert np.array_equal(cstart, ref)
+        R.close()
+
+
+def test_neighbour_set_matches_oracle(torch_cuda):
+    """The interacting pair set equals the oracle's: the ordered pair count agrees exactly up
+    to pairs within the 1e-5 band of the cut-off, on graded 2D and 3D inputs."""
+    for name, scale in (("annulus_262k", 0.004), ("cube_inclusion_2m", 0.002)):
+        cfg = W.config(name, scale=scale)
+        x32, col, typ = PU.state_f32(cfg)
+        spec = dict(cfg["spec"], n=x32.shape[0])
+        s0 = _s0(spec)
+        op = O.OracleParams(spec, s0=s0)
+        pi, pj = O.pairs(op, x32.astype(np.float64))
+        m, g = PU.gpu_run(spec, s0, x32, col, typ, fields=("nn",))
+        _, _, _, r = PU.oracle_step(spec, s0, x32, col, typ)
+        assert abs(m["pairs"] - len(pi)) <= r["band_pairs"]
+        # nearest interacting neighbour distance per particle (FP32 vs FP64)
+        assert np.allclose(g["nn"], r["nn"], rtol=1e-6, atol=0)
+
+
+def test_deterministic_repeat(torch_cuda):
+    cfg = W.config("annulus_262k", scale=0.02)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    ma, ga = PU.gpu_run(spec, s0, x32, col, typ, steps=5, fields=("a", "at"))
+    mb, gb = PU.gpu_run(spec, s0, x32, col, typ, steps=5, fields=("a", "at"))
+    assert np.array_equal(ga["x1"], gb["x1"]) and np.array_equal(ga["a"], gb["a"])
+    assert ma == mb
+
+
+def test_p0_power_of_two_invariance(torch_cuda):
+    """p0 -> 4 p0 scales every intermediate by a power of two: bit-identical trajectory."""
+    for name, scale in (("square_4k", 0.25), ("cube_inclusion_2m", 0.002)):
+        cfg = W.config(name, scale=scale)
+        x32, col, typ = PU.state_f32(cfg)
+        spec = dict(cfg["spec"], n=x32.shape[0])
+        s0 = _s0(spec)
+        ma, ga = PU.gpu_run(spec, s0, x32, col, typ, steps=4, fields=())
+        mb, gb = PU.gpu_run(dict(spec, p0=4.0), s0, x32, col, typ, steps=4, fields=())
+        assert np.array_equal(ga["x1"], gb["x1"])
+        assert mb["dt1"] == ma["dt1"] / 2
+
+
+def test_single_colour_ignores_sigma(torch_cuda):
+    cfg = W.config("square_4k", scale=0.25)
+    x32, col, typ = PU.state_f32(cfg)
+    col = np.zeros_like(col)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    ma, ga = PU.gpu_run(dict(spec, sigma0=3.0), s0, x32, col, typ, steps=3, fields=())
+    mb, gb = PU.gpu_run(dict(spec, sigma0=0.0), s0, x32, col, typ, steps=3, fields=())
+    assert np.array_equal(ga["x1"], gb["x1"])
+
+
+def test_momentum_conservation(torch_cuda):
+    cfg = W.config("cube_inclusion_2m", scale=0.01)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    m, g = PU.gpu_run(spec, s0, x32, col, typ, fields=("a", "a_abs", "at"))
+    assert np.linalg.norm(g["a"].sum(0)) <= 1e-6 * g["a_abs"].sum()
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 255, 257, 1000])
+def test_small_and_ragged_sizes(torch_cuda, n):
+    rng = np.random.Generator(np.random.PCG64(n + 3))
+    spec = W.unit_square(max(n, 1))
+    x32 = rng.uniform(0.05, 0.95, size=(n, 2)).astype(np.float32)
+    col = rng.integers(0, 3, size=n).astype(np.int32)
+    typ = np.zeros(n, np.int32)
+    spec = dict(spec, n=n)
+    s0 = 0.03
+    if n == 0:
+        from paper_1906_07925_amd import mpsph as M
+        R = M.Relaxer(spec, n=0, s0=s0)
+        R.load(torch_cuda.zeros((0, 2), device="cuda"), torch_cuda.zeros((0,), dtype=torch_cuda.int32, device="cuda"))
+        R.step(2)
+        m = R.metrics()
+        assert m["pairs"] == 0 and m["kinetic"] == 0 and m["dt1"] == 0
+        R.close()
+        return
+    PU.check_single_step(spec, s0, x32, col, typ)
+
+
+def test_feature_particles_after_many_steps(torch_cuda):
+    """Walls: particles that leave the box are clamped and retagged; a run of 30 steps on the
+    GPU and on the oracle from the same input ends with the same types (one-way retagging) and
+    feature particles lying exactly on the walls."""
+    cfg = W.config("square_4k", scale=0.25)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    m, g = PU.gpu_run(spec, s0, x32, col, typ, steps=30, fields=())
+    feat = g["t1"] > 0
+    assert feat.sum() > 0
+    onwall = np.any((g["x1"] == 0.0) | (g["x1"] == 1.0), axis=1)
+    assert np.all(onwall[feat])
+    assert np.all((g["x1"] >= 0) & (g["x1"] <= 1))
+
+
+def test_invalid_inputs_rejected(torch_cuda):
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    spec = dict(W.unit_square(4), n=4)
+    R = M.Relaxer(spec, n=4, s0=0.3)
+    x = torch.tensor([[0.1, 0.1], [0.5, 0.5], [1.5, 0.2], [0.3, 0.3]], device="cuda")
+    c = torch.zeros(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(M.MpsphError) as e:
+        R.load(x, c)
+    assert e.value.code == 1
+    x[2, 0] = float("nan")
+    with pytest.raises(M.MpsphError):
+        R.load(x, c)
+    with pytest.raises(M.MpsphError) as e:
+        R.step(1)                      # not loaded
+    assert e.value.code == 4
+    R.close()
+
+
+@pytest.mark.slow
+def test_full_size_cube_inclusion_single_step(torch_cuda):
+    """Full 2,097,152-particle graded cube at the benchmark's launch configuration: the whole
+    step against the oracle (about 10-20 s of host time)."""
+    cfg = W.config("cube_inclusion_2m")
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    rep = {}
+    errs = PU.check_single_step(spec, _s0(spec), x32, col, typ, report=rep)
+    print("full C3", {kk: f"{v:.2e}" for kk, v in errs.items()}, rep["counts"])
