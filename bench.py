@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Benchmark of the relaxation step on one MI355X.
+
+Workload: the 3D unit cube with a spherical inclusion, 2,097,152 particles (128^3 jittered
+lattice), spacing graded 1:4 with the distance to the sphere, 64 colours (seeded, synthetic).
+A step is one full pass of the relaxation step (sort, field, density + pressure + surface
+tension, both time steps, viscous pass, integrator, FP64 metrics) on that particle set.
+
+Prints one JSON line: pair interactions per second over the timed steps (ordered pairs
+i != j inside the cut-off that pass the type mask, counted on the device each step), the step
+rate, per-kernel times measured with HIP events on the library's stream, the roofline entry of
+the dominant kernel, and the CPU oracle timed on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair interactions/s + relax steps/s at 2M-particle 3D; adjoint/forward ratio"
+WORKLOAD = "cube_inclusion_2m"
+PEAK_FP32_TFLOPS = 157.3      # published MI355X FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+# Algorithmic FP32 operations per ordered interacting pair in the density / force pass:
+# separation and r^2 (8), 1/sqrt (1), density term with h_i (9), h_ij and 1/h_ij (3), kernel
+# derivative with h_ij^-(d+1) (10), pressure coefficients P_i + P_j (5), surface-tension factor
+# (2), accumulation of a and of sum |term| (9).
+FLOPS_PER_PAIR_PASS1 = 47
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_density_force_cube_inclusion_2m.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1906_07925_amd", "csrc", f)
+                  for f in ("mpsph.hip", "mpsph_device.h", "sort.hip", "sort.h")]
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
+    valid only while the kernel sources are unchanged since the counters were taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, x, col, typ):
+    """The FP64 oracle as it stands, one step of the same 2M-particle input on the host."""
+    from oracle import oracle as O
+    op = O.OracleParams(cfg["spec"])
+    t0 = time.perf_counter()
+    _, _, r = O.step(op, x.astype(np.float32).astype(np.float64), col, typ, 0, want=())
+    dt = time.perf_counter() - t0
+    return {"value": r["pairs"] / dt, "unit": "pair interactions/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"1 step (step 0) of the full {x.shape[0]}-particle input, {r['pairs']} pairs, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cell-log2", type=int, default=-1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1906_07925_amd import mpsph as M
+    from paper_1906_07925_amd import workloads as W
+
+    cfg = W.config(WORKLOAD)
+    spec = cfg["spec"]
+    x, col, typ = W.make_state(cfg)
+    n = x.shape[0]
+    print(f"[bench] {WORKLOAD}: n={n}, generating done", file=sys.stderr, flush=True)
+
+    dev_x = torch.from_numpy(x.astype(np.float32)).cuda()
+    dev_c = torch.from_numpy(col).cuda()
+    R = M.Relaxer(spec, n=n, cell_log2=args.cell_log2)
+    R.load(dev_x, dev_c)
+
+    if args.copy_calibration_mb > 0:
+        nb = args.copy_calibration_mb << 20
+        src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    R.step(args.warmup)
+    m0 = R.metrics()
+    torch.cuda.synchronize()
+    R.profile(True)
+    t0 = time.perf_counter()
+    R.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    m1 = R.metrics()
+    kern = R.profile_read()
+    R.profile(False)
+    elapsed = t1 - t0
+    pairs = m1["pairs_total"] - m0["pairs_total"]
+    cands = m1["candidates_total"] - m0["candidates_total"]
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; last residual {m1['residual_l2']:.4f}",
+          file=sys.stderr, flush=True)
+
+    # dominant kernel: the largest summed event time in the timed region
+    kname = max(kern, key=lambda k: kern[k][1])
+    launches, ms = kern[kname]
+    avg_s = ms / launches / 1e3
+    roof = {"kernel": kname}
+    if kname in ("pass_density_force",):
+        flops = FLOPS_PER_PAIR_PASS1 * pairs / launches
+        achieved = flops / avg_s / 1e12
+        roof.update(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / PEAK_FP32_TFLOPS)
+    else:
+        roof.update(bound="alu", achieved=None, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s", frac=None)
+    roof["traffic"] = load_traffic()
+    roof["avg_launch_ms"] = ms / launches
+
+    out = {
+        "metric": METRIC,
+        "value": pairs / elapsed,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "particles": n, "dim": 3, "colours": cfg["n_colours"],
+                   "cell_log2": R.cell_log2(), "field": "sphere_distance 1:4", "init": "jittered 128^3 lattice"},
+        "steps_per_s": args.steps / elapsed,
+        "pairs_per_step": pairs / args.steps,
+        "candidates_per_s": cands / elapsed,
+        "adjoint_forward_ratio": None,
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])},
+        "roofline": roof,
+    }
+    R.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, x, col, typ)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

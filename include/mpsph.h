@@ -119,6 +119,8 @@ typedef struct {
   int64_t n_elr;           /* normal particles with at least one neighbour */
   int64_t nonfinite;       /* particles with a non-finite acceleration or position */
   int64_t n_feature;       /* particles of type >= 1 after the step */
+  int64_t pairs_total;     /* sum of `pairs` over all steps since mpsph_load() */
+  int64_t candidates_total;/* sum of `candidates` over all steps since mpsph_load() */
   double residual_l2;      /* sqrt(mean over normal particles of (rho/rho_t - 1)^2) */
   double residual_linf;    /* max over normal particles of |rho/rho_t - 1| */
   double kinetic;          /* 1/2 sum |v_{n+1/2}|^2, domain units */

@@ -480,7 +480,7 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
         rc = ORC_E_NOMEM;
         continue;
       }
-      double rs = orc_kernel_w(0.0, h[i], d), ai[3] = {0, 0, 0}, A = 0.0, nearest = INFINITY;
+      double rs = orc_kernel_w(0.0, h[i], d), ai[3] = {0, 0, 0}, A = 0.0, K = 0.0, nearest = INFINITY;
       int64_t np = 0, ni = 0, nb = 0;
       for (int64_t k = 0; k < cand.n; ++k) {
         int64_t j = cand.j[k];
@@ -503,10 +503,12 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
           mag += (s * e[c]) * (s * e[c]);
         }
         A += sqrt(mag);
+        K += sqrt(mag) * (1.0 + 3.0 * (r / hij) / (2.0 - r / hij));
       }
       rho[i] = rs;
       for (int c = 0; c < d; ++c) a[i * d + c] = ai[c];
       aabs[i] = A;
+      if (out->a_kabs) out->a_kabs[i] = K;
       nn[i] = nearest;
       npair[i] = np;
       nifc[i] = ni;
@@ -555,7 +557,7 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
         rc = ORC_E_NOMEM;
         continue;
       }
-      double ai[3] = {0, 0, 0}, A = 0.0;
+      double ai[3] = {0, 0, 0}, A = 0.0, K = 0.0;
       for (int64_t k = 0; k < cand.n; ++k) {
         int64_t j = cand.j[k];
         double e[3];
@@ -573,9 +575,11 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
           mag += t * t;
         }
         A += sqrt(mag);
+        K += sqrt(mag) * (1.0 + 3.0 * (r / hij) / (2.0 - r / hij));
       }
       for (int c = 0; c < d; ++c) at[i * d + c] = ai[c];
       atabs[i] = A;
+      if (out->at_kabs) out->at_kabs[i] = K;
     }
     free(cand.j);
   }

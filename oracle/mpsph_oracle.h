@@ -48,6 +48,9 @@ typedef struct {
 typedef struct {
   /* per-particle outputs, each may be NULL; vectors are n*dim */
   double *rho, *rho_t, *h, *a, *a_abs, *vt, *at, *at_abs, *v, *dr, *nn;
+  /* conditioning diagnostics: sum over pair terms of |term| (1 + 3 q / (2 - q)), q = r/h_ij,
+   * the relative sensitivity of a kernel-derivative term to a relative change of r */
+  double *a_kabs, *at_kabs;
   /* scalars of the step */
   double dt1, dt2, sigma, residual_l2, residual_linf, kinetic;
   double elr_mean, elr_std, elr_min, elr_max;

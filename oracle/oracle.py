@@ -55,7 +55,7 @@ _DP = C.POINTER(C.c_double)
 
 class Out(C.Structure):
     _fields_ = [(k, _DP) for k in ("rho", "rho_t", "h", "a", "a_abs", "vt", "at", "at_abs", "v",
-                                   "dr", "nn")] + [
+                                   "dr", "nn", "a_kabs", "at_kabs")] + [
         (k, C.c_double) for k in ("dt1", "dt2", "sigma", "residual_l2", "residual_linf", "kinetic",
                                   "elr_mean", "elr_std", "elr_min", "elr_max")] + [
         (k, C.c_int64) for k in ("pairs", "interface_pairs", "band_pairs", "n_normal", "n_elr",
@@ -194,7 +194,8 @@ def level_set(op: OracleParams, x: np.ndarray) -> np.ndarray:
 
 
 def step(op: OracleParams, x: np.ndarray, colour: np.ndarray, ptype: np.ndarray, step_index: int,
-         want: tuple = ("rho", "rho_t", "h", "a", "a_abs", "vt", "at", "at_abs", "v", "dr", "nn")):
+         want: tuple = ("rho", "rho_t", "h", "a", "a_abs", "vt", "at", "at_abs", "v", "dr", "nn", "a_kabs",
+                        "at_kabs")):
     """Run one step.  Returns (new_x, new_type, result dict)."""
     x = np.array(x, dtype=np.float64, order="C", copy=True)
     n, d = x.shape
@@ -202,7 +203,7 @@ def step(op: OracleParams, x: np.ndarray, colour: np.ndarray, ptype: np.ndarray,
     typ = np.array(ptype, dtype=np.int32, order="C", copy=True)
     out = Out()
     arrays = {}
-    for k in ("rho", "rho_t", "h", "a_abs", "at_abs", "nn"):
+    for k in ("rho", "rho_t", "h", "a_abs", "at_abs", "nn", "a_kabs", "at_kabs"):
         if k in want:
             arrays[k] = np.zeros(n)
     for k in ("a", "vt", "at", "v", "dr"):
@@ -215,7 +216,7 @@ def step(op: OracleParams, x: np.ndarray, colour: np.ndarray, ptype: np.ndarray,
     if rc != 0:
         raise RuntimeError(f"orc_step failed with code {rc}")
     res = dict(arrays)
-    for k, _ in Out._fields_[11:]:
+    for k, _ in Out._fields_[13:]:
         res[k] = getattr(out, k)
     return x, typ, res
 

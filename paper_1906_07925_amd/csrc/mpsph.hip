@@ -48,18 +48,21 @@ namespace {
 template <int D>
 __global__ __launch_bounds__(kBlock) void load_kernel(const float *__restrict__ pos, const int32_t *__restrict__ colour,
                                                       const int32_t *__restrict__ type, int n, double lo0,
-                                                      double lo1, double lo2, double inv_cs, int k, int gmax,
+                                                      double lo1, double lo2, double xhi0, double xhi1,
+                                                      double xhi2, double inv_cs, int k, int gmax,
                                                       uint32_t *__restrict__ key, float4 *__restrict__ off,
                                                       uint32_t *__restrict__ ct, uint32_t *__restrict__ id,
                                                       int *__restrict__ bad) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const double lo[3] = {lo0, lo1, lo2};
+  const double xhi[3] = {xhi0, xhi1, xhi2};  // upper face of the bounding box in cell units
   int c[3] = {0, 0, 0};
   float o[3] = {0.f, 0.f, 0.f};
   bool ok = true;
   for (int a = 0; a < D; ++a) {
     double X = ((double)pos[(size_t)i * D + a] - lo[a]) * inv_cs;
+    if (!(X >= 0.0 && X <= xhi[a])) ok = false;
     double f = floor(X);
     float fo = (float)(X - f);
     if (fo >= 1.0f) {
@@ -206,7 +209,9 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
       const bool dens = r2 < rci2;
       const bool inter = r2 < rcij2;
       if (!(dens || inter)) return;
-      const float rinv = fast_rsq(r2);
+      // coincident particles (two particles clamped into one corner): r = 0, no direction
+      const bool apart = r2 > 1e-30f;
+      const float rinv = apart ? fast_rsq(r2) : 0.f;
       const float r = r2 * rinv;
       if (dens) {
         const float q = r * ihi, u = 1.f - 0.5f * q, u2 = u * u;
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
       if (colj != coli) ++nifc;
       if (tj < ti) return;
       ++npair;
-      if (!(r2 > 0.f)) return;
+      if (!apart) return;
       const float ih = sp.kappa * fast_rcp(hij);      // 1 / h_ij
       const float q = r * ih, u = 1.f - 0.5f * q;
       float ihp = ih * ih * ih;                       // h_ij^-(d+1)
@@ -353,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
         }
         const float hij = kh * (hi + pj.w);
         if (!(r2 < hij * hij)) return;
-        if ((int)((aj >> 12) & 3) < ti || !(r2 > 0.f)) return;
+        if ((int)((aj >> 12) & 3) < ti || !(r2 > 1e-30f)) return;
         const float4 vj = vt[j];
         const float esum = vi.w + vj.w;
         if (!(esum > 0.f)) return;
@@ -511,6 +516,10 @@ __global__ __launch_bounds__(256) void finalize(int nblocks, const double *__res
     float d1 = __uint_as_float(dtcells[0]), d2 = __uint_as_float(dtcells[1]);
     m[16] = d1 < INFINITY ? (double)d1 : 0.0;
     m[17] = d2 < INFINITY ? (double)d2 : 0.0;
+    // running totals since the last load (exact integers below 2^53)
+    m[18] += m[P_PAIRS];
+    m[19] += m[P_CAND];
+    m[20] += 1.0;
   }
 }
 
@@ -599,7 +608,7 @@ struct Layout {
 
 struct Derived {
   int dim, k, gmax;
-  double L, cs, inv_cs, lo[3];
+  double L, cs, inv_cs, lo[3], xhi[3];
   double smin, smax, lip;  // spacing bounds (domain units), Lipschitz constant of s
   double search_fac;
 };
@@ -817,6 +826,7 @@ int derive(const mpsph_params *p, int64_t n, double s0, Derived *d) {
   d->gmax = (1 << k) - 1;
   d->cs = L / (double)d->gmax;
   d->inv_cs = (double)d->gmax / L;
+  for (int a = 0; a < 3; ++a) d->xhi[a] = a < p->dim ? (p->hi[a] - p->lo[a]) * d->inv_cs : 0.0;
   // neighbour search bound: j interacts only if r < kappa (h_i + h_j)/2 and h_j <= h_i + L_h r
   // (L_h = tau * Lipschitz(s)), so r < kappa h_i / (1 - kappa L_h / 2).
   double Lh = p->tau * d->lip;
@@ -1200,7 +1210,8 @@ int mpsph_load(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, cons
   if (n > 0) {
     auto kern = ctx->p.dim == 2 ? load_kernel<2> : load_kernel<3>;
     kern<<<(n + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
-        d_pos, d_colour, d_type, n, ctx->d.lo[0], ctx->d.lo[1], ctx->d.lo[2], ctx->d.inv_cs, ctx->d.k, ctx->d.gmax,
+        d_pos, d_colour, d_type, n, ctx->d.lo[0], ctx->d.lo[1], ctx->d.lo[2], ctx->d.xhi[0], ctx->d.xhi[1],
+        ctx->d.xhi[2], ctx->d.inv_cs, ctx->d.k, ctx->d.gmax,
         ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id),
         ctx->at<int>(L.bad));
     HIP_OK(hipGetLastError());
@@ -1241,6 +1252,8 @@ int mpsph_metrics(mpsph_ctx *ctx, mpsph_metrics_t *out) {
   out->n_feature = (int64_t)m[P_NFEAT];
   out->residual_l2 = m[P_NNORM] > 0 ? std::sqrt(m[P_E2] / m[P_NNORM]) : 0.0;
   out->residual_linf = m[P_EMAX];
+  out->pairs_total = (int64_t)m[18];
+  out->candidates_total = (int64_t)m[19];
   out->kinetic = m[P_KE] * cs * cs;
   out->dt1 = m[16];
   out->dt2 = m[17];

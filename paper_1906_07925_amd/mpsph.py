@@ -47,7 +47,7 @@ class Params(C.Structure):
 
 class Metrics(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("step", "pairs", "interface_pairs", "candidates", "n_normal",
-                                         "n_elr", "nonfinite", "n_feature")] + \
+                                         "n_elr", "nonfinite", "n_feature", "pairs_total", "candidates_total")] + \
                [(k, C.c_double) for k in ("residual_l2", "residual_linf", "kinetic", "dt1", "dt2", "sigma",
                                           "elr_mean", "elr_std", "elr_min", "elr_max")]
 

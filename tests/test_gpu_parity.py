@@ -213,3 +213,18 @@ def test_full_size_cube_inclusion_single_step(torch_cuda):
     rep = {}
     errs = PU.check_single_step(spec, _s0(spec), x32, col, typ, report=rep)
     print("full C3", {kk: f"{v:.2e}" for kk, v in errs.items()}, rep["counts"])
+
+
+def test_coincident_particles(torch_cuda):
+    """Particles at identical positions (as when two particles are clamped into one corner)
+    contribute W(0) to each other's density and no force; nothing becomes non-finite."""
+    rng = np.random.Generator(np.random.PCG64(17))
+    x32 = rng.uniform(0.1, 0.9, size=(200, 3)).astype(np.float32)
+    x32[10] = x32[11]
+    x32[20] = x32[21] = x32[22]
+    x32[30] = x32[31] = np.array([0.0, 0.0, 1.0], np.float32)
+    col = rng.integers(0, 2, size=200).astype(np.int32)
+    typ = np.zeros(200, np.int32)
+    typ[30] = typ[31] = 3
+    spec = dict(W.unit_cube(200), n=200)
+    PU.check_single_step(spec, 0.12, x32, col, typ)
