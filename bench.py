@@ -29,12 +29,16 @@ METRIC = "pair interactions/s + relax steps/s at 2M-particle 3D; adjoint/forward
 WORKLOAD = "cube_inclusion_2m"
 PEAK_FP32_TFLOPS = 157.3      # published MI355X FP32 vector peak
 PEAK_HBM_GBS = 8000.0
-# Algorithmic FP32 operations per ordered interacting pair in the density / force pass:
-# separation and r^2 (8), 1/sqrt (1), density term with h_i (9), h_ij and 1/h_ij (3), kernel
-# derivative with h_ij^-(d+1) (10), pressure coefficients P_i + P_j (5), surface-tension factor
-# (2), accumulation of a and of sum |term| (9).
-FLOPS_PER_PAIR_PASS1 = 47
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pass_density_force_cube_inclusion_2m.json")
+# Algorithmic FP32 operations per ordered interacting pair (each arithmetic operation of the
+# formula once, a fused multiply-add as two, rsqrt / rcp as one):
+#  density / force pass: separation 6, r^2 5, 1/r and r 2, density term with h_i 9, h_ij and
+#    1/h_ij 3, q and 1 - q/2 3, h_ij^-(d+1) 3, P_j from s_j 4, P_i + P_j 1, (1 + beta) 1,
+#    coefficient 6, accumulation of a 6                                               = 49
+#  viscous pass: separation 6, r^2 5, 1/r and r 2, h_ij and 1/h_ij 3, q and 1 - q/2 3,
+#    h_ij^-(d+1) 3, 1/rho_t,j^2 and the sum 5, eta_j 1, harmonic mean 4, coefficient 6,
+#    v~_j and v~_ij 6, accumulation 6                                                  = 50
+FLOPS_PER_PAIR = {"pass_density_force": 49, "pass_viscous_integrate": 50}
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1906_07925_amd", "csrc", f)
                   for f in ("mpsph.hip", "mpsph_device.h", "sort.hip", "sort.h")]
 
@@ -46,11 +50,11 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
-    valid only while the kernel sources are unchanged since the counters were taken."""
+def load_traffic(kernel: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, valid only
+    while the kernel sources are unchanged since the counters were taken."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(os.path.join(TRAFFIC_DIR, f"traffic_{kernel}_{WORKLOAD}.json")))
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_digest") != kernel_source_digest():
@@ -128,14 +132,15 @@ def main():
     launches, ms = kern[kname]
     avg_s = ms / launches / 1e3
     roof = {"kernel": kname}
-    if kname in ("pass_density_force",):
-        flops = FLOPS_PER_PAIR_PASS1 * pairs / launches
+    if kname in FLOPS_PER_PAIR:
+        flops = FLOPS_PER_PAIR[kname] * pairs / launches
         achieved = flops / avg_s / 1e12
         roof.update(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / PEAK_FP32_TFLOPS)
+                    frac=achieved / PEAK_FP32_TFLOPS, flops_per_pair=FLOPS_PER_PAIR[kname],
+                    pairs_per_launch=pairs / launches)
     else:
-        roof.update(bound="alu", achieved=None, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s", frac=None)
-    roof["traffic"] = load_traffic()
+        roof.update(bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s", frac=None)
+    roof["traffic"] = load_traffic(kname)
     roof["avg_launch_ms"] = ms / launches
 
     out = {

@@ -107,7 +107,7 @@ typedef struct {
   double nu_coeff;         /* nu = nu_coeff r_c |v~| (Eq. 21), 0.1 in the paper */
   double c_acc, c_vel, c_visc; /* constants of Eq. 29: 0.25, 1/40, 0.125 */
   int32_t cell_log2;       /* cells per axis = 2^cell_log2; -1: chosen from the field */
-  int32_t debug;           /* 1: keep a~, v, dr and the nearest distance of the last step */
+  int32_t debug;           /* 1: keep rho, sum|term|, a~, v, dr, nearest distance of the last step */
 } mpsph_params;
 
 typedef struct {
@@ -162,8 +162,8 @@ MPSPH_API int mpsph_metrics(mpsph_ctx *ctx, mpsph_metrics_t *out);
 MPSPH_API int mpsph_store(mpsph_ctx *ctx, float *d_pos, int32_t *d_type);
 
 /* Copy one per-particle quantity of the last step (MPSPH_F_*) into d_out (float32, n or
- * n x dim values, original particle order, domain units).  MPSPH_F_AT, MPSPH_F_V, MPSPH_F_DR
- * and MPSPH_F_NN need params.debug = 1.  Synchronises.  Errors: MPSPH_E_INVALID (unknown field), MPSPH_E_STATE. */
+ * n x dim values, original particle order, domain units).  MPSPH_F_RHO, MPSPH_F_A_ABS, MPSPH_F_AT,
+ * MPSPH_F_V, MPSPH_F_DR and MPSPH_F_NN need params.debug = 1.  Synchronises.  Errors: MPSPH_E_INVALID (unknown field), MPSPH_E_STATE. */
 MPSPH_API int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out);
 
 /* Cell structure of the last step: d_key (n uint32, the cell key of each particle in

@@ -20,16 +20,20 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str | None = None, defines: dict | None = None) -> str:
+    """Compile the library; ``defines`` sets tuning macros (row group, batch width, waves per
+    EU) for a build written to ``out`` instead of the default in-tree path."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    out_tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+    lib = out or LIB
+    out_tmp = lib + ".tmp"
+    dflags = [f"-D{k}={v}" for k, v in (defines or {}).items()]
+    cmd = [hipcc, *FLAGS, *dflags, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", out_tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(out_tmp, LIB)
-    return LIB
+    os.replace(out_tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

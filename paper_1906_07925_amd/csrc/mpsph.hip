@@ -6,7 +6,8 @@
 //          (type | colour << 2), id u32 (index at load)
 //   work   (order of this step's sort): key u32, pos float4 (offsets, h), jaux u32
 //          (cx | type << 12 | colour << 14), id u32
-//   per step: acc float4 (a, sum|term|), rho f32, vt float4 (v~, eta), cell table u32[ncells+1]
+//   per step: acc float4 (a, e = rho_t nu_coeff r_c |a|), cell table u32[ncells+1]; rho, sum|term|,
+//             a~, v, dr, nearest distance only in debug mode
 // Positions are an integer cell coordinate per axis (packed in the key, row-major, x fastest)
 // plus a float offset in [0, 1) in cell units, so pair separations are formed from exact
 // integer differences plus differences of numbers below one.  Lengths inside the kernels are
@@ -18,10 +19,10 @@
 //   reorder_field   gather the state in key order, evaluate the target field (Eq. 1-2, 16), fill
 //                   the cell table
 //   pass_density_force  density (Eq. 17), pressure + surface tension (Eq. 18-19, 23-25),
-//                   projection (Eq. 30-31), first time-step candidate (Eq. 29)
-//   kick            mid-point velocity (Eq. 26), viscosity (Eq. 21-22), second time step (Eq. 29)
-//   pass_viscous_integrate  viscous acceleration (Eq. 20), velocity (Eq. 27), drift (Eq. 28),
-//                   feature projection and re-tagging (Eq. 32)
+//                   projection (Eq. 30-31), first time step (Eq. 29, block minima)
+//   pass_viscous_integrate  mid-point velocity (Eq. 26), viscosity (Eq. 21-22), viscous
+//                   acceleration (Eq. 20), second time step (Eq. 29), velocity (Eq. 27), drift
+//                   (Eq. 28), feature projection and re-tagging (Eq. 32)
 //   finalize        FP64 reduction of the per-block partials in a fixed order
 #include <hip/hip_runtime.h>
 
@@ -93,10 +94,7 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
     uint32_t *__restrict__ wjaux, uint32_t *__restrict__ wid, uint32_t *__restrict__ cstart,
     uint32_t *__restrict__ dtcells) {
   int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i == 0) {
-    dtcells[0] = kInfBits;
-    dtcells[1] = kInfBits;
-  }
+  if (i < kDtSlots) dtcells[i] = kInfBits;
   if (i > n) return;
   // cells (key[i-1], key[i]] start at sorted index i; the sentinel thread i = n closes the table
   const uint32_t lo = i == 0 ? 0u : skey[i - 1] + 1u;
@@ -117,12 +115,36 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
   wid[i] = sid[s];
 }
 
-// Iterate over the neighbour candidates of particle i: every x-run of cells (fixed y, z) that
-// intersects the ball of radius rs around the particle is one contiguous range of the sorted
-// arrays.  body(j, cy, cz) is called for each candidate j != i.
-template <int D, typename F>
-__device__ __forceinline__ void for_candidates(int i, const int *ci, const float *oi, float rs, const GridDev &g,
-                                               const uint32_t *__restrict__ cstart, F &&body) {
+// Neighbour candidates of particle i.  Every x-run of cells (fixed y, z) that intersects the ball
+// of radius rs around the particle is one contiguous range of the sorted arrays.  Rows are taken
+// four at a time (their eight cell-table reads in flight together) and the candidates of the
+// four rows are visited as one flat sequence, four per iteration with all loads issued first.
+// load(j) fetches the record of particle j; body(rec, drow, valid) consumes it, where drow packs
+// the integer row offsets (ci[1] - cy) in the low and (ci[2] - cz) in the high 16 bits.
+// Tuning of the candidate scan (measured on the 2M-particle graded cube: one row at a time,
+// one candidate per iteration, with a branch around the pair arithmetic is fastest).
+#ifndef MPSPH_ROWS_G
+#define MPSPH_ROWS_G 1
+#endif
+#ifndef MPSPH_BATCH_U
+#define MPSPH_BATCH_U 1
+#endif
+#ifndef MPSPH_BRANCHY
+#define MPSPH_BRANCHY 1
+#endif
+#ifndef MPSPH_WAVES_PER_EU
+#define MPSPH_WAVES_PER_EU 0
+#endif
+#if MPSPH_WAVES_PER_EU > 0
+#define PAIR_KERNEL_ATTR __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPSPH_WAVES_PER_EU, 8)))
+#else
+#define PAIR_KERNEL_ATTR __launch_bounds__(kBlock)
+#endif
+
+template <int D, typename Rec, typename LoadF, typename BodyF>
+__device__ __forceinline__ void scan_candidates(int i, const int *ci, const float *oi, float rs, const GridDev &g,
+                                                const uint32_t *__restrict__ cstart, LoadF &&load, BodyF &&body) {
+  constexpr int G = MPSPH_ROWS_G, U = MPSPH_BATCH_U;
   // a finite, non-negative radius keeps every cell range inside [0, gmax] (NaN -> 0)
   rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
   const float rs2 = rs * rs;
@@ -130,41 +152,124 @@ __device__ __forceinline__ void for_candidates(int i, const int *ci, const float
   const int z1 = D == 3 ? min(g.gmax, ci[2] + (int)floorf(oi[2] + rs)) : 0;
   const int y0 = max(0, ci[1] + (int)floorf(oi[1] - rs));
   const int y1 = min(g.gmax, ci[1] + (int)floorf(oi[1] + rs));
-  for (int cz = z0; cz <= z1; ++cz) {
-    float ez = 0.f;
-    if constexpr (D == 3) {
-      float lo = (float)(cz - ci[2]) - oi[2], hi = lo + 1.f;
-      ez = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
-    }
-    for (int cy = y0; cy <= y1; ++cy) {
-      float lo = (float)(cy - ci[1]) - oi[1], hi = lo + 1.f;
-      float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
-      float d2 = ey * ey + ez * ez;
-      if (d2 >= rs2) continue;
-      float wx = sqrtf(rs2 - d2);
-      int x0 = max(0, ci[0] + (int)floorf(oi[0] - wx));
-      int x1 = min(g.gmax, ci[0] + (int)floorf(oi[0] + wx));
+  const uint32_t nmax = (uint32_t)g.n;
+  int cy = y0, cz = z0;
+  while (cz <= z1) {
+    uint32_t off[G], P[G + 1];
+    uint32_t drow[G], klo[G], khi[G];
+    bool hit[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      const bool live = cz <= z1;
+      float ez = 0.f;
+      if constexpr (D == 3) {
+        const float lo = (float)(cz - ci[2]) - oi[2], hi = lo + 1.f;
+        ez = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
+      }
+      const float lo = (float)(cy - ci[1]) - oi[1], hi = lo + 1.f;
+      const float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
+      const float d2 = ey * ey + ez * ez;
+      hit[t] = live && d2 < rs2;
+      const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
+      const int x0 = max(0, ci[0] + (int)floorf(oi[0] - wx));
+      const int x1 = min(g.gmax, ci[0] + (int)floorf(oi[0] + wx));
       uint32_t kb = (uint32_t)x0 | ((uint32_t)cy << g.k);
       if constexpr (D == 3) kb |= (uint32_t)cz << (2 * g.k);
-      const uint32_t j0 = cstart[kb], j1 = min(cstart[kb + (uint32_t)(x1 - x0) + 1u], (uint32_t)g.n);
-      for (uint32_t j = j0; j < j1; ++j) {
-        if ((int)j == i) continue;
-        body((int)j, cy, cz);
+      klo[t] = hit[t] ? kb : 0u;
+      khi[t] = hit[t] ? kb + (uint32_t)(x1 - x0) + 1u : 0u;
+      drow[t] = ((uint32_t)(ci[1] - cy) & 0xffffu) | ((uint32_t)(D == 3 ? ci[2] - cz : 0) << 16);
+      if (live && ++cy > y1) {
+        cy = y0;
+        ++cz;
       }
     }
+    // all cell-table reads of the group in flight together
+    uint32_t ja[G], jb[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      ja[t] = cstart[klo[t]];
+      jb[t] = cstart[khi[t]];
+    }
+    P[0] = 0u;
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      const uint32_t b = min(jb[t], nmax);
+      const uint32_t len = (hit[t] && b > ja[t]) ? b - ja[t] : 0u;
+      off[t] = ja[t] - P[t];
+      P[t + 1] = P[t] + len;
+    }
+    const uint32_t T = P[G];
+    for (uint32_t s = 0; s < T; s += U) {
+      Rec rec[U];
+      uint32_t dr[U];
+      bool val[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t t = s + (uint32_t)u;
+        uint32_t o = off[0];
+        dr[u] = drow[0];
+#pragma unroll
+        for (int q = 1; q < G; ++q) {
+          const bool c = t >= P[q];
+          o = c ? off[q] : o;
+          dr[u] = c ? drow[q] : dr[u];
+        }
+        const uint32_t j = o + t;
+        const bool v = t < T && j != (uint32_t)i;
+        val[u] = v;
+        rec[u] = load(v ? (int)j : i);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) body(rec[u], dr[u], val[u]);
+    }
   }
+}
+
+struct RecP {
+  float4 p;
+  uint32_t a;
+};
+struct RecV {
+  float4 p;
+  uint32_t a;
+  float4 acc;
+};
+
+__device__ __forceinline__ float row_dy(uint32_t dr) { return (float)(int)(int16_t)(dr & 0xffffu); }
+__device__ __forceinline__ float row_dz(uint32_t dr) { return (float)((int)dr >> 16); }
+
+// Minimum of the first time step: one atomic per block, spread over kDtSlots words.
+__device__ __forceinline__ void block_min_to_slots(float v, int lb, uint32_t *slots) {
+  __shared__ float wmin[kBlock / kWave];
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) wmin[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = wmin[0];
+    for (int w = 1; w < kBlock / kWave; ++w) m = fminf(m, wmin[w]);
+    if (m < INFINITY) atomic_min_pos(&slots[lb & (kDtSlots - 1)], m);
+  }
+}
+
+// First time step (Eq. 29 with v = 0): minimum over the slots, every lane of the wave gets it.
+__device__ __forceinline__ float read_dt1(const uint32_t *slots) {
+  float v = __uint_as_float(slots[threadIdx.x & (kDtSlots - 1)]);
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+  return v < INFINITY ? v : 0.f;
 }
 
 // Pass 1: density (Eq. 17, self term included, radius kappa h_i) and
 //   a_i = -sum_j (1 + beta_ij) (P_i + P_j) dW(r_ij, h_ij)/dr e_ij   (Eq. 18, 23; gamma = 2, Eq. 19)
 // with e_ij = r_ij / |r_ij|, r_ij = r_i - r_j, beta_ij = sigma for different colours (Eq. 24),
 // P = p0 / rho_t^2, h_ij = (h_i + h_j)/2, over j with r_ij < kappa h_ij that particle i feels.
+// Writes acc = (a after the force mapping of Eq. 30-31, e_i) with e_i = rho_t nu_coeff r_c |a_i|,
+// the viscosity of Eq. 21-22 per unit of dt1/2, and the first time-step candidate (Eq. 29).
 template <int D>
-__global__ __launch_bounds__(kBlock) void pass_density_force(
+__global__ PAIR_KERNEL_ATTR void pass_density_force(
     int n, GridDev g, StepDev sp, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
     const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ cstart, float4 *__restrict__ acc,
-    float *__restrict__ rho_out, float *__restrict__ nn_out, uint32_t *__restrict__ dtcells,
-    double *__restrict__ partials) {
+    float *__restrict__ rho_out, float *__restrict__ nn_out, float *__restrict__ aabs_out,
+    uint32_t *__restrict__ dtslots, double *__restrict__ partials) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int i = lb * kBlock + threadIdx.x;
   const bool active = i < n;
@@ -184,78 +289,81 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
     const uint32_t coli = ai >> 14;
     const float hi = pi.w;
     const float si = hi * sp.inv_tau;                 // target spacing, rho_t = s^-d
-    const float si2 = si * si;
-    const float Pi = sp.p0c * powd<D>(si2);           // p0 / rho_t^2 = p0 s^(2d)
+    const float Pi = sp.p0c * powd<D>(si * si);       // p0 / rho_t^2 = p0 s^(2d)
     const float ihi = fast_rcp(hi);
     const float rci = sp.kappa * hi, rci2 = rci * rci;
     const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
     const float kh = 0.5f * sp.kappa;
+    const float alpha5 = 5.f * sp.alpha;
+    const float opb = 1.f + sp.sigma;
     float wsum = 0.f, ax = 0.f, ay = 0.f, az = 0.f, A = 0.f, nn2 = INFINITY;
     uint32_t npair = 0, nifc = 0, ncand = 0;
-    for_candidates<D>(i, ci, oi, rs, g, cstart, [&](int j, int cy, int cz) {
-      const float4 pj = wpos[j];
-      const uint32_t aj = wjaux[j];
-      const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
-      const float dy = (float)(ci[1] - cy) + (oi[1] - pj.y);
-      float r2 = dx * dx + dy * dy;
-      float dz = 0.f;
-      if constexpr (D == 3) {
-        dz = (float)(ci[2] - cz) + (oi[2] - pj.z);
-        r2 += dz * dz;
-      }
-      ++ncand;
-      const float hij = kh * (hi + pj.w);             // kappa h_ij
-      const float rcij2 = hij * hij;
-      const bool dens = r2 < rci2;
-      const bool inter = r2 < rcij2;
-      if (!(dens || inter)) return;
-      // coincident particles (two particles clamped into one corner): r = 0, no direction
-      const bool apart = r2 > 1e-30f;
-      const float rinv = apart ? fast_rsq(r2) : 0.f;
-      const float r = r2 * rinv;
-      if (dens) {
-        const float q = r * ihi, u = 1.f - 0.5f * q, u2 = u * u;
-        wsum += u2 * u2 * (1.f + 2.f * q);
-      }
-      if (!inter) return;
-      nn2 = fminf(nn2, r2);
-      const uint32_t colj = aj >> 14;
-      const int tj = (aj >> 12) & 3;
-      if (colj != coli) ++nifc;
-      if (tj < ti) return;
-      ++npair;
-      if (!apart) return;
-      const float ih = sp.kappa * fast_rcp(hij);      // 1 / h_ij
-      const float q = r * ih, u = 1.f - 0.5f * q;
-      float ihp = ih * ih * ih;                       // h_ij^-(d+1)
-      if constexpr (D == 3) ihp *= ih;
-      const float sj = pj.w * sp.inv_tau, sj2 = sj * sj;
-      const float Pj = sp.p0c * powd<D>(sj2);
-      const float beta = colj != coli ? sp.sigma : 0.f;
-      // dW/dr = alpha h^-(d+1) (-5 q) (1 - q/2)^3
-      const float s = (1.f + beta) * (Pi + Pj) * sp.alpha * ihp * 5.f * q * u * u * u * rinv;
-      ax += s * dx;
-      ay += s * dy;
-      az += s * dz;
-      A += s * r;
-    });
+    scan_candidates<D, RecP>(
+        i, ci, oi, rs, g, cstart, [&](int j) { return RecP{wpos[j], wjaux[j]}; },
+        [&](const RecP &rj, uint32_t drw, bool v) {
+          const float4 pj = rj.p;
+          const uint32_t aj = rj.a;
+          const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+          const float dy = row_dy(drw) + (oi[1] - pj.y);
+          float r2 = dx * dx + dy * dy;
+          float dz = 0.f;
+          if constexpr (D == 3) {
+            dz = row_dz(drw) + (oi[2] - pj.z);
+            r2 += dz * dz;
+          }
+          ncand += v ? 1u : 0u;
+          const float hij = kh * (hi + pj.w);           // kappa h_ij
+          const bool dens = v && r2 < rci2;
+          const bool inter = v && r2 < hij * hij;
+          // coincident particles (two particles clamped into one corner): r = 0, no direction
+          const bool apart = r2 > 1e-30f;
+          const float rinv = fast_rsq(apart ? r2 : 1.f);
+          const float r = apart ? r2 * rinv : 0.f;
+          const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
+          wsum += dens ? u2 * u2 * fmaf(2.f, q, 1.f) : 0.f;
+          const uint32_t colj = aj >> 14;
+          const bool diff = colj != coli;
+          const bool feel = inter && (int)((aj >> 12) & 3) >= ti;
+          nifc += (inter && diff) ? 1u : 0u;
+          npair += feel ? 1u : 0u;
+          nn2 = inter ? fminf(nn2, r2) : nn2;
+#if MPSPH_BRANCHY
+          if (!(feel && apart)) return;
+#endif
+          const float ih = sp.kappa * fast_rcp(hij);    // 1 / h_ij
+          const float q2 = r * ih, uu = fmaf(-0.5f, q2, 1.f);
+          const float ih2 = ih * ih;
+          const float ihp = D == 3 ? ih2 * ih2 : ih2 * ih;  // h_ij^-(d+1)
+          const float sj = pj.w * sp.inv_tau;
+          const float Pj = sp.p0c * powd<D>(sj * sj);
+          // -dW/dr = alpha h^-(d+1) 5 q (1 - q/2)^3 >= 0
+          float s = (diff ? opb : 1.f) * (Pi + Pj) * (alpha5 * ihp * q2 * uu * uu * uu * rinv);
+          s = (feel && apart) ? s : 0.f;
+          ax = fmaf(s, dx, ax);
+          ay = fmaf(s, dy, ay);
+          az = fmaf(s, dz, az);
+          A = fmaf(s, r, A);
+        });
     const float ihd = D == 3 ? ihi * ihi * ihi : ihi * ihi;
     const float rho = sp.alpha * ihd * (1.f + wsum);
     float a[3] = {ax, ay, az};
     project_feature<D>(g, ti, ci, oi, a);
-    acc[i] = make_float4(a[0], a[1], D == 3 ? a[2] : 0.f, A);
-    rho_out[i] = rho;
+    const float am2 = a[0] * a[0] + a[1] * a[1] + (D == 3 ? a[2] * a[2] : 0.f);
+    const float am = sqrtf(am2);
+    const float ehat = sp.nu_coeff * rci * am / powd<D>(si);  // rho_t nu_coeff r_c |a|
+    acc[i] = make_float4(a[0], a[1], D == 3 ? a[2] : 0.f, ehat);
+    if (rho_out) rho_out[i] = rho;
     if (nn_out) nn_out[i] = sqrtf(nn2);
-    float am2 = a[0] * a[0] + a[1] * a[1] + (D == 3 ? a[2] * a[2] : 0.f);
+    if (aabs_out) aabs_out[i] = A;
     if (ti != 3 && am2 > 0.f) dtc = sp.c_acc * sqrtf(rci * fast_rsq(am2));
-    bool fin = isfinite(am2) && isfinite(rho);
+    const bool fin = isfinite(am2) && isfinite(rho);
     if (ti == 0) {
-      double e = (double)(rho * powd<D>(si)) - 1.0;   // rho / rho_t - 1
+      const double e = (double)(rho * powd<D>(si)) - 1.0;   // rho / rho_t - 1
       part[0] = e * e;
       part[1] = fabs(e);
       part[2] = 1.0;
       if (nn2 < INFINITY) {
-        double elr = (double)sqrtf(nn2) / (double)si;
+        const double elr = (double)sqrtf(nn2) / (double)si;
         part[3] = elr;
         part[4] = elr * elr;
         part[5] = elr;
@@ -268,45 +376,8 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
     part[10] = (double)ncand;
     part[11] = fin ? 0.0 : 1.0;
   }
-  // time-step candidate: wave min then one atomic per wave (order-free)
-  for (int off = kWave / 2; off > 0; off >>= 1) dtc = fminf(dtc, __shfl_xor(dtc, off, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0 && dtc < INFINITY) atomic_min_pos(&dtcells[0], dtc);
+  block_min_to_slots(dtc, lb, dtslots);
   block_reduce_write<12>(part, ops, partials + (size_t)lb * kNumPartials);
-}
-
-// Mid-point velocity v~ = a dt1 / 2 (Eq. 26 with the velocity reset v_n = 0), viscosity
-// nu = nu_coeff r_c |v~| (Eq. 21), eta = rho_t nu (Eq. 22), and the second time-step
-// candidate: min of the three criteria of Eq. 29.
-template <int D>
-__global__ __launch_bounds__(kBlock) void kick(int n, StepDev sp, const float4 *__restrict__ wpos,
-                                               const uint32_t *__restrict__ wjaux, const float4 *__restrict__ acc,
-                                               float4 *__restrict__ vt, uint32_t *__restrict__ dtcells) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  float dtc = INFINITY;
-  if (i < n) {
-    float dt1 = __uint_as_float(dtcells[0]);
-    if (!(dt1 < INFINITY)) dt1 = 0.f;
-    const float4 a = acc[i];
-    const int t = (wjaux[i] >> 12) & 3;
-    const float h = wpos[i].w;
-    const float rc = sp.kappa * h;
-    const float s = h * sp.inv_tau;
-    const float hd = 0.5f * dt1;
-    float v[3] = {a.x * hd, a.y * hd, a.z * hd};
-    if (t == 3) v[0] = v[1] = v[2] = 0.f;
-    const float vm = sqrtf(v[0] * v[0] + v[1] * v[1] + (D == 3 ? v[2] * v[2] : 0.f));
-    const float nu = sp.nu_coeff * rc * vm;
-    const float eta = nu / powd<D>(s);               // rho_t nu, rho_t = s^-d
-    vt[i] = make_float4(v[0], v[1], v[2], eta);
-    if (t != 3) {
-      const float am2 = a.x * a.x + a.y * a.y + (D == 3 ? a.z * a.z : 0.f);
-      if (am2 > 0.f) dtc = fminf(dtc, sp.c_acc * sqrtf(rc * fast_rsq(am2)));
-      if (vm > 0.f) dtc = fminf(dtc, sp.c_vel * rc / vm);
-      if (nu > 0.f) dtc = fminf(dtc, sp.c_visc * rc * rc / nu);
-    }
-  }
-  for (int off = kWave / 2; off > 0; off >>= 1) dtc = fminf(dtc, __shfl_xor(dtc, off, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0 && dtc < INFINITY) atomic_min_pos(&dtcells[1], dtc);
 }
 
 // Box type from the number of faces a particle lies on.
@@ -316,88 +387,99 @@ __device__ __forceinline__ int type_from_faces(int nf, int d) {
 
 // Pass 2: viscous acceleration (Eq. 20 with rho = rho_t, Eq. 22)
 //   a~_i = sum_j [2 eta_i eta_j / (eta_i + eta_j)] (1/rho_t,i^2 + 1/rho_t,j^2) dW(r_ij,h_ij)/dr v~_ij / r_ij
-// over the same pairs as pass 1, then per particle: projection, v = v~ + a~ dt2 / 2 (Eq. 27),
-// drift r += v dt2 (Eq. 28), feature projection / re-tagging (Eq. 32); the new state is
-// written in this step's sorted order.
+// over the same pairs as pass 1, with the mid-point velocity v~ = a dt1 / 2 (Eq. 26 after the
+// velocity reset) and eta = rho_t nu_coeff r_c |v~| (Eq. 21-22) formed from pass 1's output.
+// Then per particle: projection, v = v~ + a~ dt2 / 2 (Eq. 27), drift r += v dt2 (Eq. 28),
+// feature projection / re-tagging (Eq. 32); the new state is written in this step's order.
+// With v~ = a dt1/2 the three criteria of Eq. 29 are increasing functions of r_c/|a| and give
+// dt2 = dt1 min(1, 2 min(c_vel, c_visc / nu_coeff) / c_acc^2) (sp.dt2_factor).
 template <int D>
-__global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
+__global__ PAIR_KERNEL_ATTR void pass_viscous_integrate(
     int n, GridDev g, StepDev sp, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
     const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ wid, const uint32_t *__restrict__ cstart,
-    const float4 *__restrict__ vt, const uint32_t *__restrict__ dtcells, uint32_t *__restrict__ skey,
+    const float4 *__restrict__ acc, const uint32_t *__restrict__ dtslots, uint32_t *__restrict__ skey,
     float4 *__restrict__ soff, uint32_t *__restrict__ sct, uint32_t *__restrict__ sid, float4 *__restrict__ at_out,
     float4 *__restrict__ v_out, float4 *__restrict__ dr_out, double *__restrict__ partials) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int i = lb * kBlock + threadIdx.x;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   const int ops[4] = {0, 0, 0, 0};
+  const float dt1 = read_dt1(dtslots);
+  const float hdt = 0.5f * dt1;
+  const float dt2 = dt1 * sp.dt2_factor;
   if (i < n) {
     int ci[3];
     unpack_key<D>(wkey[i], g.k, g.xmask, ci);
     const float4 pi = wpos[i];
-    float oi[3] = {pi.x, pi.y, pi.z};
+    const float oi[3] = {pi.x, pi.y, pi.z};
     const uint32_t ai = wjaux[i];
     int ti = (ai >> 12) & 3;
     const float hi = pi.w;
-    const float si = hi * sp.inv_tau, si2 = si * si;
-    const float invi = powd<D>(si2);                  // 1 / rho_t,i^2
-    const float4 vi = vt[i];
+    const float si = hi * sp.inv_tau;
+    const float invi = powd<D>(si * si);              // 1 / rho_t,i^2
+    const float4 acci = acc[i];
+    const float vix = hdt * acci.x, viy = hdt * acci.y, viz = hdt * acci.z, ei = hdt * acci.w;
     const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
     const float kh = 0.5f * sp.kappa;
+    const float alpha5 = 5.f * sp.alpha;
     float bx = 0.f, by = 0.f, bz = 0.f;
     // with eta_i = 0 every harmonic-mean viscosity of particle i vanishes: nothing to sum
-    if (vi.w > 0.f) {
-      for_candidates<D>(i, ci, oi, rs, g, cstart, [&](int j, int cy, int cz) {
-        const float4 pj = wpos[j];
-        const uint32_t aj = wjaux[j];
-        const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
-        const float dy = (float)(ci[1] - cy) + (oi[1] - pj.y);
-        float r2 = dx * dx + dy * dy;
-        if constexpr (D == 3) {
-          const float dz = (float)(ci[2] - cz) + (oi[2] - pj.z);
-          r2 += dz * dz;
-        }
-        const float hij = kh * (hi + pj.w);
-        if (!(r2 < hij * hij)) return;
-        if ((int)((aj >> 12) & 3) < ti || !(r2 > 1e-30f)) return;
-        const float4 vj = vt[j];
-        const float esum = vi.w + vj.w;
-        if (!(esum > 0.f)) return;
-        const float rinv = fast_rsq(r2);
-        const float r = r2 * rinv;
-        const float ih = sp.kappa * fast_rcp(hij);
-        const float q = r * ih, u = 1.f - 0.5f * q;
-        float ihp = ih * ih * ih;
-        if constexpr (D == 3) ihp *= ih;
-        const float sj = pj.w * sp.inv_tau, sj2 = sj * sj;
-        const float etaij = 2.f * vi.w * vj.w / esum;
-        const float inv2 = invi + powd<D>(sj2);
-        // dW/dr / r = -5 alpha h^-(d+1) q (1 - q/2)^3 / r
-        const float s = -etaij * inv2 * sp.alpha * ihp * 5.f * q * u * u * u * rinv;
-        bx += s * (vi.x - vj.x);
-        by += s * (vi.y - vj.y);
-        if constexpr (D == 3) bz += s * (vi.z - vj.z);
-      });
+    if (ei > 0.f) {
+      scan_candidates<D, RecV>(
+          i, ci, oi, rs, g, cstart, [&](int j) { return RecV{wpos[j], wjaux[j], acc[j]}; },
+          [&](const RecV &rj, uint32_t drw, bool v) {
+            const float4 pj = rj.p;
+            const uint32_t aj = rj.a;
+            const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+            const float dy = row_dy(drw) + (oi[1] - pj.y);
+            float r2 = dx * dx + dy * dy;
+            if constexpr (D == 3) {
+              const float dz = row_dz(drw) + (oi[2] - pj.z);
+              r2 += dz * dz;
+            }
+            const float hij = kh * (hi + pj.w);
+            const bool apart = r2 > 1e-30f;
+            const bool use = v && apart && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti;
+#if MPSPH_BRANCHY
+            if (!use) return;
+#endif
+            const float rinv = fast_rsq(apart ? r2 : 1.f);
+            const float r = r2 * rinv;
+            const float ej = hdt * rj.acc.w;
+            const float esum = ei + ej;
+            const float etaij = 2.f * ei * ej * fast_rcp(esum > 0.f ? esum : 1.f);
+            const float ih = sp.kappa * fast_rcp(hij);
+            const float q = r * ih, uu = fmaf(-0.5f, q, 1.f);
+            const float ih2 = ih * ih;
+            const float ihp = D == 3 ? ih2 * ih2 : ih2 * ih;
+            const float sj = pj.w * sp.inv_tau;
+            const float inv2 = invi + powd<D>(sj * sj);
+            // dW/dr / r = -5 alpha h^-(d+1) q (1 - q/2)^3 / r
+            float s = -etaij * inv2 * (alpha5 * ihp * q * uu * uu * uu * rinv);
+            s = use ? s : 0.f;
+            bx = fmaf(s, vix - hdt * rj.acc.x, bx);
+            by = fmaf(s, viy - hdt * rj.acc.y, by);
+            if constexpr (D == 3) bz = fmaf(s, viz - hdt * rj.acc.z, bz);
+          });
     }
     float b[3] = {bx, by, bz};
     project_feature<D>(g, ti, ci, oi, b);
-    float dt2 = __uint_as_float(dtcells[1]);
-    if (!(dt2 < INFINITY)) dt2 = 0.f;
-    float v[3] = {vi.x + 0.5f * b[0] * dt2, vi.y + 0.5f * b[1] * dt2, vi.z + 0.5f * b[2] * dt2};
+    float v[3] = {vix + 0.5f * b[0] * dt2, viy + 0.5f * b[1] * dt2, viz + 0.5f * b[2] * dt2};
     if (ti == 3) v[0] = v[1] = v[2] = 0.f;
     float dr[3] = {v[0] * dt2, v[1] * dt2, v[2] * dt2};
     float ke = 0.f;
 #pragma unroll
     for (int a = 0; a < D; ++a) ke += 0.5f * v[a] * v[a];
-    bool fin = isfinite(b[0]) && isfinite(b[1]) && isfinite(b[2]) && isfinite(dr[0]) && isfinite(dr[1]) &&
-               isfinite(dr[2]);
+    const bool fin = isfinite(b[0]) && isfinite(b[1]) && isfinite(b[2]) && isfinite(dr[0]) && isfinite(dr[1]) &&
+                     isfinite(dr[2]);
     // drift in (cell, offset) form with carry
     int c[3] = {ci[0], ci[1], D == 3 ? ci[2] : 0};
     float o[3] = {oi[0], oi[1], D == 3 ? oi[2] : 0.f};
     if (ti != 3 && fin) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        float x = o[a] + dr[a];
-        float fl = floorf(x);
+        const float x = o[a] + dr[a];
+        const float fl = floorf(x);
         c[a] += (int)fl;
         o[a] = x - fl;
         if (o[a] >= 1.f) {
@@ -446,14 +528,6 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
               o[a] = 0.f;
               c[a] += 1;
             }
-            if (c[a] < 0) {
-              c[a] = 0;
-              o[a] = 0.f;
-            }
-            if (c[a] > g.gmax) {
-              c[a] = g.gmax;
-              o[a] = 0.f;
-            }
           }
           ti = max(ti, 1);
         }
@@ -486,39 +560,46 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
   block_reduce_write<4>(part, ops, partials + (size_t)lb * kNumPartials + P_KE);
 }
 
-// Reduce the per-block partials in a fixed order into the metrics block:
-//   m[0..]: e2, emax, nnorm, elr, elr2, elrmin, elrmax, nelr, pairs, ifc, cand, nonfin1, ke,
-//   nonfin2, nfeat, spare, then dt1, dt2 (as stored, +inf -> 0).
+// Reduce the per-block partials in a fixed order into the metrics block: slots 0..15 as laid
+// out in kNumPartials, then 16: dt1, 17: dt2, 18..20: running totals of pairs, candidates,
+// steps.  Thread t owns blocks t, t+256, ... (fixed order), then a fixed tree over threads.
 __global__ __launch_bounds__(256) void finalize(int nblocks, const double *__restrict__ partials,
-                                                const uint32_t *__restrict__ dtcells, double *__restrict__ m) {
-  __shared__ double red[256];
-  for (int s = 0; s < kNumPartials; ++s) {
-    const int op = (s == P_EMAX || s == P_ELRMAX) ? 2 : (s == P_ELRMIN ? 1 : 0);
-    double x = op == 1 ? INFINITY : 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += 256) {
-      double y = partials[(size_t)b * kNumPartials + s];
-      x = op == 0 ? x + y : (op == 1 ? fmin(x, y) : fmax(x, y));
+                                                const uint32_t *__restrict__ dtslots, float dt2_factor,
+                                                double *__restrict__ m) {
+  __shared__ double red[kNumPartials][257];
+  double acc[kNumPartials];
+#pragma unroll
+  for (int s = 0; s < kNumPartials; ++s) acc[s] = s == P_ELRMIN ? INFINITY : 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+    const double *p = partials + (size_t)b * kNumPartials;
+#pragma unroll
+    for (int s = 0; s < kNumPartials; ++s) {
+      const double y = p[s];
+      acc[s] = (s == P_EMAX || s == P_ELRMAX) ? fmax(acc[s], y) : (s == P_ELRMIN ? fmin(acc[s], y) : acc[s] + y);
     }
-    red[threadIdx.x] = x;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) {
-        double y = red[threadIdx.x + w];
-        double z = red[threadIdx.x];
-        red[threadIdx.x] = op == 0 ? z + y : (op == 1 ? fmin(z, y) : fmax(z, y));
+  }
+#pragma unroll
+  for (int s = 0; s < kNumPartials; ++s) red[s][threadIdx.x] = acc[s];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int s = 0; s < kNumPartials; ++s) {
+        const double y = red[s][threadIdx.x + w], z = red[s][threadIdx.x];
+        red[s][threadIdx.x] = (s == P_EMAX || s == P_ELRMAX) ? fmax(z, y) : (s == P_ELRMIN ? fmin(z, y) : z + y);
       }
-      __syncthreads();
     }
-    if (threadIdx.x == 0) m[s] = red[0];
     __syncthreads();
   }
+  if (threadIdx.x < kNumPartials) m[threadIdx.x] = red[threadIdx.x][0];
   if (threadIdx.x == 0) {
-    float d1 = __uint_as_float(dtcells[0]), d2 = __uint_as_float(dtcells[1]);
+    float d1 = INFINITY;
+    for (int s = 0; s < kDtSlots; ++s) d1 = fminf(d1, __uint_as_float(dtslots[s]));
     m[16] = d1 < INFINITY ? (double)d1 : 0.0;
-    m[17] = d2 < INFINITY ? (double)d2 : 0.0;
+    m[17] = d1 < INFINITY ? (double)(d1 * dt2_factor) : 0.0;
     // running totals since the last load (exact integers below 2^53)
-    m[18] += m[P_PAIRS];
-    m[19] += m[P_CAND];
+    m[18] += red[P_PAIRS][0];
+    m[19] += red[P_CAND][0];
     m[20] += 1.0;
   }
 }
@@ -548,8 +629,8 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void dump_kernel(int n, int which, int k, uint32_t mask, double lo0, double lo1,
                                                       double lo2, double cs, float tau, const uint32_t *__restrict__ wkey,
                                                       const float4 *__restrict__ wpos, const uint32_t *__restrict__ wid,
-                                                      const float *__restrict__ rho, const float *__restrict__ nn,
-                                                      const float4 *__restrict__ vec, float *__restrict__ out) {
+                                                      const float *__restrict__ sc, const float4 *__restrict__ vec,
+                                                      float vscale, float *__restrict__ out) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const uint32_t id = wid[i];
@@ -557,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void dump_kernel(int n, int which, int k, u
   const double csd = cs;
   switch (which) {
     case MPSPH_F_RHO:
-      out[id] = (float)((double)rho[i] / pow(csd, D));
+      out[id] = (float)((double)sc[i] / pow(csd, D));
       break;
     case MPSPH_F_RHO_T: {
       double s = (double)p.w / tau * csd;
@@ -568,10 +649,8 @@ __global__ __launch_bounds__(kBlock) void dump_kernel(int n, int which, int k, u
       out[id] = (float)((double)p.w * csd);
       break;
     case MPSPH_F_NN:
-      out[id] = (float)((double)nn[i] * csd);
-      break;
     case MPSPH_F_A_ABS:
-      out[id] = (float)((double)vec[i].w * csd);
+      out[id] = (float)((double)sc[i] * csd);
       break;
     case MPSPH_F_X0: {
       int c[3];
@@ -581,10 +660,10 @@ __global__ __launch_bounds__(kBlock) void dump_kernel(int n, int which, int k, u
       for (int a = 0; a < D; ++a) out[(size_t)id * D + a] = (float)(lo[a] + ((double)c[a] + (double)oo[a]) * csd);
       break;
     }
-    default: {  // vector quantities in cell units per time: scale by cs
+    default: {  // vector quantities in cell units per time: scale by cs (and vscale)
       const float4 v = vec[i];
       const float vv[3] = {v.x, v.y, v.z};
-      for (int a = 0; a < D; ++a) out[(size_t)id * D + a] = (float)((double)vv[a] * csd);
+      for (int a = 0; a < D; ++a) out[(size_t)id * D + a] = (float)((double)(vv[a] * vscale) * csd);
     }
   }
 }
@@ -602,7 +681,7 @@ struct Layout {
   int nblocks = 0;
   size_t bytes = 0;
   // offsets
-  size_t s_key, s_off, s_ct, s_id, w_key, w_pos, w_jaux, w_id, k0, v0, k1, v1, hist, cstart, acc, rho, nn, vt, at, v,
+  size_t s_key, s_off, s_ct, s_id, w_key, w_pos, w_jaux, w_id, k0, v0, k1, v1, hist, cstart, acc, rho, nn, aabs, at, v,
       dr, partials, metrics, dtcells, bad, rbf_c, rbf_o, rbf_k;
 };
 
@@ -867,13 +946,13 @@ Layout make_layout(int dim, int k, int64_t n, int n_rbf) {
   L.acc = take(nn * 16);
   L.rho = take(nn * 4);
   L.nn = take(nn * 4);
-  L.vt = take(nn * 16);
+  L.aabs = take(nn * 4);
   L.at = take(nn * 16);
   L.v = take(nn * 16);
   L.dr = take(nn * 16);
   L.partials = take((size_t)L.nblocks * kNumPartials * 8);
   L.metrics = take(32 * 8);
-  L.dtcells = take(2 * 4);
+  L.dtcells = take(kDtSlots * 4);
   L.bad = take(4);
   L.rbf_c = take((size_t)std::max(n_rbf, 1) * 3 * 4);
   L.rbf_o = take((size_t)std::max(n_rbf, 1) * 3 * 4);
@@ -1001,6 +1080,16 @@ double sigma_at(const mpsph_params *p, int64_t step) {
   return 0.0;
 }
 
+// dt2 / dt1: with the velocity reset, v~ = a dt1 / 2 (Eq. 26) and nu = nu_coeff r_c |v~| (Eq. 21),
+// so the three criteria of Eq. 29 are c_acc sqrt(m), (2 c_vel / dt1) m and
+// (2 c_visc / (nu_coeff dt1)) m in m = r_c / |a|; their minima over the particles are reached at
+// the same m = (dt1 / c_acc)^2, which gives dt2 = dt1 min(1, 2 min(c_vel, c_visc/nu_coeff) / c_acc^2).
+double dt2_factor(const mpsph_params *p) {
+  double c = p->c_vel;
+  if (p->nu_coeff > 0) c = std::min(c, p->c_visc / p->nu_coeff);
+  return std::min(1.0, 2.0 * c / (p->c_acc * p->c_acc));
+}
+
 template <int D>
 int run_steps(mpsph_ctx *ctx, int nsteps) {
   const int n = (int)ctx->L.n;
@@ -1020,6 +1109,7 @@ int run_steps(mpsph_ctx *ctx, int nsteps) {
   sp.search_fac = (float)ctx->d.search_fac;
   sp.hmax = (float)(ctx->p.tau * ctx->d.smax / cs * (1.0 + 1e-5));
   sp.alpha = (float)(D == 2 ? 7.0 / (4.0 * M_PI) : 21.0 / (16.0 * M_PI));
+  sp.dt2_factor = (float)dt2_factor(&ctx->p);
   const bool dbg = ctx->p.debug != 0;
   EventHook *hk = ctx->hook.on ? &ctx->hook : nullptr;
   for (int s = 0; s < nsteps; ++s) {
@@ -1040,25 +1130,22 @@ int run_steps(mpsph_ctx *ctx, int nsteps) {
       if (hk) hk->begin("pass_density_force");
       pass_density_force<D><<<nb, kBlock, 0, st>>>(
           n, ctx->g, sp, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
-          ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc), ctx->at<float>(L.rho), dbg ? ctx->at<float>(L.nn) : nullptr,
+          ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc), dbg ? ctx->at<float>(L.rho) : nullptr,
+          dbg ? ctx->at<float>(L.nn) : nullptr, dbg ? ctx->at<float>(L.aabs) : nullptr,
           ctx->at<uint32_t>(L.dtcells), ctx->at<double>(L.partials));
-      if (hk) hk->end();
-      if (hk) hk->begin("kick");
-      kick<D><<<nb, kBlock, 0, st>>>(n, sp, ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
-                                     ctx->at<float4>(L.acc), ctx->at<float4>(L.vt), ctx->at<uint32_t>(L.dtcells));
       if (hk) hk->end();
       if (hk) hk->begin("pass_viscous_integrate");
       pass_viscous_integrate<D><<<nb, kBlock, 0, st>>>(
           n, ctx->g, sp, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
-          ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.vt), ctx->at<uint32_t>(L.dtcells),
-          ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id),
-          dbg ? ctx->at<float4>(L.at) : nullptr, dbg ? ctx->at<float4>(L.v) : nullptr, dbg ? ctx->at<float4>(L.dr) : nullptr,
-          ctx->at<double>(L.partials));
+          ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
+          ctx->at<uint32_t>(L.dtcells), ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off),
+          ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), dbg ? ctx->at<float4>(L.at) : nullptr,
+          dbg ? ctx->at<float4>(L.v) : nullptr, dbg ? ctx->at<float4>(L.dr) : nullptr, ctx->at<double>(L.partials));
       if (hk) hk->end();
     }
     if (hk) hk->begin("finalize");
     finalize<<<1, 256, 0, st>>>(n > 0 ? nb : 0, ctx->at<double>(L.partials), ctx->at<uint32_t>(L.dtcells),
-                                ctx->at<double>(L.metrics));
+                                sp.dt2_factor, ctx->at<double>(L.metrics));
     if (hk) hk->end();
     if (hipGetLastError() != hipSuccess) return fail(ctx, MPSPH_E_DEVICE);
     ctx->steps_done += 1;
@@ -1288,21 +1375,32 @@ int mpsph_store(mpsph_ctx *ctx, float *d_pos, int32_t *d_type) {
 int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out) {
   if (!ctx || !d_out || which < 0 || which > MPSPH_F_X0) return MPSPH_E_INVALID;
   if (ctx->poisoned || !ctx->loaded || ctx->steps_done == 0) return MPSPH_E_STATE;
-  if ((which == MPSPH_F_V || which == MPSPH_F_DR || which == MPSPH_F_AT || which == MPSPH_F_NN) && !ctx->p.debug)
-    return MPSPH_E_STATE;
+  const bool needs_debug = which == MPSPH_F_RHO || which == MPSPH_F_A_ABS || which == MPSPH_F_AT ||
+                           which == MPSPH_F_V || which == MPSPH_F_DR || which == MPSPH_F_NN;
+  if (needs_debug && !ctx->p.debug) return MPSPH_E_STATE;
   const int n = (int)ctx->L.n;
   const Layout &L = ctx->L;
   const float4 *vec = ctx->at<float4>(L.acc);
-  if (which == MPSPH_F_VT) vec = ctx->at<float4>(L.vt);
+  const float *sc = ctx->at<float>(L.rho);
+  float vscale = 1.f;
+  if (which == MPSPH_F_NN) sc = ctx->at<float>(L.nn);
+  if (which == MPSPH_F_A_ABS) sc = ctx->at<float>(L.aabs);
   if (which == MPSPH_F_AT) vec = ctx->at<float4>(L.at);
   if (which == MPSPH_F_V) vec = ctx->at<float4>(L.v);
   if (which == MPSPH_F_DR) vec = ctx->at<float4>(L.dr);
+  if (which == MPSPH_F_VT) {
+    // v~ = a dt1 / 2 (Eq. 26 after the velocity reset); fixed particles carry a = 0
+    double m[17];
+    HIP_OK(hipMemcpyAsync(m, ctx->at<double>(L.metrics), sizeof(m), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    vscale = (float)(0.5 * m[16]);
+  }
   if (n > 0) {
     auto kern = ctx->p.dim == 2 ? dump_kernel<2> : dump_kernel<3>;
     kern<<<(n + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
         n, which, ctx->d.k, (uint32_t)ctx->d.gmax, ctx->d.lo[0], ctx->d.lo[1], ctx->d.lo[2], ctx->d.cs,
-        (float)ctx->p.tau, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_id),
-        ctx->at<float>(L.rho), ctx->at<float>(L.nn), vec, d_out);
+        (float)ctx->p.tau, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_id), sc, vec,
+        vscale, d_out);
     HIP_OK(hipGetLastError());
   }
   HIP_OK(hipStreamSynchronize(ctx->stream));

@@ -9,6 +9,7 @@ constexpr int kBlock = 256;       // threads per block of the particle kernels (
 constexpr int kWave = 64;
 constexpr int kNumPartials = 16;  // FP64 partial slots per block
 constexpr uint32_t kInfBits = 0x7f800000u;
+constexpr int kDtSlots = 64;      // words over which the first time-step minimum is spread
 
 // Slots of the per-block FP64 partials.
 enum : int {
@@ -69,6 +70,7 @@ struct StepDev {
   float search_fac;  // neighbour search radius bound: search_fac * h_i
   float hmax;        // upper bound of h over the region (cell units)
   float alpha;       // kernel normalisation alpha_d
+  float dt2_factor;  // dt2 / dt1 implied by Eq. 29 after the velocity reset
 };
 
 __device__ __forceinline__ int xcd_block(int b, int nb) {

@@ -13,8 +13,16 @@ def short_name(n: str) -> str:
     return head.split("::")[-1] if "::" in head and "<" not in head else head.replace("mpsph::", "")
 
 
-def kernel_rows(db: str):
-    con = sqlite3.connect(db)
+def kernel_rows(path: str):
+    """(name, calls, total us, average us, percent) from a rocpd database or a kernel_stats.csv."""
+    if path.endswith(".csv"):
+        import csv
+        rows = []
+        for r in csv.DictReader(open(path)):
+            rows.append((short_name(r["Name"]), int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
+                         float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+        return rows
+    con = sqlite3.connect(path)
     return [(short_name(n), c, t, a, p) for n, c, t, a, p in
             con.execute("select name,total_calls,total_duration,average,percentage from top_kernels")]
 
