@@ -115,36 +115,31 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
   wid[i] = sid[s];
 }
 
-// Neighbour candidates of particle i.  Every x-run of cells (fixed y, z) that intersects the ball
-// of radius rs around the particle is one contiguous range of the sorted arrays.  Rows are taken
-// four at a time (their eight cell-table reads in flight together) and the candidates of the
-// four rows are visited as one flat sequence, four per iteration with all loads issued first.
-// load(j) fetches the record of particle j; body(rec, drow, valid) consumes it, where drow packs
-// the integer row offsets (ci[1] - cy) in the low and (ci[2] - cz) in the high 16 bits.
-// Tuning of the candidate scan (measured on the 2M-particle graded cube: one row at a time,
-// one candidate per iteration, with a branch around the pair arithmetic is fastest).
-#ifndef MPSPH_ROWS_G
-#define MPSPH_ROWS_G 1
-#endif
-#ifndef MPSPH_BATCH_U
-#define MPSPH_BATCH_U 1
-#endif
-#ifndef MPSPH_BRANCHY
-#define MPSPH_BRANCHY 1
-#endif
-#ifndef MPSPH_WAVES_PER_EU
-#define MPSPH_WAVES_PER_EU 0
-#endif
-#if MPSPH_WAVES_PER_EU > 0
-#define PAIR_KERNEL_ATTR __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MPSPH_WAVES_PER_EU, 8)))
-#else
-#define PAIR_KERNEL_ATTR __launch_bounds__(kBlock)
+// ------------------------------------------------------------------------------------------
+// Neighbour candidates
+//
+// Particle i's candidates are the particles of every x-run of cells (fixed y, z) that meets the
+// ball of radius rs around it; in the row-major cell order each run is one contiguous range of
+// the sorted arrays.  A group of L lanes works on one particle: the L lanes take L rows at a
+// time (each reads its row's range from the cell table), form the prefix sum of the run lengths,
+// and then visit the flattened candidates of those rows L at a time, lane l taking every L-th
+// one (its row is found by a binary search over the prefix sums with cross-lane reads).  All
+// lanes of a wave thus run the same loop trip counts whatever the run lengths are.
+// body(j, drow, valid) is called for every slot; drow packs the row offsets (ci[1] - cy) in the
+// low and (ci[2] - cz) in the high 16 bits; invalid slots carry j = i.
+// ------------------------------------------------------------------------------------------
+// Lanes per particle in the pair kernels (measured on the 2M-particle graded cube: 4 is the
+// fastest of 1, 2, 4, 8, 16, 32).
+#ifndef MPSPH_LANES
+#define MPSPH_LANES 4
 #endif
 
-template <int D, typename Rec, typename LoadF, typename BodyF>
-__device__ __forceinline__ void scan_candidates(int i, const int *ci, const float *oi, float rs, const GridDev &g,
-                                                const uint32_t *__restrict__ cstart, LoadF &&load, BodyF &&body) {
-  constexpr int G = MPSPH_ROWS_G, U = MPSPH_BATCH_U;
+__device__ __forceinline__ float row_dy(uint32_t dr) { return (float)(int)(int16_t)(dr & 0xffffu); }
+__device__ __forceinline__ float row_dz(uint32_t dr) { return (float)((int)dr >> 16); }
+
+template <int D, int L, typename BodyF>
+__device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, const float *oi, float rs,
+                                               const GridDev &g, const uint32_t *__restrict__ cstart, BodyF &&body) {
   // a finite, non-negative radius keeps every cell range inside [0, gmax] (NaN -> 0)
   rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
   const float rs2 = rs * rs;
@@ -152,91 +147,81 @@ __device__ __forceinline__ void scan_candidates(int i, const int *ci, const floa
   const int z1 = D == 3 ? min(g.gmax, ci[2] + (int)floorf(oi[2] + rs)) : 0;
   const int y0 = max(0, ci[1] + (int)floorf(oi[1] - rs));
   const int y1 = min(g.gmax, ci[1] + (int)floorf(oi[1] + rs));
+  const int ny = y1 - y0 + 1;
+  const int nrows = ny * (z1 - z0 + 1);
+  const float inv_ny = 1.f / (float)ny;
   const uint32_t nmax = (uint32_t)g.n;
-  int cy = y0, cz = z0;
-  while (cz <= z1) {
-    uint32_t off[G], P[G + 1];
-    uint32_t drow[G], klo[G], khi[G];
-    bool hit[G];
-#pragma unroll
-    for (int t = 0; t < G; ++t) {
-      const bool live = cz <= z1;
-      float ez = 0.f;
-      if constexpr (D == 3) {
-        const float lo = (float)(cz - ci[2]) - oi[2], hi = lo + 1.f;
-        ez = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
-      }
-      const float lo = (float)(cy - ci[1]) - oi[1], hi = lo + 1.f;
-      const float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
-      const float d2 = ey * ey + ez * ez;
-      hit[t] = live && d2 < rs2;
-      const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
-      const int x0 = max(0, ci[0] + (int)floorf(oi[0] - wx));
-      const int x1 = min(g.gmax, ci[0] + (int)floorf(oi[0] + wx));
-      uint32_t kb = (uint32_t)x0 | ((uint32_t)cy << g.k);
-      if constexpr (D == 3) kb |= (uint32_t)cz << (2 * g.k);
-      klo[t] = hit[t] ? kb : 0u;
-      khi[t] = hit[t] ? kb + (uint32_t)(x1 - x0) + 1u : 0u;
-      drow[t] = ((uint32_t)(ci[1] - cy) & 0xffffu) | ((uint32_t)(D == 3 ? ci[2] - cz : 0) << 16);
-      if (live && ++cy > y1) {
-        cy = y0;
-        ++cz;
-      }
+  uint32_t ncand = 0;
+  for (int q0 = 0; q0 < nrows; q0 += L) {
+    const int q = q0 + sub;
+    const int qz = (int)(((float)q + 0.5f) * inv_ny);   // q / ny (q, ny < 2^12)
+    const int cz = z0 + qz, cy = y0 + (q - qz * ny);
+    float ez = 0.f;
+    if constexpr (D == 3) {
+      const float lo = (float)(cz - ci[2]) - oi[2], hi = lo + 1.f;
+      ez = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
     }
-    // all cell-table reads of the group in flight together
-    uint32_t ja[G], jb[G];
-#pragma unroll
-    for (int t = 0; t < G; ++t) {
-      ja[t] = cstart[klo[t]];
-      jb[t] = cstart[khi[t]];
+    const float lo = (float)(cy - ci[1]) - oi[1], hi = lo + 1.f;
+    const float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
+    const float d2 = ey * ey + ez * ez;
+    const bool hit = q < nrows && d2 < rs2;
+    const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
+    const int x0 = max(0, ci[0] + (int)floorf(oi[0] - wx));
+    const int x1 = min(g.gmax, ci[0] + (int)floorf(oi[0] + wx));
+    uint32_t kb = (uint32_t)x0 | ((uint32_t)cy << g.k);
+    if constexpr (D == 3) kb |= (uint32_t)cz << (2 * g.k);
+    uint32_t a = 0u, b = 0u;
+    if (hit) {
+      a = cstart[kb];
+      b = min(cstart[kb + (uint32_t)(x1 - x0) + 1u], nmax);
     }
-    P[0] = 0u;
+    const uint32_t len = b > a ? b - a : 0u;
+    const uint32_t drow = ((uint32_t)(ci[1] - cy) & 0xffffu) | ((uint32_t)(D == 3 ? ci[2] - cz : 0) << 16);
+    uint32_t incl = len;
 #pragma unroll
-    for (int t = 0; t < G; ++t) {
-      const uint32_t b = min(jb[t], nmax);
-      const uint32_t len = (hit[t] && b > ja[t]) ? b - ja[t] : 0u;
-      off[t] = ja[t] - P[t];
-      P[t + 1] = P[t] + len;
+    for (int o = 1; o < L; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, L);
+      if (sub >= o) incl += v;
     }
-    const uint32_t T = P[G];
-    for (uint32_t s = 0; s < T; s += U) {
-      Rec rec[U];
-      uint32_t dr[U];
-      bool val[U];
+    const uint32_t T = __shfl(incl, L - 1, L);
+    const uint32_t excl = incl - len;
+    for (uint32_t t0 = 0; t0 < T; t0 += L) {
+      const uint32_t t = t0 + (uint32_t)sub;
+      int r = 0;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t t = s + (uint32_t)u;
-        uint32_t o = off[0];
-        dr[u] = drow[0];
-#pragma unroll
-        for (int q = 1; q < G; ++q) {
-          const bool c = t >= P[q];
-          o = c ? off[q] : o;
-          dr[u] = c ? drow[q] : dr[u];
-        }
-        const uint32_t j = o + t;
-        const bool v = t < T && j != (uint32_t)i;
-        val[u] = v;
-        rec[u] = load(v ? (int)j : i);
+      for (int step = L / 2; step > 0; step >>= 1) {
+        const uint32_t v = __shfl(incl, r + step - 1, L);
+        if (v <= t) r += step;
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u) body(rec[u], dr[u], val[u]);
+      const uint32_t ar = __shfl(a, r, L), er = __shfl(excl, r, L), dr = __shfl(drow, r, L);
+      const uint32_t j = ar + (t - er);
+      const bool valid = t < T && (int)j != i;
+      ncand += valid ? 1u : 0u;
+      body(valid ? (int)j : i, dr, valid);
     }
   }
+  return ncand;
 }
 
-struct RecP {
-  float4 p;
-  uint32_t a;
-};
-struct RecV {
-  float4 p;
-  uint32_t a;
-  float4 acc;
-};
-
-__device__ __forceinline__ float row_dy(uint32_t dr) { return (float)(int)(int16_t)(dr & 0xffffu); }
-__device__ __forceinline__ float row_dz(uint32_t dr) { return (float)((int)dr >> 16); }
+// Sum / minimum across the L lanes of a group (fixed butterfly order).
+template <int L>
+__device__ __forceinline__ float group_sum(float x) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, L);
+  return x;
+}
+template <int L>
+__device__ __forceinline__ uint32_t group_sum_u(uint32_t x) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, L);
+  return x;
+}
+template <int L>
+__device__ __forceinline__ float group_min(float x) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, L));
+  return x;
+}
 
 // Minimum of the first time step: one atomic per block, spread over kDtSlots words.
 __device__ __forceinline__ void block_min_to_slots(float v, int lb, uint32_t *slots) {
@@ -264,14 +249,16 @@ __device__ __forceinline__ float read_dt1(const uint32_t *slots) {
 // P = p0 / rho_t^2, h_ij = (h_i + h_j)/2, over j with r_ij < kappa h_ij that particle i feels.
 // Writes acc = (a after the force mapping of Eq. 30-31, e_i) with e_i = rho_t nu_coeff r_c |a_i|,
 // the viscosity of Eq. 21-22 per unit of dt1/2, and the first time-step candidate (Eq. 29).
-template <int D>
-__global__ PAIR_KERNEL_ATTR void pass_density_force(
+// L lanes per particle (group); lane 0 of the group writes the particle's results.
+template <int D, int L>
+__global__ __launch_bounds__(kBlock) void pass_density_force(
     int n, GridDev g, StepDev sp, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
     const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ cstart, float4 *__restrict__ acc,
     float *__restrict__ rho_out, float *__restrict__ nn_out, float *__restrict__ aabs_out,
     uint32_t *__restrict__ dtslots, double *__restrict__ partials) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int i = lb * kBlock + threadIdx.x;
+  const int gid = lb * kBlock + threadIdx.x;
+  const int i = gid / L, sub = gid % L;
   const bool active = i < n;
   double part[12];
   const int ops[12] = {0, 2, 0, 0, 0, 1, 2, 0, 0, 0, 0, 0};
@@ -297,84 +284,90 @@ __global__ PAIR_KERNEL_ATTR void pass_density_force(
     const float alpha5 = 5.f * sp.alpha;
     const float opb = 1.f + sp.sigma;
     float wsum = 0.f, ax = 0.f, ay = 0.f, az = 0.f, A = 0.f, nn2 = INFINITY;
-    uint32_t npair = 0, nifc = 0, ncand = 0;
-    scan_candidates<D, RecP>(
-        i, ci, oi, rs, g, cstart, [&](int j) { return RecP{wpos[j], wjaux[j]}; },
-        [&](const RecP &rj, uint32_t drw, bool v) {
-          const float4 pj = rj.p;
-          const uint32_t aj = rj.a;
-          const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
-          const float dy = row_dy(drw) + (oi[1] - pj.y);
-          float r2 = dx * dx + dy * dy;
-          float dz = 0.f;
-          if constexpr (D == 3) {
-            dz = row_dz(drw) + (oi[2] - pj.z);
-            r2 += dz * dz;
-          }
-          ncand += v ? 1u : 0u;
-          const float hij = kh * (hi + pj.w);           // kappa h_ij
-          const bool dens = v && r2 < rci2;
-          const bool inter = v && r2 < hij * hij;
-          // coincident particles (two particles clamped into one corner): r = 0, no direction
-          const bool apart = r2 > 1e-30f;
-          const float rinv = fast_rsq(apart ? r2 : 1.f);
-          const float r = apart ? r2 * rinv : 0.f;
-          const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
-          wsum += dens ? u2 * u2 * fmaf(2.f, q, 1.f) : 0.f;
-          const uint32_t colj = aj >> 14;
-          const bool diff = colj != coli;
-          const bool feel = inter && (int)((aj >> 12) & 3) >= ti;
-          nifc += (inter && diff) ? 1u : 0u;
-          npair += feel ? 1u : 0u;
-          nn2 = inter ? fminf(nn2, r2) : nn2;
-#if MPSPH_BRANCHY
-          if (!(feel && apart)) return;
-#endif
-          const float ih = sp.kappa * fast_rcp(hij);    // 1 / h_ij
-          const float q2 = r * ih, uu = fmaf(-0.5f, q2, 1.f);
-          const float ih2 = ih * ih;
-          const float ihp = D == 3 ? ih2 * ih2 : ih2 * ih;  // h_ij^-(d+1)
-          const float sj = pj.w * sp.inv_tau;
-          const float Pj = sp.p0c * powd<D>(sj * sj);
-          // -dW/dr = alpha h^-(d+1) 5 q (1 - q/2)^3 >= 0
-          float s = (diff ? opb : 1.f) * (Pi + Pj) * (alpha5 * ihp * q2 * uu * uu * uu * rinv);
-          s = (feel && apart) ? s : 0.f;
-          ax = fmaf(s, dx, ax);
-          ay = fmaf(s, dy, ay);
-          az = fmaf(s, dz, az);
-          A = fmaf(s, r, A);
-        });
-    const float ihd = D == 3 ? ihi * ihi * ihi : ihi * ihi;
-    const float rho = sp.alpha * ihd * (1.f + wsum);
-    float a[3] = {ax, ay, az};
-    project_feature<D>(g, ti, ci, oi, a);
-    const float am2 = a[0] * a[0] + a[1] * a[1] + (D == 3 ? a[2] * a[2] : 0.f);
-    const float am = sqrtf(am2);
-    const float ehat = sp.nu_coeff * rci * am / powd<D>(si);  // rho_t nu_coeff r_c |a|
-    acc[i] = make_float4(a[0], a[1], D == 3 ? a[2] : 0.f, ehat);
-    if (rho_out) rho_out[i] = rho;
-    if (nn_out) nn_out[i] = sqrtf(nn2);
-    if (aabs_out) aabs_out[i] = A;
-    if (ti != 3 && am2 > 0.f) dtc = sp.c_acc * sqrtf(rci * fast_rsq(am2));
-    const bool fin = isfinite(am2) && isfinite(rho);
-    if (ti == 0) {
-      const double e = (double)(rho * powd<D>(si)) - 1.0;   // rho / rho_t - 1
-      part[0] = e * e;
-      part[1] = fabs(e);
-      part[2] = 1.0;
-      if (nn2 < INFINITY) {
-        const double elr = (double)sqrtf(nn2) / (double)si;
-        part[3] = elr;
-        part[4] = elr * elr;
-        part[5] = elr;
-        part[6] = elr;
-        part[7] = 1.0;
+    uint32_t npair = 0, nifc = 0;
+    uint32_t ncand = scan_group<D, L>(i, sub, ci, oi, rs, g, cstart, [&](int j, uint32_t drw, bool v) {
+      const float4 pj = wpos[j];
+      const uint32_t aj = wjaux[j];
+      const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+      const float dy = row_dy(drw) + (oi[1] - pj.y);
+      float r2 = dx * dx + dy * dy;
+      float dz = 0.f;
+      if constexpr (D == 3) {
+        dz = row_dz(drw) + (oi[2] - pj.z);
+        r2 += dz * dz;
       }
+      const float hij = kh * (hi + pj.w);           // kappa h_ij
+      const bool dens = v && r2 < rci2;
+      const bool inter = v && r2 < hij * hij;
+      if (!(dens || inter)) return;
+      // coincident particles (two particles clamped into one corner): r = 0, no direction
+      const bool apart = r2 > 1e-30f;
+      const float rinv = fast_rsq(apart ? r2 : 1.f);
+      const float r = apart ? r2 * rinv : 0.f;
+      const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
+      wsum += dens ? u2 * u2 * fmaf(2.f, q, 1.f) : 0.f;
+      const uint32_t colj = aj >> 14;
+      const bool diff = colj != coli;
+      const bool feel = inter && (int)((aj >> 12) & 3) >= ti;
+      nifc += (inter && diff) ? 1u : 0u;
+      npair += feel ? 1u : 0u;
+      nn2 = inter ? fminf(nn2, r2) : nn2;
+      if (!(feel && apart)) return;
+      const float ih = sp.kappa * fast_rcp(hij);    // 1 / h_ij
+      const float q2 = r * ih, uu = fmaf(-0.5f, q2, 1.f);
+      const float ih2 = ih * ih;
+      const float ihp = D == 3 ? ih2 * ih2 : ih2 * ih;  // h_ij^-(d+1)
+      const float sj = pj.w * sp.inv_tau;
+      const float Pj = sp.p0c * powd<D>(sj * sj);
+      // -dW/dr = alpha h^-(d+1) 5 q (1 - q/2)^3 >= 0
+      const float s = (diff ? opb : 1.f) * (Pi + Pj) * (alpha5 * ihp * q2 * uu * uu * uu * rinv);
+      ax = fmaf(s, dx, ax);
+      ay = fmaf(s, dy, ay);
+      az = fmaf(s, dz, az);
+      A = fmaf(s, r, A);
+    });
+    wsum = group_sum<L>(wsum);
+    ax = group_sum<L>(ax);
+    ay = group_sum<L>(ay);
+    if constexpr (D == 3) az = group_sum<L>(az);
+    if (aabs_out) A = group_sum<L>(A);
+    nn2 = group_min<L>(nn2);
+    npair = group_sum_u<L>(npair);
+    nifc = group_sum_u<L>(nifc);
+    ncand = group_sum_u<L>(ncand);
+    if (sub == 0) {
+      const float ihd = D == 3 ? ihi * ihi * ihi : ihi * ihi;
+      const float rho = sp.alpha * ihd * (1.f + wsum);
+      float a[3] = {ax, ay, az};
+      project_feature<D>(g, ti, ci, oi, a);
+      const float am2 = a[0] * a[0] + a[1] * a[1] + (D == 3 ? a[2] * a[2] : 0.f);
+      const float am = sqrtf(am2);
+      const float ehat = sp.nu_coeff * rci * am / powd<D>(si);  // rho_t nu_coeff r_c |a|
+      acc[i] = make_float4(a[0], a[1], D == 3 ? a[2] : 0.f, ehat);
+      if (rho_out) rho_out[i] = rho;
+      if (nn_out) nn_out[i] = sqrtf(nn2);
+      if (aabs_out) aabs_out[i] = A;
+      if (ti != 3 && am2 > 0.f) dtc = sp.c_acc * sqrtf(rci * fast_rsq(am2));
+      const bool fin = isfinite(am2) && isfinite(rho);
+      if (ti == 0) {
+        const double e = (double)(rho * powd<D>(si)) - 1.0;   // rho / rho_t - 1
+        part[0] = e * e;
+        part[1] = fabs(e);
+        part[2] = 1.0;
+        if (nn2 < INFINITY) {
+          const double elr = (double)sqrtf(nn2) / (double)si;
+          part[3] = elr;
+          part[4] = elr * elr;
+          part[5] = elr;
+          part[6] = elr;
+          part[7] = 1.0;
+        }
+      }
+      part[8] = (double)npair;
+      part[9] = (double)nifc;
+      part[10] = (double)ncand;
+      part[11] = fin ? 0.0 : 1.0;
     }
-    part[8] = (double)npair;
-    part[9] = (double)nifc;
-    part[10] = (double)ncand;
-    part[11] = fin ? 0.0 : 1.0;
   }
   block_min_to_slots(dtc, lb, dtslots);
   block_reduce_write<12>(part, ops, partials + (size_t)lb * kNumPartials);
@@ -393,15 +386,16 @@ __device__ __forceinline__ int type_from_faces(int nf, int d) {
 // feature projection / re-tagging (Eq. 32); the new state is written in this step's order.
 // With v~ = a dt1/2 the three criteria of Eq. 29 are increasing functions of r_c/|a| and give
 // dt2 = dt1 min(1, 2 min(c_vel, c_visc / nu_coeff) / c_acc^2) (sp.dt2_factor).
-template <int D>
-__global__ PAIR_KERNEL_ATTR void pass_viscous_integrate(
+template <int D, int L>
+__global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
     int n, GridDev g, StepDev sp, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
     const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ wid, const uint32_t *__restrict__ cstart,
     const float4 *__restrict__ acc, const uint32_t *__restrict__ dtslots, uint32_t *__restrict__ skey,
     float4 *__restrict__ soff, uint32_t *__restrict__ sct, uint32_t *__restrict__ sid, float4 *__restrict__ at_out,
     float4 *__restrict__ v_out, float4 *__restrict__ dr_out, double *__restrict__ partials) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int i = lb * kBlock + threadIdx.x;
+  const int gid = lb * kBlock + threadIdx.x;
+  const int i = gid / L, sub = gid % L;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   const int ops[4] = {0, 0, 0, 0};
   const float dt1 = read_dt1(dtslots);
@@ -425,158 +419,161 @@ __global__ PAIR_KERNEL_ATTR void pass_viscous_integrate(
     float bx = 0.f, by = 0.f, bz = 0.f;
     // with eta_i = 0 every harmonic-mean viscosity of particle i vanishes: nothing to sum
     if (ei > 0.f) {
-      scan_candidates<D, RecV>(
-          i, ci, oi, rs, g, cstart, [&](int j) { return RecV{wpos[j], wjaux[j], acc[j]}; },
-          [&](const RecV &rj, uint32_t drw, bool v) {
-            const float4 pj = rj.p;
-            const uint32_t aj = rj.a;
-            const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
-            const float dy = row_dy(drw) + (oi[1] - pj.y);
-            float r2 = dx * dx + dy * dy;
-            if constexpr (D == 3) {
-              const float dz = row_dz(drw) + (oi[2] - pj.z);
-              r2 += dz * dz;
-            }
-            const float hij = kh * (hi + pj.w);
-            const bool apart = r2 > 1e-30f;
-            const bool use = v && apart && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti;
-#if MPSPH_BRANCHY
-            if (!use) return;
-#endif
-            const float rinv = fast_rsq(apart ? r2 : 1.f);
-            const float r = r2 * rinv;
-            const float ej = hdt * rj.acc.w;
-            const float esum = ei + ej;
-            const float etaij = 2.f * ei * ej * fast_rcp(esum > 0.f ? esum : 1.f);
-            const float ih = sp.kappa * fast_rcp(hij);
-            const float q = r * ih, uu = fmaf(-0.5f, q, 1.f);
-            const float ih2 = ih * ih;
-            const float ihp = D == 3 ? ih2 * ih2 : ih2 * ih;
-            const float sj = pj.w * sp.inv_tau;
-            const float inv2 = invi + powd<D>(sj * sj);
-            // dW/dr / r = -5 alpha h^-(d+1) q (1 - q/2)^3 / r
-            float s = -etaij * inv2 * (alpha5 * ihp * q * uu * uu * uu * rinv);
-            s = use ? s : 0.f;
-            bx = fmaf(s, vix - hdt * rj.acc.x, bx);
-            by = fmaf(s, viy - hdt * rj.acc.y, by);
-            if constexpr (D == 3) bz = fmaf(s, viz - hdt * rj.acc.z, bz);
-          });
+      scan_group<D, L>(i, sub, ci, oi, rs, g, cstart, [&](int j, uint32_t drw, bool v) {
+        const float4 pj = wpos[j];
+        const uint32_t aj = wjaux[j];
+        const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+        const float dy = row_dy(drw) + (oi[1] - pj.y);
+        float r2 = dx * dx + dy * dy;
+        if constexpr (D == 3) {
+          const float dz = row_dz(drw) + (oi[2] - pj.z);
+          r2 += dz * dz;
+        }
+        const float hij = kh * (hi + pj.w);
+        if (!(v && r2 > 1e-30f && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti)) return;
+        const float4 accj = acc[j];
+        const float rinv = fast_rsq(r2);
+        const float r = r2 * rinv;
+        const float ej = hdt * accj.w;
+        const float esum = ei + ej;
+        const float etaij = 2.f * ei * ej * fast_rcp(esum > 0.f ? esum : 1.f);
+        const float ih = sp.kappa * fast_rcp(hij);
+        const float q = r * ih, uu = fmaf(-0.5f, q, 1.f);
+        const float ih2 = ih * ih;
+        const float ihp = D == 3 ? ih2 * ih2 : ih2 * ih;
+        const float sj = pj.w * sp.inv_tau;
+        const float inv2 = invi + powd<D>(sj * sj);
+        // dW/dr / r = -5 alpha h^-(d+1) q (1 - q/2)^3 / r
+        const float s = -etaij * inv2 * (alpha5 * ihp * q * uu * uu * uu * rinv);
+        const float dxv = hdt * accj.x, dyv = hdt * accj.y, dzv = hdt * accj.z;
+        bx = fmaf(s, vix - dxv, bx);
+        by = fmaf(s, viy - dyv, by);
+        if constexpr (D == 3) bz = fmaf(s, viz - dzv, bz);
+      });
     }
-    float b[3] = {bx, by, bz};
-    project_feature<D>(g, ti, ci, oi, b);
-    float v[3] = {vix + 0.5f * b[0] * dt2, viy + 0.5f * b[1] * dt2, viz + 0.5f * b[2] * dt2};
-    if (ti == 3) v[0] = v[1] = v[2] = 0.f;
-    float dr[3] = {v[0] * dt2, v[1] * dt2, v[2] * dt2};
-    float ke = 0.f;
+    bx = group_sum<L>(bx);
+    by = group_sum<L>(by);
+    if constexpr (D == 3) bz = group_sum<L>(bz);
+    if (sub == 0) {
+      float b[3] = {bx, by, bz};
+      project_feature<D>(g, ti, ci, oi, b);
+      float v[3] = {vix + 0.5f * b[0] * dt2, viy + 0.5f * b[1] * dt2, viz + 0.5f * b[2] * dt2};
+      if (ti == 3) v[0] = v[1] = v[2] = 0.f;
+      float dr[3] = {v[0] * dt2, v[1] * dt2, v[2] * dt2};
+      float ke = 0.f;
 #pragma unroll
-    for (int a = 0; a < D; ++a) ke += 0.5f * v[a] * v[a];
-    const bool fin = isfinite(b[0]) && isfinite(b[1]) && isfinite(b[2]) && isfinite(dr[0]) && isfinite(dr[1]) &&
-                     isfinite(dr[2]);
-    // drift in (cell, offset) form with carry
-    int c[3] = {ci[0], ci[1], D == 3 ? ci[2] : 0};
-    float o[3] = {oi[0], oi[1], D == 3 ? oi[2] : 0.f};
-    if (ti != 3 && fin) {
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const float x = o[a] + dr[a];
-        const float fl = floorf(x);
-        c[a] += (int)fl;
-        o[a] = x - fl;
-        if (o[a] >= 1.f) {
-          o[a] = 0.f;
-          c[a] += 1;
-        }
-      }
-      if (g.geometry == 1) {
-        // box: closest-point projection is a clamp to the walls; type from the faces touched
-        int nf = 0;
+      for (int a = 0; a < D; ++a) ke += 0.5f * v[a] * v[a];
+      const bool fin = isfinite(b[0]) && isfinite(b[1]) && isfinite(b[2]) && isfinite(dr[0]) && isfinite(dr[1]) &&
+                       isfinite(dr[2]);
+      // drift in (cell, offset) form with carry
+      int c[3] = {ci[0], ci[1], D == 3 ? ci[2] : 0};
+      float o[3] = {oi[0], oi[1], D == 3 ? oi[2] : 0.f};
+      if (ti != 3 && fin) {
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          if (c[a] < 0) {
-            c[a] = 0;
+          const float x = o[a] + dr[a];
+          const float fl = floorf(x);
+          c[a] += (int)fl;
+          o[a] = x - fl;
+          if (o[a] >= 1.f) {
             o[a] = 0.f;
+            c[a] += 1;
           }
-          if (c[a] > g.whi_c[a] || (c[a] == g.whi_c[a] && o[a] > g.whi_o[a])) {
-            c[a] = g.whi_c[a];
-            o[a] = g.whi_o[a];
-          }
-          if ((c[a] == 0 && o[a] == 0.f) || (c[a] == g.whi_c[a] && o[a] == g.whi_o[a])) ++nf;
         }
-        ti = max(ti, type_from_faces(nf, D));
-      } else {
-        // annulus / ball: radial projection onto the nearest boundary circle / sphere
-        float rel[3], r2 = 0.f;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          rel[a] = (float)(c[a] - g.gc_c[a]) + (o[a] - g.gc_o[a]);
-          r2 += rel[a] * rel[a];
-        }
-        const float rr = sqrtf(r2);
-        const float phi = g.geometry == 2 ? fminf(rr - g.r_in, g.r_out - rr) : g.r_out - rr;
-        if (ti != 0 || phi < 0.f) {
-          float rb = g.r_out;
-          if (g.geometry == 2 && (rr - g.r_in) < (g.r_out - rr)) rb = g.r_in;
-          const float sc = rb / rr;
+        if (g.geometry == 1) {
+          // box: closest-point projection is a clamp to the walls; type from the faces touched
+          int nf = 0;
 #pragma unroll
           for (int a = 0; a < D; ++a) {
-            // new coordinate relative to the origin of cell c[a]: centre + rel * rb / |rel|
-            const float x = (float)(g.gc_c[a] - c[a]) + g.gc_o[a] + rel[a] * sc;
-            const float fl = floorf(x);
-            c[a] += (int)fl;
-            o[a] = x - fl;
-            if (o[a] >= 1.f) {
+            if (c[a] < 0) {
+              c[a] = 0;
               o[a] = 0.f;
-              c[a] += 1;
             }
+            if (c[a] > g.whi_c[a] || (c[a] == g.whi_c[a] && o[a] > g.whi_o[a])) {
+              c[a] = g.whi_c[a];
+              o[a] = g.whi_o[a];
+            }
+            if ((c[a] == 0 && o[a] == 0.f) || (c[a] == g.whi_c[a] && o[a] == g.whi_o[a])) ++nf;
           }
-          ti = max(ti, 1);
+          ti = max(ti, type_from_faces(nf, D));
+        } else {
+          // annulus / ball: radial projection onto the nearest boundary circle / sphere
+          float rel[3], r2 = 0.f;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            rel[a] = (float)(c[a] - g.gc_c[a]) + (o[a] - g.gc_o[a]);
+            r2 += rel[a] * rel[a];
+          }
+          const float rr = sqrtf(r2);
+          const float phi = g.geometry == 2 ? fminf(rr - g.r_in, g.r_out - rr) : g.r_out - rr;
+          if (ti != 0 || phi < 0.f) {
+            float rb = g.r_out;
+            if (g.geometry == 2 && (rr - g.r_in) < (g.r_out - rr)) rb = g.r_in;
+            const float sc = rb / rr;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              // new coordinate relative to the origin of cell c[a]: centre + rel * rb / |rel|
+              const float x = (float)(g.gc_c[a] - c[a]) + g.gc_o[a] + rel[a] * sc;
+              const float fl = floorf(x);
+              c[a] += (int)fl;
+              o[a] = x - fl;
+              if (o[a] >= 1.f) {
+                o[a] = 0.f;
+                c[a] += 1;
+              }
+            }
+            ti = max(ti, 1);
+          }
         }
       }
-    }
-    // keys must stay inside the grid whatever the arithmetic above produced
+      // keys must stay inside the grid whatever the arithmetic above produced
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      if (!(o[a] >= 0.f && o[a] < 1.f)) o[a] = 0.f;
-      if (c[a] < 0) {
-        c[a] = 0;
-        o[a] = 0.f;
+      for (int a = 0; a < D; ++a) {
+        if (!(o[a] >= 0.f && o[a] < 1.f)) o[a] = 0.f;
+        if (c[a] < 0) {
+          c[a] = 0;
+          o[a] = 0.f;
+        }
+        if (c[a] > g.gmax) {
+          c[a] = g.gmax;
+          o[a] = 0.f;
+        }
       }
-      if (c[a] > g.gmax) {
-        c[a] = g.gmax;
-        o[a] = 0.f;
-      }
+      skey[i] = pack_key<D>(c, g.k);
+      soff[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
+      sct[i] = (uint32_t)ti | ((ai >> 14) << 2);
+      sid[i] = wid[i];
+      if (at_out) at_out[i] = make_float4(b[0], b[1], b[2], 0.f);
+      if (v_out) v_out[i] = make_float4(v[0], v[1], v[2], 0.f);
+      if (dr_out) dr_out[i] = make_float4(dr[0], dr[1], dr[2], 0.f);
+      part[0] = (double)ke;
+      part[1] = fin ? 0.0 : 1.0;
+      part[2] = ti != 0 ? 1.0 : 0.0;
     }
-    skey[i] = pack_key<D>(c, g.k);
-    soff[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
-    sct[i] = (uint32_t)ti | ((ai >> 14) << 2);
-    sid[i] = wid[i];
-    if (at_out) at_out[i] = make_float4(b[0], b[1], b[2], 0.f);
-    if (v_out) v_out[i] = make_float4(v[0], v[1], v[2], 0.f);
-    if (dr_out) dr_out[i] = make_float4(dr[0], dr[1], dr[2], 0.f);
-    part[0] = (double)ke;
-    part[1] = fin ? 0.0 : 1.0;
-    part[2] = ti != 0 ? 1.0 : 0.0;
   }
   block_reduce_write<4>(part, ops, partials + (size_t)lb * kNumPartials + P_KE);
 }
 
-// Reduce the per-block partials in a fixed order into the metrics block: slots 0..15 as laid
-// out in kNumPartials, then 16: dt1, 17: dt2, 18..20: running totals of pairs, candidates,
-// steps.  Thread t owns blocks t, t+256, ... (fixed order), then a fixed tree over threads.
-__global__ __launch_bounds__(256) void finalize(int nblocks, const double *__restrict__ partials,
-                                                const uint32_t *__restrict__ dtslots, float dt2_factor,
-                                                double *__restrict__ m) {
+// Combine partials slot by slot: sums, or min / max for the slots that hold extrema.
+__device__ __forceinline__ double combine_slot(int s, double a, double b) {
+  return (s == P_EMAX || s == P_ELRMAX) ? fmax(a, b) : (s == P_ELRMIN ? fmin(a, b) : a + b);
+}
+__device__ __forceinline__ double slot_identity(int s) { return s == P_ELRMIN ? INFINITY : 0.0; }
+
+// First level of the metric reduction: block b reduces the contiguous chunk
+// [b * chunk, (b + 1) * chunk) of the per-block partials; thread t owns entries t, t + 256, ...
+// of the chunk, then a fixed tree over the threads.  Output: one partial row per block.
+__global__ __launch_bounds__(256) void reduce_partials(int nrows, int chunk, const double *__restrict__ partials,
+                                                       double *__restrict__ out) {
   __shared__ double red[kNumPartials][257];
   double acc[kNumPartials];
 #pragma unroll
-  for (int s = 0; s < kNumPartials; ++s) acc[s] = s == P_ELRMIN ? INFINITY : 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += 256) {
+  for (int s = 0; s < kNumPartials; ++s) acc[s] = slot_identity(s);
+  const int b0 = blockIdx.x * chunk, b1 = min(nrows, b0 + chunk);
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += 256) {
     const double *p = partials + (size_t)b * kNumPartials;
 #pragma unroll
-    for (int s = 0; s < kNumPartials; ++s) {
-      const double y = p[s];
-      acc[s] = (s == P_EMAX || s == P_ELRMAX) ? fmax(acc[s], y) : (s == P_ELRMIN ? fmin(acc[s], y) : acc[s] + y);
-    }
+    for (int s = 0; s < kNumPartials; ++s) acc[s] = combine_slot(s, acc[s], p[s]);
   }
 #pragma unroll
   for (int s = 0; s < kNumPartials; ++s) red[s][threadIdx.x] = acc[s];
@@ -584,10 +581,35 @@ __global__ __launch_bounds__(256) void finalize(int nblocks, const double *__res
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
 #pragma unroll
-      for (int s = 0; s < kNumPartials; ++s) {
-        const double y = red[s][threadIdx.x + w], z = red[s][threadIdx.x];
-        red[s][threadIdx.x] = (s == P_EMAX || s == P_ELRMAX) ? fmax(z, y) : (s == P_ELRMIN ? fmin(z, y) : z + y);
-      }
+      for (int s = 0; s < kNumPartials; ++s) red[s][threadIdx.x] = combine_slot(s, red[s][threadIdx.x], red[s][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kNumPartials) out[(size_t)blockIdx.x * kNumPartials + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Second level: one block reduces the first-level rows (same fixed order) into the metrics
+// block: slots 0..15 as laid out in kNumPartials, then 16: dt1, 17: dt2, 18..20: running totals
+// of pairs, candidates and steps.
+__global__ __launch_bounds__(256) void finalize(int nrows, const double *__restrict__ rows,
+                                                const uint32_t *__restrict__ dtslots, float dt2_factor,
+                                                double *__restrict__ m) {
+  __shared__ double red[kNumPartials][257];
+  double acc[kNumPartials];
+#pragma unroll
+  for (int s = 0; s < kNumPartials; ++s) acc[s] = slot_identity(s);
+  for (int b = threadIdx.x; b < nrows; b += 256) {
+    const double *p = rows + (size_t)b * kNumPartials;
+#pragma unroll
+    for (int s = 0; s < kNumPartials; ++s) acc[s] = combine_slot(s, acc[s], p[s]);
+  }
+#pragma unroll
+  for (int s = 0; s < kNumPartials; ++s) red[s][threadIdx.x] = acc[s];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int s = 0; s < kNumPartials; ++s) red[s][threadIdx.x] = combine_slot(s, red[s][threadIdx.x], red[s][threadIdx.x + w]);
     }
     __syncthreads();
   }
@@ -679,8 +701,10 @@ struct Layout {
   int64_t n = 0;
   uint32_t ncells = 0;
   int nblocks = 0;
+  int nblocks_pair = 0;
   size_t bytes = 0;
   // offsets
+  size_t partials2;
   size_t s_key, s_off, s_ct, s_id, w_key, w_pos, w_jaux, w_id, k0, v0, k1, v1, hist, cstart, acc, rho, nn, aabs, at, v,
       dr, partials, metrics, dtcells, bad, rbf_c, rbf_o, rbf_k;
 };
@@ -922,6 +946,7 @@ Layout make_layout(int dim, int k, int64_t n, int n_rbf) {
   L.n = n;
   L.ncells = (uint32_t)1u << (dim * k);
   L.nblocks = (int)std::max<int64_t>(1, (n + kBlock - 1) / kBlock);
+  L.nblocks_pair = (int)std::max<int64_t>(1, (n * MPSPH_LANES + kBlock - 1) / kBlock);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -950,7 +975,8 @@ Layout make_layout(int dim, int k, int64_t n, int n_rbf) {
   L.at = take(nn * 16);
   L.v = take(nn * 16);
   L.dr = take(nn * 16);
-  L.partials = take((size_t)L.nblocks * kNumPartials * 8);
+  L.partials = take((size_t)L.nblocks_pair * kNumPartials * 8);
+  L.partials2 = take((size_t)kReduceBlocks * kNumPartials * 8);
   L.metrics = take(32 * 8);
   L.dtcells = take(kDtSlots * 4);
   L.bad = take(4);
@@ -1096,6 +1122,8 @@ int run_steps(mpsph_ctx *ctx, int nsteps) {
   const Layout &L = ctx->L;
   hipStream_t st = ctx->stream;
   const int nb = L.nblocks;
+  const int nbp = L.nblocks_pair;  // blocks of the pair kernels: MPSPH_LANES lanes per particle
+  (void)nb;
   const double cs = ctx->d.cs;
   StepDev sp;
   sp.kappa = (float)ctx->p.kappa;
@@ -1128,14 +1156,14 @@ int run_steps(mpsph_ctx *ctx, int nsteps) {
           ctx->at<uint32_t>(L.dtcells));
       if (hk) hk->end();
       if (hk) hk->begin("pass_density_force");
-      pass_density_force<D><<<nb, kBlock, 0, st>>>(
+      pass_density_force<D, MPSPH_LANES><<<nbp, kBlock, 0, st>>>(
           n, ctx->g, sp, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
           ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc), dbg ? ctx->at<float>(L.rho) : nullptr,
           dbg ? ctx->at<float>(L.nn) : nullptr, dbg ? ctx->at<float>(L.aabs) : nullptr,
           ctx->at<uint32_t>(L.dtcells), ctx->at<double>(L.partials));
       if (hk) hk->end();
       if (hk) hk->begin("pass_viscous_integrate");
-      pass_viscous_integrate<D><<<nb, kBlock, 0, st>>>(
+      pass_viscous_integrate<D, MPSPH_LANES><<<nbp, kBlock, 0, st>>>(
           n, ctx->g, sp, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
           ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
           ctx->at<uint32_t>(L.dtcells), ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off),
@@ -1144,8 +1172,15 @@ int run_steps(mpsph_ctx *ctx, int nsteps) {
       if (hk) hk->end();
     }
     if (hk) hk->begin("finalize");
-    finalize<<<1, 256, 0, st>>>(n > 0 ? nb : 0, ctx->at<double>(L.partials), ctx->at<uint32_t>(L.dtcells),
-                                sp.dt2_factor, ctx->at<double>(L.metrics));
+    {
+      const int rows = n > 0 ? nbp : 0;
+      const int chunk = (rows + kReduceBlocks - 1) / kReduceBlocks;
+      const int nred = rows > 0 ? (rows + chunk - 1) / chunk : 0;
+      if (nred > 0)
+        reduce_partials<<<nred, 256, 0, st>>>(rows, chunk, ctx->at<double>(L.partials), ctx->at<double>(L.partials2));
+      finalize<<<1, 256, 0, st>>>(nred, ctx->at<double>(L.partials2), ctx->at<uint32_t>(L.dtcells), sp.dt2_factor,
+                                  ctx->at<double>(L.metrics));
+    }
     if (hk) hk->end();
     if (hipGetLastError() != hipSuccess) return fail(ctx, MPSPH_E_DEVICE);
     ctx->steps_done += 1;

@@ -10,6 +10,7 @@ constexpr int kWave = 64;
 constexpr int kNumPartials = 16;  // FP64 partial slots per block
 constexpr uint32_t kInfBits = 0x7f800000u;
 constexpr int kDtSlots = 64;      // words over which the first time-step minimum is spread
+constexpr int kReduceBlocks = 256;  // first-level blocks of the metric reduction
 
 // Slots of the per-block FP64 partials.
 enum : int {
