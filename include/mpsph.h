@@ -145,6 +145,24 @@ MPSPH_API size_t mpsph_workspace_bytes(const mpsph_params *params, int64_t n);
 MPSPH_API int mpsph_create(const mpsph_params *params, int64_t n, void *d_workspace, size_t workspace_bytes,
                  void *hip_stream, mpsph_ctx **out);
 
+/* Batched context: ndom >= 1 independent domains (one mpsph_params and particle count n[d]
+ * each; 2D and 3D domains may be mixed; one debug flag for all) advanced together: each kernel
+ * of a step is launched once for all domains of one dimension.  Particle arrays passed to
+ * mpsph_load / mpsph_store / mpsph_debug_fields hold the domains one after the other in the
+ * given order: domain d owns rows [u_d, u_d + n[d]) of the colour / type / scalar arrays,
+ * u_d = n[0] + ... + n[d-1], and the n[d] x dim_d row-major block of positions (or vector
+ * quantities) that starts at float n[0] dim_0 + ... + n[d-1] dim_(d-1).  A domain evolves
+ * exactly (bit for bit) as it would in a context of its own; domains never interact.
+ * Workspace and stream as in mpsph_create (mpsph_batch_workspace_bytes gives the size).
+ * Errors: MPSPH_E_INVALID (bad params or counts, mixed debug flags, ndom outside [1, 4096]),
+ * MPSPH_E_NOMEM, MPSPH_E_DEVICE, MPSPH_E_UNSUPPORTED (more than 2^30 particles or 2^28 cells). */
+MPSPH_API size_t mpsph_batch_workspace_bytes(int32_t ndom, const mpsph_params *params, const int64_t *n);
+MPSPH_API int mpsph_batch_create(int32_t ndom, const mpsph_params *params, const int64_t *n, void *d_workspace,
+                                 size_t workspace_bytes, void *hip_stream, mpsph_ctx **out);
+
+/* Number of domains and total particle count of a context (either pointer may be NULL). */
+MPSPH_API int mpsph_domain_count(mpsph_ctx *ctx, int32_t *ndom, int64_t *n_total);
+
 /* Load the particle set: d_pos (n x dim float32, domain units), d_colour (n int32 in
  * [0, 2^18)), d_type (n int32 in [0,3], or NULL for all normal).  Resets the step counter.
  * Every position must lie inside the bounding box [lo, hi] (MPSPH_E_INVALID otherwise). */
@@ -153,9 +171,21 @@ MPSPH_API int mpsph_load(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_co
 /* Enqueue nsteps >= 0 relaxation steps on the context's stream; returns without waiting. */
 MPSPH_API int mpsph_step(mpsph_ctx *ctx, int32_t nsteps);
 
+/* As mpsph_step, but the nsteps steps run as one HIP graph: captured (on a private stream of
+ * the context, default priority) at the first call with this nsteps and replayed by later
+ * calls, launched on the context's stream.  Every step reads its step index from device
+ * memory, so replays follow the same trajectory as mpsph_step.  The graph holds no memset
+ * node.  Profiling records one "step_graph" entry per launch instead of per-kernel entries.
+ * Errors: MPSPH_E_STATE (not loaded), MPSPH_E_DEVICE (capture or launch failed). */
+MPSPH_API int mpsph_step_graph(mpsph_ctx *ctx, int32_t nsteps);
+
 /* Metrics of the last step (synchronises the stream).  Returns MPSPH_E_NONFINITE (with the
  * metrics still written) when that step produced non-finite values. */
 MPSPH_API int mpsph_metrics(mpsph_ctx *ctx, mpsph_metrics_t *out);
+
+/* Metrics of domains first .. first + count - 1 of a batched context into out[0 .. count)
+ * (mpsph_metrics reports domain 0).  Same synchronisation and MPSPH_E_NONFINITE rule. */
+MPSPH_API int mpsph_domain_metrics(mpsph_ctx *ctx, int32_t first, int32_t count, mpsph_metrics_t *out);
 
 /* Current positions (n x dim float32, domain units) and types (n int32) in the original
  * particle order of mpsph_load().  Either pointer may be NULL.  Synchronises. */
@@ -167,9 +197,11 @@ MPSPH_API int mpsph_store(mpsph_ctx *ctx, float *d_pos, int32_t *d_type);
 MPSPH_API int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out);
 
 /* Cell structure of the last step: d_key (n uint32, the cell key of each particle in
- * original order: cx + 2^k cy + 4^k cz), d_cell_start (ncells + 1 uint32: index of the first
- * sorted particle of each cell, last entry n) -- either may be NULL -- and the host values
- * ncells and cell_log2.  Synchronises. */
+ * original order: cellbase + cx + 2^k cy + 4^k cz, where cellbase is 0 for a single domain and
+ * in a batch the first cell of the domain's range of the global cell table), d_cell_start
+ * (ncells + 1 uint32: index of the first sorted particle of each cell, last entry n) -- either
+ * may be NULL -- and the host values ncells (all domains) and cell_log2 (of domain 0).
+ * Synchronises. */
 MPSPH_API int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cell_start, int64_t *ncells,
                       int32_t *cell_log2);
 

@@ -1,9 +1,14 @@
 // Relaxation step of the multi-phase SPH mesh generator (Ji, Fu, Hu & Adams, arXiv 1906.07925)
 // on MI355X / gfx950.  The C ABI is declared in include/mpsph.h.
 //
-// Data layout (HBM, structure of arrays, n particles):
-//   state  (order of the previous step's sort): key u32, off float4 (cell offsets), ct u32
-//          (type | colour << 2), id u32 (index at load)
+// A context holds one or more independent domains of the same dimension (a batch).  Domains
+// occupy contiguous ranges of every particle array and of the global cell index space, so one
+// launch of each kernel serves all of them; kernels read their domain's parameters from a device
+// table.  The step counter lives on the device, so a captured step can be replayed.
+//
+// Data layout (HBM, structure of arrays, n particles over all domains):
+//   state  (order of the previous step's sort): key u32 (domain cell base + packed cell), off
+//          float4 (cell offsets), ct u32 (type | colour << 2), id u32 (index at load)
 //   work   (order of this step's sort): key u32, pos float4 (offsets, h), jaux u32
 //          (cx | type << 12 | colour << 14), id u32
 //   per step: acc float4 (a, e = rho_t nu_coeff r_c |a|), cell table u32[ncells+1]; rho, sum|term|,
@@ -15,7 +20,7 @@
 // (time is unchanged; the EOS constant is scaled by cs^(d-2) to make this exact).
 //
 // Launch sequence of one step (all on the context stream, no host synchronisation):
-//   radix sort of the keys (3 kernels per 8-bit digit)
+//   radix sort of the keys (3 kernels per digit of at most 8 bits)
 //   reorder_field   gather the state in key order, evaluate the target field (Eq. 1-2, 16), fill
 //                   the cell table
 //   pass_density_force  density (Eq. 17), pressure + surface tension (Eq. 18-19, 23-25),
@@ -23,7 +28,7 @@
 //   pass_viscous_integrate  mid-point velocity (Eq. 26), viscosity (Eq. 21-22), viscous
 //                   acceleration (Eq. 20), second time step (Eq. 29), velocity (Eq. 27), drift
 //                   (Eq. 28), feature projection and re-tagging (Eq. 32)
-//   finalize        FP64 reduction of the per-block partials in a fixed order
+//   reduce_partials, finalize   FP64 reduction of the per-block partials in a fixed order
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,76 +51,82 @@ namespace {
 // Kernels
 // ------------------------------------------------------------------------------------------
 
+// Domain units -> (cell, offset) in FP64 (identical inputs give identical keys), validation.
+// Internal particles [i0, i1) of one dimension group.
 template <int D>
-__global__ __launch_bounds__(kBlock) void load_kernel(const float *__restrict__ pos, const int32_t *__restrict__ colour,
-                                                      const int32_t *__restrict__ type, int n, double lo0,
-                                                      double lo1, double lo2, double xhi0, double xhi1,
-                                                      double xhi2, double inv_cs, int k, int gmax,
-                                                      uint32_t *__restrict__ key, float4 *__restrict__ off,
-                                                      uint32_t *__restrict__ ct, uint32_t *__restrict__ id,
-                                                      int *__restrict__ bad) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double lo[3] = {lo0, lo1, lo2};
-  const double xhi[3] = {xhi0, xhi1, xhi2};  // upper face of the bounding box in cell units
+__global__ __launch_bounds__(kBlock) void load_kernel(const DomDev *__restrict__ doms, int ndom, int i0, int i1,
+                                                      const float *__restrict__ pos, const int32_t *__restrict__ colour,
+                                                      const int32_t *__restrict__ type, uint32_t *__restrict__ key,
+                                                      float4 *__restrict__ off, uint32_t *__restrict__ ct,
+                                                      uint32_t *__restrict__ id, int *__restrict__ bad) {
+  const int i = i0 + blockIdx.x * kBlock + threadIdx.x;
+  if (i >= i1) return;
+  const DomDev &dd = doms[domain_of(doms, ndom, i)];
+  const int local = i - dd.off;
+  const int u = dd.uoff + local;
+  const float *x = pos + dd.xoff + (int64_t)local * D;
   int c[3] = {0, 0, 0};
   float o[3] = {0.f, 0.f, 0.f};
   bool ok = true;
   for (int a = 0; a < D; ++a) {
-    double X = ((double)pos[(size_t)i * D + a] - lo[a]) * inv_cs;
-    if (!(X >= 0.0 && X <= xhi[a])) ok = false;
+    const double X = ((double)x[a] - dd.lo[a]) * dd.inv_cs;
+    if (!(X >= 0.0 && X <= dd.xhi[a])) ok = false;
     double f = floor(X);
     float fo = (float)(X - f);
     if (fo >= 1.0f) {
       fo = 0.0f;
       f += 1.0;
     }
-    if (!(f >= 0.0 && f <= (double)gmax)) ok = false;
+    if (!(f >= 0.0 && f <= (double)dd.g.gmax)) ok = false;
     c[a] = ok ? (int)f : 0;
     o[a] = ok ? fo : 0.f;
   }
-  int col = colour[i];
-  int t = type ? type[i] : 0;
+  const int col = colour[u];
+  const int t = type ? type[u] : 0;
   if (col < 0 || col >= (1 << 18) || t < 0 || t > 3) ok = false;
   if (!ok) atomicOr(bad, 1);
-  key[i] = pack_key<D>(c, k);
+  key[i] = dd.cellbase + pack_key<D>(c, dd.g.k);
   off[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
   ct[i] = (uint32_t)(t & 3) | ((uint32_t)col << 2);
-  id[i] = (uint32_t)i;
+  id[i] = (uint32_t)u;
 }
 
 // Gather the state in sorted order, evaluate the size field (h = tau s, Eq. 16) and build the
-// cell table: cstart[c] = first sorted index with key >= c, cstart[ncells] = n.
+// cell table: cstart[c] = first sorted index with key >= c, cstart[ncells] = n.  Sorted keys are
+// grouped by domain, so the sorted range of domain d is [off_d, off_d + n_d); one launch covers
+// the sorted indices [i0, i1) of one dimension group (and the sentinel i = n if i1 = n).  The
+// first nreset threads also reset the time-step slots.
 template <int D>
 __global__ __launch_bounds__(kBlock) void reorder_field(
-    int n, uint32_t ncells, GridDev g, FieldDev f, float tau, const uint32_t *__restrict__ skey,
-    const uint32_t *__restrict__ perm, const float4 *__restrict__ soff, const uint32_t *__restrict__ sct,
-    const uint32_t *__restrict__ sid, uint32_t *__restrict__ wkey, float4 *__restrict__ wpos,
-    uint32_t *__restrict__ wjaux, uint32_t *__restrict__ wid, uint32_t *__restrict__ cstart,
-    uint32_t *__restrict__ dtcells) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < kDtSlots) dtcells[i] = kInfBits;
-  if (i > n) return;
+    const DomDev *__restrict__ doms, int ndom, int i0, int i1, int n, uint32_t ncells, int nreset,
+    const uint32_t *__restrict__ skey, const uint32_t *__restrict__ perm, const float4 *__restrict__ soff,
+    const uint32_t *__restrict__ sct, const uint32_t *__restrict__ sid, uint32_t *__restrict__ wkey,
+    float4 *__restrict__ wpos, uint32_t *__restrict__ wjaux, uint32_t *__restrict__ wid,
+    uint32_t *__restrict__ cstart, uint32_t *__restrict__ dtslots) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t < nreset) dtslots[t] = kInfBits;
+  const int i = i0 + t;
+  if (i > i1 || (i == i1 && i1 != n)) return;
   // cells (key[i-1], key[i]] start at sorted index i; the sentinel thread i = n closes the table
   const uint32_t lo = i == 0 ? 0u : skey[i - 1] + 1u;
   const uint32_t hi = i == n ? ncells : min(skey[i], ncells);
   for (uint32_t c = lo; c <= hi; ++c) cstart[c] = (uint32_t)i;
   if (i == n) return;
-  uint32_t s = perm[i];
-  uint32_t key = skey[i];
-  float4 o4 = soff[s];
-  uint32_t ct = sct[s];
+  const DomDev &dd = doms[domain_of(doms, ndom, i)];
+  const uint32_t s = perm[i];
+  const uint32_t key = skey[i];
+  const float4 o4 = soff[s];
+  const uint32_t ct = sct[s];
   int c[3];
-  unpack_key<D>(key, g.k, g.xmask, c);
-  float o[3] = {o4.x, o4.y, o4.z};
-  float sp = field_spacing<D>(f, c, o);
+  unpack_key<D>(key - dd.cellbase, dd.g.k, dd.g.xmask, c);
+  const float o[3] = {o4.x, o4.y, o4.z};
+  const float spc = field_spacing<D>(dd.f, c, o);
   wkey[i] = key;
-  wpos[i] = make_float4(o4.x, o4.y, o4.z, tau * sp);
+  wpos[i] = make_float4(o4.x, o4.y, o4.z, dd.sp.tau * spc);
   wjaux[i] = (uint32_t)c[0] | ((ct & 3u) << 12) | ((ct >> 2) << 14);
   wid[i] = sid[s];
 }
 
-// ------------------------------------------------------------------------------------------
 // Neighbour candidates
 //
 // Particle i's candidates are the particles of every x-run of cells (fixed y, z) that meets the
@@ -139,7 +150,8 @@ __device__ __forceinline__ float row_dz(uint32_t dr) { return (float)((int)dr >>
 
 template <int D, int L, typename BodyF>
 __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, const float *oi, float rs,
-                                               const GridDev &g, const uint32_t *__restrict__ cstart, BodyF &&body) {
+                                               const GridDev &g, uint32_t cellbase, const uint32_t *__restrict__ cstart,
+                                               BodyF &&body) {
   // a finite, non-negative radius keeps every cell range inside [0, gmax] (NaN -> 0)
   rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
   const float rs2 = rs * rs;
@@ -170,6 +182,7 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
     const int x1 = min(g.gmax, ci[0] + (int)floorf(oi[0] + wx));
     uint32_t kb = (uint32_t)x0 | ((uint32_t)cy << g.k);
     if constexpr (D == 3) kb |= (uint32_t)cz << (2 * g.k);
+    kb += cellbase;
     uint32_t a = 0u, b = 0u;
     if (hit) {
       a = cstart[kb];
@@ -223,7 +236,8 @@ __device__ __forceinline__ float group_min(float x) {
   return x;
 }
 
-// Minimum of the first time step: one atomic per block, spread over kDtSlots words.
+// Minimum of the first time step: one atomic per block, spread over the kDtSlots words of the
+// block's domain.
 __device__ __forceinline__ void block_min_to_slots(float v, int lb, uint32_t *slots) {
   __shared__ float wmin[kBlock / kWave];
   for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
@@ -236,7 +250,7 @@ __device__ __forceinline__ void block_min_to_slots(float v, int lb, uint32_t *sl
   }
 }
 
-// First time step (Eq. 29 with v = 0): minimum over the slots, every lane of the wave gets it.
+// First time step (Eq. 29 with v = 0): minimum over the domain's slots, every lane gets it.
 __device__ __forceinline__ float read_dt1(const uint32_t *slots) {
   float v = __uint_as_float(slots[threadIdx.x & (kDtSlots - 1)]);
   for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
@@ -252,14 +266,20 @@ __device__ __forceinline__ float read_dt1(const uint32_t *slots) {
 // L lanes per particle (group); lane 0 of the group writes the particle's results.
 template <int D, int L>
 __global__ __launch_bounds__(kBlock) void pass_density_force(
-    int n, GridDev g, StepDev sp, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
-    const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ cstart, float4 *__restrict__ acc,
-    float *__restrict__ rho_out, float *__restrict__ nn_out, float *__restrict__ aabs_out,
+    const DomDev *__restrict__ doms, int ndom, int b0, const int64_t *__restrict__ stepctr, const uint32_t *__restrict__ wkey,
+    const float4 *__restrict__ wpos, const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ cstart,
+    float4 *__restrict__ acc, float *__restrict__ rho_out, float *__restrict__ nn_out, float *__restrict__ aabs_out,
     uint32_t *__restrict__ dtslots, double *__restrict__ partials) {
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int gid = lb * kBlock + threadIdx.x;
-  const int i = gid / L, sub = gid % L;
-  const bool active = i < n;
+  const int lb = b0 + xcd_block(blockIdx.x, gridDim.x);
+  const int d = domain_of_block(doms, ndom, lb);
+  const GridDev g = doms[d].g;
+  const StepDev sp = doms[d].sp;
+  const uint32_t cellbase = doms[d].cellbase;
+  const int local = (lb - doms[d].blk0) * kBlock + threadIdx.x;
+  const int li = local / L, sub = local % L;
+  const int i = doms[d].off + li;
+  const bool active = li < doms[d].n;
+  const float sigma = sigma_of(sp, (float)*stepctr);
   double part[12];
   const int ops[12] = {0, 2, 0, 0, 0, 1, 2, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -268,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
   float dtc = INFINITY;
   if (active) {
     int ci[3];
-    unpack_key<D>(wkey[i], g.k, g.xmask, ci);
+    unpack_key<D>(wkey[i] - cellbase, g.k, g.xmask, ci);
     const float4 pi = wpos[i];
     const float oi[3] = {pi.x, pi.y, pi.z};
     const uint32_t ai = wjaux[i];
@@ -282,10 +302,10 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
     const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
     const float kh = 0.5f * sp.kappa;
     const float alpha5 = 5.f * sp.alpha;
-    const float opb = 1.f + sp.sigma;
+    const float opb = 1.f + sigma;
     float wsum = 0.f, ax = 0.f, ay = 0.f, az = 0.f, A = 0.f, nn2 = INFINITY;
     uint32_t npair = 0, nifc = 0;
-    uint32_t ncand = scan_group<D, L>(i, sub, ci, oi, rs, g, cstart, [&](int j, uint32_t drw, bool v) {
+    uint32_t ncand = scan_group<D, L>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](int j, uint32_t drw, bool v) {
       const float4 pj = wpos[j];
       const uint32_t aj = wjaux[j];
       const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
@@ -369,9 +389,10 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
       part[11] = fin ? 0.0 : 1.0;
     }
   }
-  block_min_to_slots(dtc, lb, dtslots);
+  block_min_to_slots(dtc, lb, dtslots + d * kDtSlots);
   block_reduce_write<12>(part, ops, partials + (size_t)lb * kNumPartials);
 }
+
 
 // Box type from the number of faces a particle lies on.
 __device__ __forceinline__ int type_from_faces(int nf, int d) {
@@ -388,22 +409,27 @@ __device__ __forceinline__ int type_from_faces(int nf, int d) {
 // dt2 = dt1 min(1, 2 min(c_vel, c_visc / nu_coeff) / c_acc^2) (sp.dt2_factor).
 template <int D, int L>
 __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
-    int n, GridDev g, StepDev sp, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
+    const DomDev *__restrict__ doms, int ndom, int b0, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
     const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ wid, const uint32_t *__restrict__ cstart,
     const float4 *__restrict__ acc, const uint32_t *__restrict__ dtslots, uint32_t *__restrict__ skey,
     float4 *__restrict__ soff, uint32_t *__restrict__ sct, uint32_t *__restrict__ sid, float4 *__restrict__ at_out,
     float4 *__restrict__ v_out, float4 *__restrict__ dr_out, double *__restrict__ partials) {
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int gid = lb * kBlock + threadIdx.x;
-  const int i = gid / L, sub = gid % L;
+  const int lb = b0 + xcd_block(blockIdx.x, gridDim.x);
+  const int d = domain_of_block(doms, ndom, lb);
+  const GridDev g = doms[d].g;
+  const StepDev sp = doms[d].sp;
+  const uint32_t cellbase = doms[d].cellbase;
+  const int local = (lb - doms[d].blk0) * kBlock + threadIdx.x;
+  const int li = local / L, sub = local % L;
+  const int i = doms[d].off + li;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   const int ops[4] = {0, 0, 0, 0};
-  const float dt1 = read_dt1(dtslots);
+  const float dt1 = read_dt1(dtslots + d * kDtSlots);
   const float hdt = 0.5f * dt1;
   const float dt2 = dt1 * sp.dt2_factor;
-  if (i < n) {
+  if (li < doms[d].n) {
     int ci[3];
-    unpack_key<D>(wkey[i], g.k, g.xmask, ci);
+    unpack_key<D>(wkey[i] - cellbase, g.k, g.xmask, ci);
     const float4 pi = wpos[i];
     const float oi[3] = {pi.x, pi.y, pi.z};
     const uint32_t ai = wjaux[i];
@@ -419,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
     float bx = 0.f, by = 0.f, bz = 0.f;
     // with eta_i = 0 every harmonic-mean viscosity of particle i vanishes: nothing to sum
     if (ei > 0.f) {
-      scan_group<D, L>(i, sub, ci, oi, rs, g, cstart, [&](int j, uint32_t drw, bool v) {
+      scan_group<D, L>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](int j, uint32_t drw, bool v) {
         const float4 pj = wpos[j];
         const uint32_t aj = wjaux[j];
         const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
@@ -539,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
           o[a] = 0.f;
         }
       }
-      skey[i] = pack_key<D>(c, g.k);
+      skey[i] = cellbase + pack_key<D>(c, g.k);
       soff[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
       sct[i] = (uint32_t)ti | ((ai >> 14) << 2);
       sid[i] = wid[i];
@@ -554,47 +580,16 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
   block_reduce_write<4>(part, ops, partials + (size_t)lb * kNumPartials + P_KE);
 }
 
+
 // Combine partials slot by slot: sums, or min / max for the slots that hold extrema.
 __device__ __forceinline__ double combine_slot(int s, double a, double b) {
   return (s == P_EMAX || s == P_ELRMAX) ? fmax(a, b) : (s == P_ELRMIN ? fmin(a, b) : a + b);
 }
 __device__ __forceinline__ double slot_identity(int s) { return s == P_ELRMIN ? INFINITY : 0.0; }
 
-// First level of the metric reduction: block b reduces the contiguous chunk
-// [b * chunk, (b + 1) * chunk) of the per-block partials; thread t owns entries t, t + 256, ...
-// of the chunk, then a fixed tree over the threads.  Output: one partial row per block.
-__global__ __launch_bounds__(256) void reduce_partials(int nrows, int chunk, const double *__restrict__ partials,
-                                                       double *__restrict__ out) {
-  __shared__ double red[kNumPartials][257];
-  double acc[kNumPartials];
-#pragma unroll
-  for (int s = 0; s < kNumPartials; ++s) acc[s] = slot_identity(s);
-  const int b0 = blockIdx.x * chunk, b1 = min(nrows, b0 + chunk);
-  for (int b = b0 + (int)threadIdx.x; b < b1; b += 256) {
-    const double *p = partials + (size_t)b * kNumPartials;
-#pragma unroll
-    for (int s = 0; s < kNumPartials; ++s) acc[s] = combine_slot(s, acc[s], p[s]);
-  }
-#pragma unroll
-  for (int s = 0; s < kNumPartials; ++s) red[s][threadIdx.x] = acc[s];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-#pragma unroll
-      for (int s = 0; s < kNumPartials; ++s) red[s][threadIdx.x] = combine_slot(s, red[s][threadIdx.x], red[s][threadIdx.x + w]);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < kNumPartials) out[(size_t)blockIdx.x * kNumPartials + threadIdx.x] = red[threadIdx.x][0];
-}
-
-// Second level: one block reduces the first-level rows (same fixed order) into the metrics
-// block: slots 0..15 as laid out in kNumPartials, then 16: dt1, 17: dt2, 18..20: running totals
-// of pairs, candidates and steps.
-__global__ __launch_bounds__(256) void finalize(int nrows, const double *__restrict__ rows,
-                                                const uint32_t *__restrict__ dtslots, float dt2_factor,
-                                                double *__restrict__ m) {
-  __shared__ double red[kNumPartials][257];
+// Fixed-order reduction of nrows partial rows (kNumPartials doubles each) by one block:
+// thread t owns rows t, t + 256, ..., then a fixed tree over the threads.  Result in red[s][0].
+__device__ __forceinline__ void reduce_rows(const double *__restrict__ rows, int nrows, double (*red)[257]) {
   double acc[kNumPartials];
 #pragma unroll
   for (int s = 0; s < kNumPartials; ++s) acc[s] = slot_identity(s);
@@ -609,61 +604,91 @@ __global__ __launch_bounds__(256) void finalize(int nrows, const double *__restr
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
 #pragma unroll
-      for (int s = 0; s < kNumPartials; ++s) red[s][threadIdx.x] = combine_slot(s, red[s][threadIdx.x], red[s][threadIdx.x + w]);
+      for (int s = 0; s < kNumPartials; ++s)
+        red[s][threadIdx.x] = combine_slot(s, red[s][threadIdx.x], red[s][threadIdx.x + w]);
     }
     __syncthreads();
   }
-  if (threadIdx.x < kNumPartials) m[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// First level of the metric reduction: row group r (never straddling two domains) reduces the
+// pair-kernel block partials [groups[r].x, groups[r].y) into one row.
+__global__ __launch_bounds__(256) void reduce_partials(const int2 *__restrict__ groups, const double *__restrict__ partials,
+                                                       double *__restrict__ out) {
+  __shared__ double red[kNumPartials][257];
+  const int2 gr = groups[blockIdx.x];
+  reduce_rows(partials + (size_t)gr.x * kNumPartials, gr.y - gr.x, red);
+  if (threadIdx.x < kNumPartials) out[(size_t)blockIdx.x * kNumPartials + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Second level, one block per domain: the domain's first-level rows into its metrics block m[32 d ...]:
+// slots 0..15 as laid out in kNumPartials, 16: dt1, 17: dt2, 18..20: running totals of pairs,
+// candidates and steps.  Block 0 then advances the device step counter.
+__global__ __launch_bounds__(256) void finalize(const DomDev *__restrict__ doms, const double *__restrict__ rows,
+                                                const uint32_t *__restrict__ dtslots, double *__restrict__ m,
+                                                int64_t *__restrict__ stepctr) {
+  __shared__ double red[kNumPartials][257];
+  const int d = blockIdx.x;
+  reduce_rows(rows + (size_t)doms[d].row0 * kNumPartials, doms[d].nrow, red);
+  double *md = m + (size_t)d * 32;
+  if (threadIdx.x < kNumPartials) md[threadIdx.x] = red[threadIdx.x][0];
   if (threadIdx.x == 0) {
     float d1 = INFINITY;
-    for (int s = 0; s < kDtSlots; ++s) d1 = fminf(d1, __uint_as_float(dtslots[s]));
-    m[16] = d1 < INFINITY ? (double)d1 : 0.0;
-    m[17] = d1 < INFINITY ? (double)(d1 * dt2_factor) : 0.0;
+    for (int s = 0; s < kDtSlots; ++s) d1 = fminf(d1, __uint_as_float(dtslots[d * kDtSlots + s]));
+    md[16] = d1 < INFINITY ? (double)d1 : 0.0;
+    md[17] = d1 < INFINITY ? (double)(d1 * doms[d].sp.dt2_factor) : 0.0;
     // running totals since the last load (exact integers below 2^53)
-    m[18] += red[P_PAIRS][0];
-    m[19] += red[P_CAND][0];
-    m[20] += 1.0;
+    md[18] += red[P_PAIRS][0];
+    md[19] += red[P_CAND][0];
+    md[20] += 1.0;
+    if (d == 0) *stepctr += 1;
   }
 }
 
-// Positions back to domain units in the load order.
+// Positions back to domain units (FP64) in the load order; state indices [i0, i1).
 template <int D>
-__global__ __launch_bounds__(kBlock) void store_kernel(int n, int k, uint32_t mask, double lo0, double lo1, double lo2,
-                                                       double cs, const uint32_t *__restrict__ skey,
-                                                       const float4 *__restrict__ soff, const uint32_t *__restrict__ sct,
-                                                       const uint32_t *__restrict__ sid, float *__restrict__ pos,
-                                                       int32_t *__restrict__ type) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+__global__ __launch_bounds__(kBlock) void store_kernel(const DomDev *__restrict__ doms, int ndom, int i0, int i1,
+                                                       const uint32_t *__restrict__ skey, const float4 *__restrict__ soff,
+                                                       const uint32_t *__restrict__ sct, const uint32_t *__restrict__ sid,
+                                                       float *__restrict__ pos, int32_t *__restrict__ type) {
+  const int i = i0 + blockIdx.x * kBlock + threadIdx.x;
+  if (i >= i1) return;
+  const DomDev &dd = doms[domain_of(doms, ndom, i)];
   int c[3];
-  unpack_key<D>(skey[i], k, mask, c);
+  unpack_key<D>(skey[i] - dd.cellbase, dd.g.k, dd.g.xmask, c);
   const float4 o = soff[i];
   const float oo[3] = {o.x, o.y, o.z};
-  const double lo[3] = {lo0, lo1, lo2};
   const uint32_t id = sid[i];
-  if (pos)
-    for (int a = 0; a < D; ++a) pos[(size_t)id * D + a] = (float)(lo[a] + ((double)c[a] + (double)oo[a]) * cs);
+  if (pos) {
+    float *x = pos + dd.xoff + (int64_t)((int)id - dd.uoff) * D;
+    for (int a = 0; a < D; ++a) x[a] = (float)(dd.lo[a] + ((double)c[a] + (double)oo[a]) * dd.cs);
+  }
   if (type) type[id] = (int32_t)(sct[i] & 3u);
 }
 
-// Scatter one per-particle quantity of the last step to load order, converted to domain units.
+// Scatter one per-particle quantity of the last step to load order, converted to domain units;
+// sorted indices [i0, i1).  vscale[d] multiplies vector quantities (dt1 / 2 of the domain for
+// v~; NULL: 1).
 template <int D>
-__global__ __launch_bounds__(kBlock) void dump_kernel(int n, int which, int k, uint32_t mask, double lo0, double lo1,
-                                                      double lo2, double cs, float tau, const uint32_t *__restrict__ wkey,
+__global__ __launch_bounds__(kBlock) void dump_kernel(const DomDev *__restrict__ doms, int ndom, int i0, int i1,
+                                                      int which, const uint32_t *__restrict__ wkey,
                                                       const float4 *__restrict__ wpos, const uint32_t *__restrict__ wid,
                                                       const float *__restrict__ sc, const float4 *__restrict__ vec,
-                                                      float vscale, float *__restrict__ out) {
-  int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+                                                      const float *__restrict__ vscale, float *__restrict__ out) {
+  const int i = i0 + blockIdx.x * kBlock + threadIdx.x;
+  if (i >= i1) return;
+  const int d = domain_of(doms, ndom, i);
+  const DomDev &dd = doms[d];
   const uint32_t id = wid[i];
+  float *ov = out + dd.xoff + (int64_t)((int)id - dd.uoff) * D;  // row of a vector quantity
   const float4 p = wpos[i];
-  const double csd = cs;
+  const double csd = dd.cs;
   switch (which) {
     case MPSPH_F_RHO:
       out[id] = (float)((double)sc[i] / pow(csd, D));
       break;
     case MPSPH_F_RHO_T: {
-      double s = (double)p.w / tau * csd;
+      const double s = (double)p.w / dd.sp.tau * csd;
       out[id] = (float)pow(s, -D);
       break;
     }
@@ -676,16 +701,16 @@ __global__ __launch_bounds__(kBlock) void dump_kernel(int n, int which, int k, u
       break;
     case MPSPH_F_X0: {
       int c[3];
-      unpack_key<D>(wkey[i], k, mask, c);
+      unpack_key<D>(wkey[i] - dd.cellbase, dd.g.k, dd.g.xmask, c);
       const float oo[3] = {p.x, p.y, p.z};
-      const double lo[3] = {lo0, lo1, lo2};
-      for (int a = 0; a < D; ++a) out[(size_t)id * D + a] = (float)(lo[a] + ((double)c[a] + (double)oo[a]) * csd);
+      for (int a = 0; a < D; ++a) ov[a] = (float)(dd.lo[a] + ((double)c[a] + (double)oo[a]) * csd);
       break;
     }
     default: {  // vector quantities in cell units per time: scale by cs (and vscale)
       const float4 v = vec[i];
       const float vv[3] = {v.x, v.y, v.z};
-      for (int a = 0; a < D; ++a) out[(size_t)id * D + a] = (float)((double)(vv[a] * vscale) * csd);
+      const float f = vscale ? vscale[d] : 1.f;
+      for (int a = 0; a < D; ++a) ov[a] = (float)((double)(vv[a] * f) * csd);
     }
   }
 }
@@ -695,19 +720,6 @@ __global__ __launch_bounds__(kBlock) void dump_kernel(int n, int which, int k, u
 // ------------------------------------------------------------------------------------------
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
-
-struct Layout {
-  int dim = 0, k = 0;
-  int64_t n = 0;
-  uint32_t ncells = 0;
-  int nblocks = 0;
-  int nblocks_pair = 0;
-  size_t bytes = 0;
-  // offsets
-  size_t partials2;
-  size_t s_key, s_off, s_ct, s_id, w_key, w_pos, w_jaux, w_id, k0, v0, k1, v1, hist, cstart, acc, rho, nn, aabs, at, v,
-      dr, partials, metrics, dtcells, bad, rbf_c, rbf_o, rbf_k;
-};
 
 struct Derived {
   int dim, k, gmax;
@@ -939,53 +951,6 @@ int derive(const mpsph_params *p, int64_t n, double s0, Derived *d) {
   return MPSPH_OK;
 }
 
-Layout make_layout(int dim, int k, int64_t n, int n_rbf) {
-  Layout L;
-  L.dim = dim;
-  L.k = k;
-  L.n = n;
-  L.ncells = (uint32_t)1u << (dim * k);
-  L.nblocks = (int)std::max<int64_t>(1, (n + kBlock - 1) / kBlock);
-  L.nblocks_pair = (int)std::max<int64_t>(1, (n * MPSPH_LANES + kBlock - 1) / kBlock);
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    size_t at = o;
-    o += align_up(std::max<size_t>(bytes, 4));
-    return at;
-  };
-  size_t nn = (size_t)std::max<int64_t>(n, 1);
-  L.s_key = take(nn * 4);
-  L.s_off = take(nn * 16);
-  L.s_ct = take(nn * 4);
-  L.s_id = take(nn * 4);
-  L.w_key = take(nn * 4);
-  L.w_pos = take(nn * 16);
-  L.w_jaux = take(nn * 4);
-  L.w_id = take(nn * 4);
-  L.k0 = take(nn * 4);
-  L.v0 = take(nn * 4);
-  L.k1 = take(nn * 4);
-  L.v1 = take(nn * 4);
-  L.hist = take(radix_hist_words((int)n) * 4);
-  L.cstart = take(((size_t)L.ncells + 1) * 4);
-  L.acc = take(nn * 16);
-  L.rho = take(nn * 4);
-  L.nn = take(nn * 4);
-  L.aabs = take(nn * 4);
-  L.at = take(nn * 16);
-  L.v = take(nn * 16);
-  L.dr = take(nn * 16);
-  L.partials = take((size_t)L.nblocks_pair * kNumPartials * 8);
-  L.partials2 = take((size_t)kReduceBlocks * kNumPartials * 8);
-  L.metrics = take(32 * 8);
-  L.dtcells = take(kDtSlots * 4);
-  L.bad = take(4);
-  L.rbf_c = take((size_t)std::max(n_rbf, 1) * 3 * 4);
-  L.rbf_o = take((size_t)std::max(n_rbf, 1) * 3 * 4);
-  L.rbf_k = take((size_t)std::max(n_rbf, 1) * 4);
-  L.bytes = o;
-  return L;
-}
 
 struct EventHook : LaunchHook {
   struct Rec {
@@ -1053,40 +1018,6 @@ struct EventHook : LaunchHook {
   }
 };
 
-}  // namespace
-
-struct mpsph_ctx {
-  mpsph_params p{};
-  std::vector<double> rbf_centre, rbf_coeff;
-  Derived d{};
-  Layout L;
-  hipStream_t stream = nullptr;
-  char *ws = nullptr;
-  bool owns = false;
-  bool loaded = false;
-  bool poisoned = false;
-  int64_t steps_done = 0;
-  double s0 = 0;
-  GridDev g{};
-  FieldDev f{};
-  EventHook hook;
-  template <typename T>
-  T *at(size_t off) {
-    return reinterpret_cast<T *>(ws + off);
-  }
-};
-
-namespace {
-
-int fail(mpsph_ctx *c, int code) {
-  if (c && code == MPSPH_E_DEVICE) c->poisoned = true;
-  return code;
-}
-
-#define HIP_OK(expr)                                       \
-  do {                                                     \
-    if ((expr) != hipSuccess) return fail(ctx, MPSPH_E_DEVICE); \
-  } while (0)
 
 void split_cell(double X, int *c, float *o) {
   double f = std::floor(X);
@@ -1098,6 +1029,7 @@ void split_cell(double X, int *c, float *o) {
   }
 }
 
+// Surface-tension strength reported for a step (the kernels evaluate the same ramp in FP32).
 double sigma_at(const mpsph_params *p, int64_t step) {
   if (p->t0 < 0) return p->sigma0;
   double t = (double)step, t0 = (double)p->t0, t1 = (double)p->t1;
@@ -1116,76 +1048,425 @@ double dt2_factor(const mpsph_params *p) {
   return std::min(1.0, 2.0 * c / (p->c_acc * p->c_acc));
 }
 
-template <int D>
-int run_steps(mpsph_ctx *ctx, int nsteps) {
-  const int n = (int)ctx->L.n;
-  const Layout &L = ctx->L;
-  hipStream_t st = ctx->stream;
-  const int nb = L.nblocks;
-  const int nbp = L.nblocks_pair;  // blocks of the pair kernels: MPSPH_LANES lanes per particle
-  (void)nb;
-  const double cs = ctx->d.cs;
-  StepDev sp;
-  sp.kappa = (float)ctx->p.kappa;
-  sp.tau = (float)ctx->p.tau;
-  sp.inv_tau = (float)(1.0 / ctx->p.tau);
-  sp.p0c = (float)(ctx->p.p0 * std::pow(cs, D - 2));
-  sp.nu_coeff = (float)ctx->p.nu_coeff;
-  sp.c_acc = (float)ctx->p.c_acc;
-  sp.c_vel = (float)ctx->p.c_vel;
-  sp.c_visc = (float)ctx->p.c_visc;
-  sp.search_fac = (float)ctx->d.search_fac;
-  sp.hmax = (float)(ctx->p.tau * ctx->d.smax / cs * (1.0 + 1e-5));
+// One domain of a context: its parameters (RBF arrays copied), derived grid and device constants.
+struct Domain {
+  mpsph_params p{};
+  std::vector<double> rbf_centre, rbf_coeff;
+  Derived d{};
+  double s0 = 0;
+  int64_t n = 0, off = 0;
+  uint32_t ncells = 0, cellbase = 0;
+  int blk0 = 0, nblk = 0, row0 = 0, nrow = 0;
+  size_t rbf0 = 0;  // first RBF term of this domain in the packed RBF arrays
+  int uidx = 0;     // index of the domain in the caller's list
+  int64_t uoff = 0, xoff = 0;  // first row / first float of the domain in the caller's arrays
+};
+
+// Domains of one dimension occupy consecutive internal domain, particle and block ranges.
+struct Group {
+  int D = 0;
+  int d0 = 0, nd = 0;   // internal domains
+  int i0 = 0, i1 = 0;   // internal particles
+  int b0 = 0, nb = 0;   // pair-kernel blocks
+};
+
+// Parameters copied into a domain; s0 normalised and the grid derived.  n is the domain's count.
+int make_domain(const mpsph_params *params, int64_t n, Domain *dm) {
+  if (!valid_params(params) || n < 0 || n > (int64_t)1 << 30) return MPSPH_E_INVALID;
+  dm->p = *params;
+  dm->n = n;
+  if (params->field == MPSPH_RBF_EXP && params->n_rbf > 0) {
+    dm->rbf_centre.assign(params->rbf_centre, params->rbf_centre + params->n_rbf * params->dim);
+    dm->rbf_coeff.assign(params->rbf_coeff, params->rbf_coeff + params->n_rbf);
+    dm->p.rbf_centre = dm->rbf_centre.data();
+    dm->p.rbf_coeff = dm->rbf_coeff.data();
+  } else {
+    dm->p.n_rbf = 0;
+    dm->p.rbf_centre = nullptr;
+    dm->p.rbf_coeff = nullptr;
+  }
+  double s0 = params->s0;
+  if (!(s0 > 0)) {
+    double I = field_integral_unit(&dm->p);
+    if (!(I > 0) || !std::isfinite(I)) return MPSPH_E_INVALID;
+    s0 = std::pow(I / (double)std::max<int64_t>(n, 1), 1.0 / params->dim);
+  }
+  dm->s0 = s0;
+  int rc = derive(&dm->p, n, s0, &dm->d);
+  if (rc) return rc;
+  dm->ncells = (uint32_t)1u << (params->dim * dm->d.k);
+  return MPSPH_OK;
+}
+
+// Workspace layout of a context (byte offsets, 256-aligned).
+struct Layout {
+  int ndom = 0;
+  Group grp[2];  // 2D domains, then 3D domains
+  std::vector<int> internal;  // caller's domain index -> internal index
+  int64_t n = 0;
+  uint32_t ncells = 0;  // cells of all domains
+  int key_bits = 0;
+  int nblocks_pair = 0, nrows = 0;
+  int64_t chunk = 1;  // block partials per first-level reduction row
+  size_t n_rbf = 0;
+  size_t bytes = 0;
+  size_t s_key, s_off, s_ct, s_id, w_key, w_pos, w_jaux, w_id, k0, v0, k1, v1, hist, cstart, acc, rho, nn, aabs, at, v,
+      dr, partials, partials2, groups, metrics, dtslots, stepctr, bad, doms, vscale, rbf_c, rbf_o, rbf_k;
+};
+
+// Orders the domains internally (2D before 3D, otherwise as given), assigns particle offsets,
+// cell bases, pair-kernel blocks and reduction rows, and lays out the workspace.
+int plan(std::vector<Domain> &doms, Layout *out) {
+  Layout L;
+  L.ndom = (int)doms.size();
+  int64_t uoff = 0, xoff = 0;
+  for (int d = 0; d < L.ndom; ++d) {
+    doms[d].uidx = d;
+    doms[d].uoff = uoff;
+    doms[d].xoff = xoff;
+    uoff += doms[d].n;
+    xoff += doms[d].n * doms[d].p.dim;
+  }
+  std::stable_sort(doms.begin(), doms.end(), [](const Domain &a, const Domain &b) { return a.p.dim < b.p.dim; });
+  L.internal.assign(L.ndom, 0);
+  for (int d = 0; d < L.ndom; ++d) L.internal[doms[d].uidx] = d;
+  uint64_t cells = 0;
+  int64_t n = 0;
+  int64_t blocks = 0;
+  size_t nrbf = 0;
+  for (int gi = 0; gi < 2; ++gi) {
+    L.grp[gi].D = 2 + gi;
+    L.grp[gi].d0 = 0;
+  }
+  for (int d = 0; d < L.ndom; ++d) {
+    Domain &dm = doms[d];
+    Group &g = L.grp[dm.p.dim - 2];
+    if (g.nd == 0) {
+      g.d0 = d;
+      g.i0 = g.i1 = (int)n;
+      g.b0 = (int)blocks;
+    }
+    dm.off = n;
+    dm.cellbase = (uint32_t)cells;
+    dm.blk0 = (int)blocks;
+    dm.nblk = (int)((dm.n * MPSPH_LANES + kBlock - 1) / kBlock);
+    dm.rbf0 = nrbf;
+    n += dm.n;
+    cells += dm.ncells;
+    blocks += dm.nblk;
+    nrbf += (size_t)dm.p.n_rbf;
+    if (n > ((int64_t)1 << 30) || cells > ((uint64_t)1 << 28) || blocks > ((int64_t)1 << 30))
+      return MPSPH_E_UNSUPPORTED;
+    g.nd += 1;
+    g.i1 = (int)n;
+    g.nb += dm.nblk;
+  }
+  // first-level reduction: rows of at most `chunk` block partials, never straddling domains
+  const int64_t chunk = std::max<int64_t>(1, (blocks + kReduceBlocks - 1) / kReduceBlocks);
+  int rows = 0;
+  for (auto &dm : doms) {
+    dm.row0 = rows;
+    dm.nrow = (int)((dm.nblk + chunk - 1) / chunk);
+    rows += dm.nrow;
+  }
+  L.n = n;
+  L.ncells = (uint32_t)cells;
+  L.key_bits = 1;
+  while (((uint64_t)1 << L.key_bits) < cells) ++L.key_bits;
+  L.nblocks_pair = (int)blocks;
+  L.nrows = rows;
+  L.chunk = chunk;
+  L.n_rbf = nrbf;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(std::max<size_t>(bytes, 4));
+    return at;
+  };
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  L.s_key = take(nn * 4);
+  L.s_off = take(nn * 16);
+  L.s_ct = take(nn * 4);
+  L.s_id = take(nn * 4);
+  L.w_key = take(nn * 4);
+  L.w_pos = take(nn * 16);
+  L.w_jaux = take(nn * 4);
+  L.w_id = take(nn * 4);
+  L.k0 = take(nn * 4);
+  L.v0 = take(nn * 4);
+  L.k1 = take(nn * 4);
+  L.v1 = take(nn * 4);
+  L.hist = take(radix_hist_words((int)n) * 4);
+  L.cstart = take(((size_t)L.ncells + 1) * 4);
+  L.acc = take(nn * 16);
+  L.rho = take(nn * 4);
+  L.nn = take(nn * 4);
+  L.aabs = take(nn * 4);
+  L.at = take(nn * 16);
+  L.v = take(nn * 16);
+  L.dr = take(nn * 16);
+  L.partials = take((size_t)std::max(L.nblocks_pair, 1) * kNumPartials * 8);
+  L.partials2 = take((size_t)std::max(L.nrows, 1) * kNumPartials * 8);
+  L.groups = take((size_t)std::max(L.nrows, 1) * sizeof(int2));
+  L.metrics = take((size_t)L.ndom * 32 * 8);
+  L.dtslots = take((size_t)L.ndom * kDtSlots * 4);
+  L.stepctr = take(8);
+  L.bad = take(4);
+  L.doms = take((size_t)L.ndom * sizeof(DomDev));
+  L.vscale = take((size_t)L.ndom * 4);
+  L.rbf_c = take(std::max<size_t>(nrbf, 1) * 3 * 4);
+  L.rbf_o = take(std::max<size_t>(nrbf, 1) * 3 * 4);
+  L.rbf_k = take(std::max<size_t>(nrbf, 1) * 4);
+  L.bytes = o;
+  *out = L;
+  return MPSPH_OK;
+}
+
+// Device constants of a domain (grid, region and field in cell units; step constants).
+DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, const float *rbf_k) {
+  const mpsph_params &p = dm.p;
+  const double cs = dm.d.cs, ics = dm.d.inv_cs;
+  const int D = p.dim;
+  DomDev dd;
+  std::memset(&dd, 0, sizeof(dd));
+  GridDev &g = dd.g;
+  g.k = dm.d.k;
+  g.n = (int)(dm.off + dm.n);
+  g.gmax = dm.d.gmax;
+  g.xmask = (uint32_t)dm.d.gmax;
+  g.geometry = p.geometry;
+  for (int a = 0; a < 3; ++a) {
+    double Xhi = a < D ? (p.hi[a] - p.lo[a]) * ics : 0.0;
+    split_cell(Xhi, &g.whi_c[a], &g.whi_o[a]);
+    if (g.whi_c[a] > g.gmax) {
+      g.whi_c[a] = g.gmax;
+      g.whi_o[a] = 0.f;
+    }
+    double Xc = a < D ? (p.centre[a] - p.lo[a]) * ics : 0.0;
+    split_cell(Xc, &g.gc_c[a], &g.gc_o[a]);
+  }
+  g.r_in = (float)(p.r_in * ics);
+  g.r_out = (float)(p.r_out * ics);
+  FieldDev &f = dd.f;
+  f.kind = p.field;
+  f.s0 = (float)(dm.s0 * ics);
+  f.g = (float)(p.fa * cs);
+  f.b = (float)(p.fb * ics);
+  for (int a = 0; a < 3; ++a) {
+    double Xc = a < D ? (p.fcentre[a] - p.lo[a]) * ics : 0.0;
+    split_cell(Xc, &f.fc_c[a], &f.fc_o[a]);
+  }
+  f.n_rbf = p.n_rbf;
+  f.e2 = p.field == MPSPH_RBF_EXP ? (float)(cs * cs / (2.0 * p.rbf_width * p.rbf_width)) : 0.f;
+  f.rbf_c = rbf_c + 3 * dm.rbf0;
+  f.rbf_o = rbf_o + 3 * dm.rbf0;
+  f.rbf_k = rbf_k + dm.rbf0;
+  StepDev &sp = dd.sp;
+  sp.kappa = (float)p.kappa;
+  sp.tau = (float)p.tau;
+  sp.inv_tau = (float)(1.0 / p.tau);
+  sp.p0c = (float)(p.p0 * std::pow(cs, D - 2));
+  sp.nu_coeff = (float)p.nu_coeff;
+  sp.c_acc = (float)p.c_acc;
+  sp.c_vel = (float)p.c_vel;
+  sp.c_visc = (float)p.c_visc;
+  sp.search_fac = (float)dm.d.search_fac;
+  sp.hmax = (float)(p.tau * dm.d.smax / cs * (1.0 + 1e-5));
   sp.alpha = (float)(D == 2 ? 7.0 / (4.0 * M_PI) : 21.0 / (16.0 * M_PI));
-  sp.dt2_factor = (float)dt2_factor(&ctx->p);
-  const bool dbg = ctx->p.debug != 0;
-  EventHook *hk = ctx->hook.on ? &ctx->hook : nullptr;
+  sp.dt2_factor = (float)dt2_factor(&p);
+  sp.sigma0 = (float)p.sigma0;
+  sp.t0 = p.t0 < 0 ? -1.f : (float)p.t0;
+  sp.t1 = (float)p.t1;
+  dd.cellbase = dm.cellbase;
+  dd.off = (int)dm.off;
+  dd.n = (int)dm.n;
+  dd.uoff = (int)dm.uoff;
+  dd.xoff = dm.xoff;
+  dd.blk0 = dm.blk0;
+  dd.nblk = dm.nblk;
+  dd.row0 = dm.row0;
+  dd.nrow = dm.nrow;
+  for (int a = 0; a < 3; ++a) {
+    dd.lo[a] = dm.d.lo[a];
+    dd.xhi[a] = dm.d.xhi[a];
+  }
+  dd.cs = cs;
+  dd.inv_cs = ics;
+  return dd;
+}
+
+}  // namespace
+
+struct mpsph_ctx {
+  std::vector<Domain> dom;
+  Layout L;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  bool owns = false;
+  bool loaded = false;
+  bool poisoned = false;
+  int64_t steps_done = 0;
+  EventHook hook;
+  // step graph: nsteps steps captured once on a private stream, replayed on `stream`
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int32_t graph_steps = 0;
+  template <typename T>
+  T *at(size_t off) {
+    return reinterpret_cast<T *>(ws + off);
+  }
+};
+
+namespace {
+
+int fail(mpsph_ctx *c, int code) {
+  if (c && code == MPSPH_E_DEVICE) c->poisoned = true;
+  return code;
+}
+
+#define HIP_OK(expr)                                            \
+  do {                                                          \
+    if ((expr) != hipSuccess) return fail(ctx, MPSPH_E_DEVICE); \
+  } while (0)
+
+// Kernels of one step for one dimension group.
+template <int D>
+void launch_group(mpsph_ctx *ctx, const Group &gr, const uint32_t *skeys, const uint32_t *perm, int nreset,
+                  hipStream_t st, EventHook *hk) {
+  const Layout &L = ctx->L;
+  const int n = (int)L.n;
+  const DomDev *doms = ctx->at<DomDev>(L.doms) + gr.d0;
+  if (hk) hk->begin("reorder_field");
+  const int nthr = std::max(gr.i1 - gr.i0 + (gr.i1 == n ? 1 : 0), nreset);
+  reorder_field<D><<<(nthr + kBlock - 1) / kBlock, kBlock, 0, st>>>(
+      doms, gr.nd, gr.i0, gr.i1, n, L.ncells, nreset, skeys, perm, ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct),
+      ctx->at<uint32_t>(L.s_id), ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
+      ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<uint32_t>(L.dtslots));
+  if (hk) hk->end();
+}
+
+template <int D>
+void launch_pass1(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk) {
+  const Layout &L = ctx->L;
+  const bool dbg = ctx->dom[0].p.debug != 0;
+  if (hk) hk->begin("pass_density_force");
+  pass_density_force<D, MPSPH_LANES><<<gr.nb, kBlock, 0, st>>>(
+      ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.b0, ctx->at<int64_t>(L.stepctr), ctx->at<uint32_t>(L.w_key),
+      ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
+      dbg ? ctx->at<float>(L.rho) : nullptr, dbg ? ctx->at<float>(L.nn) : nullptr,
+      dbg ? ctx->at<float>(L.aabs) : nullptr, ctx->at<uint32_t>(L.dtslots) + (size_t)gr.d0 * kDtSlots,
+      ctx->at<double>(L.partials));
+  if (hk) hk->end();
+}
+
+template <int D>
+void launch_pass2(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk) {
+  const Layout &L = ctx->L;
+  const bool dbg = ctx->dom[0].p.debug != 0;
+  if (hk) hk->begin("pass_viscous_integrate");
+  pass_viscous_integrate<D, MPSPH_LANES><<<gr.nb, kBlock, 0, st>>>(
+      ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.b0, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
+      ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
+      ctx->at<uint32_t>(L.dtslots) + (size_t)gr.d0 * kDtSlots, ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off),
+      ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), dbg ? ctx->at<float4>(L.at) : nullptr,
+      dbg ? ctx->at<float4>(L.v) : nullptr, dbg ? ctx->at<float4>(L.dr) : nullptr, ctx->at<double>(L.partials));
+  if (hk) hk->end();
+}
+
+// Enqueues nsteps steps of every domain on stream st.  No host synchronisation, no memset and
+// no host-side state read, so the same launches can be captured into a graph and replayed.
+// Each kernel is launched once per non-empty dimension group.
+int enqueue(mpsph_ctx *ctx, int nsteps, hipStream_t st, EventHook *hk) {
+  const Layout &L = ctx->L;
+  const int n = (int)L.n, ndom = L.ndom;
   for (int s = 0; s < nsteps; ++s) {
-    sp.sigma = (float)sigma_at(&ctx->p, ctx->steps_done);
     if (n > 0) {
       const uint32_t *skeys = nullptr, *perm = nullptr;
       if (radix_sort(ctx->at<uint32_t>(L.s_key), ctx->at<uint32_t>(L.k0), ctx->at<uint32_t>(L.v0),
-                     ctx->at<uint32_t>(L.k1), ctx->at<uint32_t>(L.v1), ctx->at<uint32_t>(L.hist), n, D * ctx->d.k, st,
+                     ctx->at<uint32_t>(L.k1), ctx->at<uint32_t>(L.v1), ctx->at<uint32_t>(L.hist), n, L.key_bits, st,
                      &skeys, &perm, hk) != hipSuccess)
         return fail(ctx, MPSPH_E_DEVICE);
-      if (hk) hk->begin("reorder_field");
-      reorder_field<D><<<(n + 1 + kBlock - 1) / kBlock, kBlock, 0, st>>>(
-          n, L.ncells, ctx->g, ctx->f, (float)ctx->p.tau, skeys, perm, ctx->at<float4>(L.s_off),
-          ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
-          ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart),
-          ctx->at<uint32_t>(L.dtcells));
-      if (hk) hk->end();
-      if (hk) hk->begin("pass_density_force");
-      pass_density_force<D, MPSPH_LANES><<<nbp, kBlock, 0, st>>>(
-          n, ctx->g, sp, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
-          ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc), dbg ? ctx->at<float>(L.rho) : nullptr,
-          dbg ? ctx->at<float>(L.nn) : nullptr, dbg ? ctx->at<float>(L.aabs) : nullptr,
-          ctx->at<uint32_t>(L.dtcells), ctx->at<double>(L.partials));
-      if (hk) hk->end();
-      if (hk) hk->begin("pass_viscous_integrate");
-      pass_viscous_integrate<D, MPSPH_LANES><<<nbp, kBlock, 0, st>>>(
-          n, ctx->g, sp, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
-          ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
-          ctx->at<uint32_t>(L.dtcells), ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off),
-          ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), dbg ? ctx->at<float4>(L.at) : nullptr,
-          dbg ? ctx->at<float4>(L.v) : nullptr, dbg ? ctx->at<float4>(L.dr) : nullptr, ctx->at<double>(L.partials));
-      if (hk) hk->end();
+      int nreset = ndom * kDtSlots;  // the first launch resets every domain's time-step slots
+      for (const Group &gr : L.grp) {
+        if (gr.i1 <= gr.i0) continue;
+        if (gr.D == 2) launch_group<2>(ctx, gr, skeys, perm, nreset, st, hk);
+        else launch_group<3>(ctx, gr, skeys, perm, nreset, st, hk);
+        nreset = 0;
+      }
+      for (const Group &gr : L.grp) {
+        if (gr.nb <= 0) continue;
+        if (gr.D == 2) launch_pass1<2>(ctx, gr, st, hk);
+        else launch_pass1<3>(ctx, gr, st, hk);
+      }
+      for (const Group &gr : L.grp) {
+        if (gr.nb <= 0) continue;
+        if (gr.D == 2) launch_pass2<2>(ctx, gr, st, hk);
+        else launch_pass2<3>(ctx, gr, st, hk);
+      }
     }
     if (hk) hk->begin("finalize");
-    {
-      const int rows = n > 0 ? nbp : 0;
-      const int chunk = (rows + kReduceBlocks - 1) / kReduceBlocks;
-      const int nred = rows > 0 ? (rows + chunk - 1) / chunk : 0;
-      if (nred > 0)
-        reduce_partials<<<nred, 256, 0, st>>>(rows, chunk, ctx->at<double>(L.partials), ctx->at<double>(L.partials2));
-      finalize<<<1, 256, 0, st>>>(nred, ctx->at<double>(L.partials2), ctx->at<uint32_t>(L.dtcells), sp.dt2_factor,
-                                  ctx->at<double>(L.metrics));
-    }
+    if (L.nrows > 0)
+      reduce_partials<<<L.nrows, 256, 0, st>>>(ctx->at<int2>(L.groups), ctx->at<double>(L.partials),
+                                               ctx->at<double>(L.partials2));
+    finalize<<<ndom, 256, 0, st>>>(ctx->at<DomDev>(L.doms), ctx->at<double>(L.partials2), ctx->at<uint32_t>(L.dtslots),
+                                   ctx->at<double>(L.metrics), ctx->at<int64_t>(L.stepctr));
     if (hk) hk->end();
     if (hipGetLastError() != hipSuccess) return fail(ctx, MPSPH_E_DEVICE);
-    ctx->steps_done += 1;
   }
   return MPSPH_OK;
+}
+
+void drop_graph(mpsph_ctx *ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  ctx->graph_exec = nullptr;
+  ctx->graph_steps = 0;
+}
+
+void fill_metrics(const mpsph_ctx *ctx, int dmi, const double *m, mpsph_metrics_t *out) {
+  const Domain &dm = ctx->dom[dmi];
+  const double cs = dm.d.cs;
+  std::memset(out, 0, sizeof(*out));
+  out->step = ctx->steps_done - 1;
+  out->pairs = (int64_t)m[P_PAIRS];
+  out->interface_pairs = (int64_t)m[P_IFC] / 2;
+  out->candidates = (int64_t)m[P_CAND];
+  out->n_normal = (int64_t)m[P_NNORM];
+  out->n_elr = (int64_t)m[P_NELR];
+  out->nonfinite = (int64_t)(m[P_NONFIN1] + m[P_NONFIN2]);
+  out->n_feature = (int64_t)m[P_NFEAT];
+  out->residual_l2 = m[P_NNORM] > 0 ? std::sqrt(m[P_E2] / m[P_NNORM]) : 0.0;
+  out->residual_linf = m[P_EMAX];
+  out->pairs_total = (int64_t)m[18];
+  out->candidates_total = (int64_t)m[19];
+  out->kinetic = m[P_KE] * cs * cs;
+  out->dt1 = m[16];
+  out->dt2 = m[17];
+  out->sigma = sigma_at(&dm.p, std::max<int64_t>(ctx->steps_done - 1, 0));
+  if (m[P_NELR] > 0) {
+    double mean = m[P_ELR] / m[P_NELR];
+    out->elr_mean = mean;
+    out->elr_std = std::sqrt(std::max(0.0, m[P_ELR2] / m[P_NELR] - mean * mean));
+    out->elr_min = m[P_ELRMIN];
+    out->elr_max = m[P_ELRMAX];
+  }
+}
+
+int batch_check(int32_t ndom, const mpsph_params *params, const int64_t *n) {
+  if (ndom < 1 || ndom > 4096 || !params || !n) return MPSPH_E_INVALID;
+  for (int d = 0; d < ndom; ++d) {
+    if (!valid_params(&params[d]) || n[d] < 0 || n[d] > (int64_t)1 << 30) return MPSPH_E_INVALID;
+    if (params[d].debug != params[0].debug) return MPSPH_E_INVALID;
+  }
+  return MPSPH_OK;
+}
+
+int build_domains(int32_t ndom, const mpsph_params *params, const int64_t *n, std::vector<Domain> *doms, Layout *L) {
+  int rc = batch_check(ndom, params, n);
+  if (rc) return rc;
+  doms->resize(ndom);
+  for (int d = 0; d < ndom; ++d)
+    if ((rc = make_domain(&params[d], n[d], &(*doms)[d])) != MPSPH_OK) return rc;
+  return plan(*doms, L);
 }
 
 }  // namespace
@@ -1205,202 +1486,189 @@ int mpsph_field_scale(const mpsph_params *params, int64_t n, double *s0_out) {
   return MPSPH_OK;
 }
 
-size_t mpsph_workspace_bytes(const mpsph_params *params, int64_t n) {
-  if (!valid_params(params) || n < 0 || n > (int64_t)1 << 30) return 0;
-  double s0 = params->s0;
-  if (!(s0 > 0) && mpsph_field_scale(params, std::max<int64_t>(n, 1), &s0) != MPSPH_OK) return 0;
-  Derived d;
-  if (derive(params, n, s0, &d) != MPSPH_OK) return 0;
-  return make_layout(params->dim, d.k, n, params->n_rbf).bytes;
+size_t mpsph_batch_workspace_bytes(int32_t ndom, const mpsph_params *params, const int64_t *n) {
+  std::vector<Domain> doms;
+  Layout L;
+  if (build_domains(ndom, params, n, &doms, &L) != MPSPH_OK) return 0;
+  return L.bytes;
 }
 
-int mpsph_create(const mpsph_params *params, int64_t n, void *d_workspace, size_t workspace_bytes, void *hip_stream,
-                 mpsph_ctx **out) {
+size_t mpsph_workspace_bytes(const mpsph_params *params, int64_t n) {
+  return mpsph_batch_workspace_bytes(1, params, &n);
+}
+
+int mpsph_batch_create(int32_t ndom, const mpsph_params *params, const int64_t *n, void *d_workspace,
+                       size_t workspace_bytes, void *hip_stream, mpsph_ctx **out) {
   if (!out) return MPSPH_E_INVALID;
   *out = nullptr;
-  if (!valid_params(params) || n < 0 || n > (int64_t)1 << 30) return MPSPH_E_INVALID;
   mpsph_ctx *ctx = new (std::nothrow) mpsph_ctx();
   if (!ctx) return MPSPH_E_NOMEM;
-  ctx->p = *params;
-  if (params->field == MPSPH_RBF_EXP && params->n_rbf > 0) {
-    ctx->rbf_centre.assign(params->rbf_centre, params->rbf_centre + params->n_rbf * params->dim);
-    ctx->rbf_coeff.assign(params->rbf_coeff, params->rbf_coeff + params->n_rbf);
-    ctx->p.rbf_centre = ctx->rbf_centre.data();
-    ctx->p.rbf_coeff = ctx->rbf_coeff.data();
-  } else {
-    ctx->p.n_rbf = params->field == MPSPH_RBF_EXP ? 0 : params->n_rbf;
-    ctx->p.rbf_centre = nullptr;
-    ctx->p.rbf_coeff = nullptr;
-    if (params->field != MPSPH_RBF_EXP) ctx->p.n_rbf = 0;
-  }
-  double s0 = params->s0;
-  if (!(s0 > 0)) {
-    int rc = mpsph_field_scale(&ctx->p, std::max<int64_t>(n, 1), &s0);
-    if (rc) {
-      delete ctx;
-      return rc;
-    }
-  }
-  ctx->s0 = s0;
-  int rc = derive(&ctx->p, n, s0, &ctx->d);
+  int rc = build_domains(ndom, params, n, &ctx->dom, &ctx->L);
   if (rc) {
     delete ctx;
     return rc;
   }
-  ctx->L = make_layout(params->dim, ctx->d.k, n, ctx->p.n_rbf);
+  const Layout &L = ctx->L;
   ctx->stream = (hipStream_t)hip_stream;
   ctx->hook.stream = ctx->stream;
   if (d_workspace) {
-    if (workspace_bytes < ctx->L.bytes || ((uintptr_t)d_workspace & 255)) {
+    if (workspace_bytes < L.bytes || ((uintptr_t)d_workspace & 255)) {
       delete ctx;
       return MPSPH_E_NOMEM;
     }
     ctx->ws = (char *)d_workspace;
   } else {
-    if (hipMalloc((void **)&ctx->ws, ctx->L.bytes) != hipSuccess) {
+    if (hipMalloc((void **)&ctx->ws, L.bytes) != hipSuccess) {
       delete ctx;
       return MPSPH_E_NOMEM;
     }
     ctx->owns = true;
   }
   // a zeroed workspace keeps every table entry a valid index before its first write
-  if (hipMemset(ctx->ws, 0, ctx->L.bytes) != hipSuccess) {
+  if (hipMemset(ctx->ws, 0, L.bytes) != hipSuccess) {
     mpsph_destroy(ctx);
     return MPSPH_E_DEVICE;
   }
-  // grid and region in cell units
-  const double cs = ctx->d.cs, ics = ctx->d.inv_cs;
-  GridDev &g = ctx->g;
-  g.k = ctx->d.k;
-  g.n = (int)n;
-  g.gmax = ctx->d.gmax;
-  g.xmask = (uint32_t)ctx->d.gmax;
-  g.geometry = params->geometry;
-  for (int a = 0; a < 3; ++a) {
-    double Xhi = a < params->dim ? (params->hi[a] - params->lo[a]) * ics : 0.0;
-    split_cell(Xhi, &g.whi_c[a], &g.whi_o[a]);
-    if (g.whi_c[a] > g.gmax) {
-      g.whi_c[a] = g.gmax;
-      g.whi_o[a] = 0.f;
+  // domain table, reduction row groups, RBF terms in cell units
+  std::vector<DomDev> dd(ndom);
+  std::vector<int2> groups;
+  std::vector<int> rc3(3 * std::max<size_t>(L.n_rbf, 1), 0);
+  std::vector<float> ro3(3 * std::max<size_t>(L.n_rbf, 1), 0.f), rk(std::max<size_t>(L.n_rbf, 1), 0.f);
+  for (int d = 0; d < ndom; ++d) {
+    const Domain &dm = ctx->dom[d];
+    dd[d] = domain_device(dm, ctx->at<int>(L.rbf_c), ctx->at<float>(L.rbf_o), ctx->at<float>(L.rbf_k));
+    for (int r = 0; r < dm.nrow; ++r) {
+      const int64_t a = dm.blk0 + (int64_t)r * L.chunk;
+      groups.push_back(make_int2((int)a, (int)std::min<int64_t>(a + L.chunk, dm.blk0 + dm.nblk)));
     }
-    double Xc = a < params->dim ? (params->centre[a] - params->lo[a]) * ics : 0.0;
-    split_cell(Xc, &g.gc_c[a], &g.gc_o[a]);
+    for (int t = 0; t < dm.p.n_rbf; ++t) {
+      const size_t kk = dm.rbf0 + t;
+      for (int a = 0; a < dm.p.dim; ++a)
+        split_cell((dm.p.rbf_centre[t * dm.p.dim + a] - dm.p.lo[a]) * dm.d.inv_cs, &rc3[kk * 3 + a], &ro3[kk * 3 + a]);
+      rk[kk] = (float)dm.p.rbf_coeff[t];
+    }
   }
-  g.r_in = (float)(params->r_in * ics);
-  g.r_out = (float)(params->r_out * ics);
-  FieldDev &f = ctx->f;
-  f.kind = params->field;
-  f.s0 = (float)(s0 * ics);
-  f.g = (float)(params->fa * cs);
-  f.b = (float)(params->fb * ics);
-  for (int a = 0; a < 3; ++a) {
-    double Xc = a < params->dim ? (params->fcentre[a] - params->lo[a]) * ics : 0.0;
-    split_cell(Xc, &f.fc_c[a], &f.fc_o[a]);
-  }
-  f.n_rbf = ctx->p.n_rbf;
-  f.e2 = (float)(cs * cs / (2.0 * params->rbf_width * params->rbf_width));
-  f.rbf_c = ctx->at<int>(ctx->L.rbf_c);
-  f.rbf_o = ctx->at<float>(ctx->L.rbf_o);
-  f.rbf_k = ctx->at<float>(ctx->L.rbf_k);
-  if (f.n_rbf > 0) {
-    std::vector<int> rc3(3 * f.n_rbf, 0);
-    std::vector<float> ro3(3 * f.n_rbf, 0.f), rk(f.n_rbf);
-    for (int k2 = 0; k2 < f.n_rbf; ++k2) {
-      for (int a = 0; a < params->dim; ++a)
-        split_cell((ctx->p.rbf_centre[k2 * params->dim + a] - params->lo[a]) * ics, &rc3[k2 * 3 + a], &ro3[k2 * 3 + a]);
-      rk[k2] = (float)ctx->p.rbf_coeff[k2];
-    }
-    if (hipMemcpy(ctx->at<int>(ctx->L.rbf_c), rc3.data(), rc3.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(ctx->at<float>(ctx->L.rbf_o), ro3.data(), ro3.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(ctx->at<float>(ctx->L.rbf_k), rk.data(), rk.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-      mpsph_destroy(ctx);
-      return MPSPH_E_DEVICE;
-    }
+  if (hipMemcpy(ctx->at<DomDev>(L.doms), dd.data(), dd.size() * sizeof(DomDev), hipMemcpyHostToDevice) != hipSuccess ||
+      (!groups.empty() && hipMemcpy(ctx->at<int2>(L.groups), groups.data(), groups.size() * sizeof(int2),
+                                    hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(ctx->at<int>(L.rbf_c), rc3.data(), rc3.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ctx->at<float>(L.rbf_o), ro3.data(), ro3.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ctx->at<float>(L.rbf_k), rk.data(), rk.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    mpsph_destroy(ctx);
+    return MPSPH_E_DEVICE;
   }
   *out = ctx;
   return MPSPH_OK;
 }
 
+int mpsph_create(const mpsph_params *params, int64_t n, void *d_workspace, size_t workspace_bytes, void *hip_stream,
+                 mpsph_ctx **out) {
+  return mpsph_batch_create(1, params, &n, d_workspace, workspace_bytes, hip_stream, out);
+}
+
 int mpsph_load(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type) {
   if (!ctx) return MPSPH_E_INVALID;
   if (ctx->poisoned) return MPSPH_E_STATE;
-  const int n = (int)ctx->L.n;
-  if (n > 0 && (!d_pos || !d_colour)) return MPSPH_E_INVALID;
   const Layout &L = ctx->L;
+  const int n = (int)L.n;
+  if (n > 0 && (!d_pos || !d_colour)) return MPSPH_E_INVALID;
   HIP_OK(hipMemsetAsync(ctx->at<int>(L.bad), 0, 4, ctx->stream));
-  HIP_OK(hipMemsetAsync(ctx->at<double>(L.metrics), 0, 32 * 8, ctx->stream));
-  if (n > 0) {
-    auto kern = ctx->p.dim == 2 ? load_kernel<2> : load_kernel<3>;
-    kern<<<(n + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
-        d_pos, d_colour, d_type, n, ctx->d.lo[0], ctx->d.lo[1], ctx->d.lo[2], ctx->d.xhi[0], ctx->d.xhi[1],
-        ctx->d.xhi[2], ctx->d.inv_cs, ctx->d.k, ctx->d.gmax,
-        ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id),
-        ctx->at<int>(L.bad));
+  HIP_OK(hipMemsetAsync(ctx->at<double>(L.metrics), 0, (size_t)L.ndom * 32 * 8, ctx->stream));
+  HIP_OK(hipMemsetAsync(ctx->at<int64_t>(L.stepctr), 0, 8, ctx->stream));
+  for (const Group &gr : L.grp) {
+    if (gr.i1 <= gr.i0) continue;
+    auto kern = gr.D == 2 ? load_kernel<2> : load_kernel<3>;
+    kern<<<(gr.i1 - gr.i0 + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
+        ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.i0, gr.i1, d_pos, d_colour, d_type, ctx->at<uint32_t>(L.s_key),
+        ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), ctx->at<int>(L.bad));
     HIP_OK(hipGetLastError());
   }
   int bad = 0;
   HIP_OK(hipMemcpyAsync(&bad, ctx->at<int>(L.bad), 4, hipMemcpyDeviceToHost, ctx->stream));
   HIP_OK(hipStreamSynchronize(ctx->stream));
+  ctx->steps_done = 0;
   if (bad) {
     ctx->loaded = false;
     return MPSPH_E_INVALID;
   }
   ctx->loaded = true;
-  ctx->steps_done = 0;
   return MPSPH_OK;
 }
 
 int mpsph_step(mpsph_ctx *ctx, int32_t nsteps) {
   if (!ctx || nsteps < 0) return MPSPH_E_INVALID;
   if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
-  return ctx->p.dim == 2 ? run_steps<2>(ctx, nsteps) : run_steps<3>(ctx, nsteps);
+  int rc = enqueue(ctx, nsteps, ctx->stream, ctx->hook.on ? &ctx->hook : nullptr);
+  if (rc == MPSPH_OK) ctx->steps_done += nsteps;
+  return rc;
 }
 
-int mpsph_metrics(mpsph_ctx *ctx, mpsph_metrics_t *out) {
-  if (!ctx || !out) return MPSPH_E_INVALID;
-  if (ctx->poisoned) return MPSPH_E_STATE;
-  double m[32];
-  HIP_OK(hipMemcpyAsync(m, ctx->at<double>(ctx->L.metrics), sizeof(m), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_OK(hipStreamSynchronize(ctx->stream));
-  const double cs = ctx->d.cs;
-  std::memset(out, 0, sizeof(*out));
-  out->step = ctx->steps_done - 1;
-  out->pairs = (int64_t)m[P_PAIRS];
-  out->interface_pairs = (int64_t)m[P_IFC] / 2;
-  out->candidates = (int64_t)m[P_CAND];
-  out->n_normal = (int64_t)m[P_NNORM];
-  out->n_elr = (int64_t)m[P_NELR];
-  out->nonfinite = (int64_t)(m[P_NONFIN1] + m[P_NONFIN2]);
-  out->n_feature = (int64_t)m[P_NFEAT];
-  out->residual_l2 = m[P_NNORM] > 0 ? std::sqrt(m[P_E2] / m[P_NNORM]) : 0.0;
-  out->residual_linf = m[P_EMAX];
-  out->pairs_total = (int64_t)m[18];
-  out->candidates_total = (int64_t)m[19];
-  out->kinetic = m[P_KE] * cs * cs;
-  out->dt1 = m[16];
-  out->dt2 = m[17];
-  out->sigma = ctx->steps_done > 0 ? sigma_at(&ctx->p, ctx->steps_done - 1) : sigma_at(&ctx->p, 0);
-  if (m[P_NELR] > 0) {
-    double mean = m[P_ELR] / m[P_NELR];
-    out->elr_mean = mean;
-    out->elr_std = std::sqrt(std::max(0.0, m[P_ELR2] / m[P_NELR] - mean * mean));
-    out->elr_min = m[P_ELRMIN];
-    out->elr_max = m[P_ELRMAX];
+int mpsph_step_graph(mpsph_ctx *ctx, int32_t nsteps) {
+  if (!ctx || nsteps < 0) return MPSPH_E_INVALID;
+  if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
+  if (nsteps == 0) return MPSPH_OK;
+  if (!ctx->graph_exec || ctx->graph_steps != nsteps) {
+    drop_graph(ctx);
+    if (!ctx->cap_stream) HIP_OK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIP_OK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue(ctx, nsteps, ctx->cap_stream, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (rc != MPSPH_OK || ec != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(ctx, MPSPH_E_DEVICE);
+    }
+    const hipError_t ei = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      ctx->graph_exec = nullptr;
+      return fail(ctx, MPSPH_E_DEVICE);
+    }
+    ctx->graph_steps = nsteps;
   }
-  return out->nonfinite ? MPSPH_E_NONFINITE : MPSPH_OK;
+  EventHook *hk = ctx->hook.on ? &ctx->hook : nullptr;
+  if (hk) hk->begin("step_graph");
+  HIP_OK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+  if (hk) hk->end();
+  ctx->steps_done += nsteps;
+  return MPSPH_OK;
 }
+
+int mpsph_domain_count(mpsph_ctx *ctx, int32_t *ndom, int64_t *n_total) {
+  if (!ctx) return MPSPH_E_INVALID;
+  if (ndom) *ndom = ctx->L.ndom;
+  if (n_total) *n_total = ctx->L.n;
+  return MPSPH_OK;
+}
+
+int mpsph_domain_metrics(mpsph_ctx *ctx, int32_t first, int32_t count, mpsph_metrics_t *out) {
+  if (!ctx || !out || first < 0 || count < 1 || first + count > ctx->L.ndom) return MPSPH_E_INVALID;
+  if (ctx->poisoned) return MPSPH_E_STATE;
+  std::vector<double> m((size_t)ctx->L.ndom * 32);
+  HIP_OK(hipMemcpyAsync(m.data(), ctx->at<double>(ctx->L.metrics), m.size() * 8, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  bool nonfinite = false;
+  for (int d = 0; d < count; ++d) {
+    const int k = ctx->L.internal[first + d];
+    fill_metrics(ctx, k, m.data() + (size_t)k * 32, &out[d]);
+    nonfinite |= out[d].nonfinite != 0;
+  }
+  return nonfinite ? MPSPH_E_NONFINITE : MPSPH_OK;
+}
+
+int mpsph_metrics(mpsph_ctx *ctx, mpsph_metrics_t *out) { return mpsph_domain_metrics(ctx, 0, 1, out); }
 
 int mpsph_store(mpsph_ctx *ctx, float *d_pos, int32_t *d_type) {
   if (!ctx) return MPSPH_E_INVALID;
   if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
-  const int n = (int)ctx->L.n;
   const Layout &L = ctx->L;
-  if (n > 0) {
-    auto kern = ctx->p.dim == 2 ? store_kernel<2> : store_kernel<3>;
-    kern<<<(n + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
-        n, ctx->d.k, (uint32_t)ctx->d.gmax, ctx->d.lo[0], ctx->d.lo[1], ctx->d.lo[2], ctx->d.cs,
-        ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id),
-        d_pos, d_type);
+  for (const Group &gr : L.grp) {
+    if (gr.i1 <= gr.i0) continue;
+    auto kern = gr.D == 2 ? store_kernel<2> : store_kernel<3>;
+    kern<<<(gr.i1 - gr.i0 + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
+        ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.i0, gr.i1, ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off),
+        ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), d_pos, d_type);
     HIP_OK(hipGetLastError());
   }
   HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -1412,30 +1680,33 @@ int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out) {
   if (ctx->poisoned || !ctx->loaded || ctx->steps_done == 0) return MPSPH_E_STATE;
   const bool needs_debug = which == MPSPH_F_RHO || which == MPSPH_F_A_ABS || which == MPSPH_F_AT ||
                            which == MPSPH_F_V || which == MPSPH_F_DR || which == MPSPH_F_NN;
-  if (needs_debug && !ctx->p.debug) return MPSPH_E_STATE;
-  const int n = (int)ctx->L.n;
+  if (needs_debug && !ctx->dom[0].p.debug) return MPSPH_E_STATE;
   const Layout &L = ctx->L;
   const float4 *vec = ctx->at<float4>(L.acc);
   const float *sc = ctx->at<float>(L.rho);
-  float vscale = 1.f;
+  const float *vscale = nullptr;
   if (which == MPSPH_F_NN) sc = ctx->at<float>(L.nn);
   if (which == MPSPH_F_A_ABS) sc = ctx->at<float>(L.aabs);
   if (which == MPSPH_F_AT) vec = ctx->at<float4>(L.at);
   if (which == MPSPH_F_V) vec = ctx->at<float4>(L.v);
   if (which == MPSPH_F_DR) vec = ctx->at<float4>(L.dr);
   if (which == MPSPH_F_VT) {
-    // v~ = a dt1 / 2 (Eq. 26 after the velocity reset); fixed particles carry a = 0
-    double m[17];
-    HIP_OK(hipMemcpyAsync(m, ctx->at<double>(L.metrics), sizeof(m), hipMemcpyDeviceToHost, ctx->stream));
+    // v~ = a dt1 / 2 (Eq. 26 after the velocity reset) with the domain's dt1; fixed particles
+    // carry a = 0
+    std::vector<double> m((size_t)L.ndom * 32);
+    std::vector<float> vs(L.ndom);
+    HIP_OK(hipMemcpyAsync(m.data(), ctx->at<double>(L.metrics), m.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
-    vscale = (float)(0.5 * m[16]);
+    for (int d = 0; d < L.ndom; ++d) vs[d] = (float)(0.5 * m[(size_t)d * 32 + 16]);
+    HIP_OK(hipMemcpyAsync(ctx->at<float>(L.vscale), vs.data(), vs.size() * 4, hipMemcpyHostToDevice, ctx->stream));
+    vscale = ctx->at<float>(L.vscale);
   }
-  if (n > 0) {
-    auto kern = ctx->p.dim == 2 ? dump_kernel<2> : dump_kernel<3>;
-    kern<<<(n + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
-        n, which, ctx->d.k, (uint32_t)ctx->d.gmax, ctx->d.lo[0], ctx->d.lo[1], ctx->d.lo[2], ctx->d.cs,
-        (float)ctx->p.tau, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_id), sc, vec,
-        vscale, d_out);
+  for (const Group &gr : L.grp) {
+    if (gr.i1 <= gr.i0) continue;
+    auto kern = gr.D == 2 ? dump_kernel<2> : dump_kernel<3>;
+    kern<<<(gr.i1 - gr.i0 + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
+        ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.i0, gr.i1, which, ctx->at<uint32_t>(L.w_key),
+        ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_id), sc, vec, vscale ? vscale + gr.d0 : nullptr, d_out);
     HIP_OK(hipGetLastError());
   }
   HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -1446,7 +1717,7 @@ int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cell_start, i
   if (!ctx) return MPSPH_E_INVALID;
   if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
   if (ncells) *ncells = ctx->L.ncells;
-  if (cell_log2) *cell_log2 = ctx->d.k;
+  if (cell_log2) *cell_log2 = ctx->dom[ctx->L.internal[0]].d.k;
   if ((d_key || d_cell_start) && ctx->steps_done == 0) return MPSPH_E_STATE;
   const Layout &L = ctx->L;
   const int n = (int)L.n;
@@ -1469,14 +1740,9 @@ int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cell_start, i
 int mpsph_profile(mpsph_ctx *ctx, int32_t enable) {
   if (!ctx) return MPSPH_E_INVALID;
   if (ctx->poisoned) return MPSPH_E_STATE;
-  if (enable) {
-    ctx->hook.collect();
-    ctx->hook.reset();
-    ctx->hook.on = true;
-  } else {
-    ctx->hook.collect();
-    ctx->hook.on = false;
-  }
+  ctx->hook.collect();
+  if (enable) ctx->hook.reset();
+  ctx->hook.on = enable != 0;
   return MPSPH_OK;
 }
 
@@ -1497,6 +1763,8 @@ int mpsph_profile_read(mpsph_ctx *ctx, int32_t cap, const char **names, int64_t 
 void mpsph_destroy(mpsph_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  drop_graph(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->owns && ctx->ws) (void)hipFree(ctx->ws);
   delete ctx;
 }

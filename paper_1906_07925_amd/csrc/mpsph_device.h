@@ -9,7 +9,7 @@ constexpr int kBlock = 256;       // threads per block of the particle kernels (
 constexpr int kWave = 64;
 constexpr int kNumPartials = 16;  // FP64 partial slots per block
 constexpr uint32_t kInfBits = 0x7f800000u;
-constexpr int kDtSlots = 64;      // words over which the first time-step minimum is spread
+constexpr int kDtSlots = 16;      // words per domain over which the first time-step minimum is spread
 constexpr int kReduceBlocks = 256;  // first-level blocks of the metric reduction
 
 // Slots of the per-block FP64 partials.
@@ -36,7 +36,7 @@ enum : int {
 // an integer cell coordinate per axis plus a float offset in [0, 1).
 struct GridDev {
   int k;             // cells per axis = 2^k
-  int n;             // particles
+  int n;             // particles of the context (bound of every sorted index)
   int gmax;          // 2^k - 1
   uint32_t xmask;    // 2^k - 1
   int geometry;      // MPSPH_BOX | MPSPH_ANNULUS | MPSPH_BALL
@@ -66,13 +66,62 @@ struct FieldDev {
 struct StepDev {
   float kappa, tau, inv_tau;
   float p0c;         // p0 cs^(d-2): keeps accelerations in cell units = domain units / cs
-  float sigma;
   float nu_coeff, c_acc, c_vel, c_visc;
   float search_fac;  // neighbour search radius bound: search_fac * h_i
   float hmax;        // upper bound of h over the region (cell units)
   float alpha;       // kernel normalisation alpha_d
   float dt2_factor;  // dt2 / dt1 implied by Eq. 29 after the velocity reset
+  float sigma0;      // surface-tension strength before the ramp (Eq. 25)
+  float t0, t1;      // ramp over steps (t0, t1]; t0 < 0: constant
 };
+
+// One domain of a (possibly batched) context.  Domains occupy contiguous particle ranges
+// [off, off + n) in every internal particle array, contiguous ranges of the global cell index space
+// [cellbase, cellbase + 2^(d k)), and contiguous ranges of the pair-kernel blocks and of the
+// first-level reduction rows.
+struct DomDev {
+  GridDev g;
+  FieldDev f;
+  StepDev sp;
+  uint32_t cellbase;
+  int off, n;        // internal particle range (domains grouped by dimension, 2D first)
+  int uoff;          // first row of the domain in the caller's colour / type arrays
+  int64_t xoff;      // first float of the domain in the caller's position arrays (rows of dim floats)
+  int blk0, nblk;    // pair-kernel blocks
+  int row0, nrow;    // first-level reduction rows
+  double lo[3];      // domain -> cell units: X = (x - lo) * inv_cs
+  double cs, inv_cs;
+  double xhi[3];     // upper face of the bounding box in cell units
+};
+
+// Surface-tension strength at step t (Eq. 25): sigma0 up to t0, linear ramp to 0 on (t0, t1].
+__device__ __forceinline__ float sigma_of(const StepDev &sp, float t) {
+  if (sp.t0 < 0.f || t <= sp.t0) return sp.sigma0;
+  if (t <= sp.t1) return sp.sigma0 * (1.f - (t - sp.t0) / (sp.t1 - sp.t0));
+  return 0.f;
+}
+
+// Domain of particle index i (domains sorted by offset).
+__device__ __forceinline__ int domain_of(const DomDev *doms, int ndom, int i) {
+  int lo = 0, hi = ndom - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (doms[mid].off <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Domain owning pair-kernel block b.
+__device__ __forceinline__ int domain_of_block(const DomDev *doms, int ndom, int b) {
+  int lo = 0, hi = ndom - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (doms[mid].blk0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous range of

@@ -67,7 +67,12 @@ def lib():
         sig = {
             "mpsph_field_scale": (C.c_int, [P, I64, C.POINTER(C.c_double)]),
             "mpsph_workspace_bytes": (C.c_size_t, [P, I64]),
+            "mpsph_batch_workspace_bytes": (C.c_size_t, [I32, P, C.POINTER(I64)]),
             "mpsph_create": (C.c_int, [P, I64, V, C.c_size_t, V, C.POINTER(V)]),
+            "mpsph_batch_create": (C.c_int, [I32, P, C.POINTER(I64), V, C.c_size_t, V, C.POINTER(V)]),
+            "mpsph_domain_count": (C.c_int, [V, C.POINTER(I32), C.POINTER(I64)]),
+            "mpsph_step_graph": (C.c_int, [V, I32]),
+            "mpsph_domain_metrics": (C.c_int, [V, I32, I32, C.POINTER(Metrics)]),
             "mpsph_load": (C.c_int, [V, V, V, V]),
             "mpsph_step": (C.c_int, [V, I32]),
             "mpsph_metrics": (C.c_int, [V, C.POINTER(Metrics)]),
@@ -148,21 +153,35 @@ def field_scale(spec: dict, n: int) -> float:
 
 
 class Relaxer:
-    """One relaxation context on the current CUDA/HIP device and stream."""
+    """A relaxation context on the current CUDA/HIP device and stream.
 
-    def __init__(self, spec: dict, n: int | None = None, s0: float | None = None, cell_log2: int = -1,
-                 debug: bool = False, stream=None):
+    ``spec`` is one workload spec (one domain of ``n`` particles) or a list of specs (a batch of
+    independent domains advanced by the same launches; ``n`` and ``s0`` are then lists too, and
+    the particle arrays hold the domains one after the other)."""
+
+    def __init__(self, spec, n=None, s0=None, cell_log2: int = -1, debug: bool = False, stream=None):
         import torch
         self._torch = torch
-        self.dim = int(spec["dim"])
-        self.n = int(spec["n"] if n is None else n)
-        self.params, self._keep = make_params(spec, s0=s0, cell_log2=cell_log2, debug=debug)
+        specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
+        ns = list(n) if isinstance(n, (list, tuple)) else [n] * len(specs)
+        s0s = list(s0) if isinstance(s0, (list, tuple)) else [s0] * len(specs)
+        ns = [int(sp["n"] if k is None else k) for sp, k in zip(specs, ns)]
+        self.ndom = len(specs)
+        self.dims = [int(sp["dim"]) for sp in specs]
+        self.dim = self.dims[0] if len(set(self.dims)) == 1 else None   # None: mixed 2D / 3D batch
+        self.counts = ns
+        self.n = sum(ns)
+        self.nfloat = sum(k * d for k, d in zip(ns, self.dims))   # floats of a position array
+        made = [make_params(sp, s0=z, cell_log2=cell_log2, debug=debug) for sp, z in zip(specs, s0s)]
+        self.params = (Params * self.ndom)(*[m[0] for m in made])
+        self._keep = [m[1] for m in made]
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self._ctx = C.c_void_p()
-        _check(lib().mpsph_create(C.byref(self.params), self.n, None, 0, C.c_void_p(stream.cuda_stream),
-                                  C.byref(self._ctx)), "mpsph_create")
+        cnt = (C.c_int64 * self.ndom)(*ns)
+        _check(lib().mpsph_batch_create(self.ndom, self.params, cnt, None, 0, C.c_void_p(stream.cuda_stream),
+                                        C.byref(self._ctx)), "mpsph_batch_create")
 
     # -- lifecycle
     def close(self):
@@ -183,11 +202,27 @@ class Relaxer:
             t = t.to(device="cuda", dtype=dtype).contiguous()
         return t
 
+    def _pos_shape(self):
+        return (self.n, self.dim) if self.dim is not None else (self.nfloat,)
+
+    def split(self, arr, vector: bool = True) -> list:
+        """Per-domain views of a particle array in the context's layout (positions / vector
+        quantities when ``vector``, else one value per particle)."""
+        flat = arr.reshape(-1)
+        out, o = [], 0
+        for k, d in zip(self.counts, self.dims):
+            w = k * d if vector else k
+            out.append(flat[o:o + w].reshape((k, d) if vector else (k,)))
+            o += w
+        return out
+
     def load(self, x, colour, ptype=None):
+        """Positions (n x dim, or for a mixed batch the flat concatenation of each domain's
+        n_d x dim_d block), colours and optional types."""
         torch = self._torch
         x = self._dev(x, torch.float32)
         c = self._dev(colour, torch.int32)
-        assert x.shape == (self.n, self.dim) and c.shape == (self.n,)
+        assert x.numel() == self.nfloat and c.shape == (self.n,)
         t = None if ptype is None else self._dev(ptype, torch.int32)
         self._hold = (x, c, t)
         _check(lib().mpsph_load(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(c.data_ptr()),
@@ -196,23 +231,32 @@ class Relaxer:
     def step(self, nsteps: int = 1):
         _check(lib().mpsph_step(self._ctx, int(nsteps)), "mpsph_step")
 
+    def step_graph(self, nsteps: int = 1):
+        """The same steps as ``step``, launched as one captured HIP graph."""
+        _check(lib().mpsph_step_graph(self._ctx, int(nsteps)), "mpsph_step_graph")
+
     def metrics(self, allow_nonfinite: bool = False) -> dict:
-        m = Metrics()
-        rc = lib().mpsph_metrics(self._ctx, C.byref(m))
+        """Metrics of the last step of domain 0."""
+        return self.domain_metrics(allow_nonfinite)[0]
+
+    def domain_metrics(self, allow_nonfinite: bool = False) -> list:
+        """Metrics of the last step of every domain."""
+        m = (Metrics * self.ndom)()
+        rc = lib().mpsph_domain_metrics(self._ctx, 0, self.ndom, m)
         if rc != 0 and not (allow_nonfinite and rc == 5):
-            raise MpsphError(rc, "mpsph_metrics")
-        return {k: getattr(m, k) for k, _ in Metrics._fields_}
+            raise MpsphError(rc, "mpsph_domain_metrics")
+        return [{k: getattr(m[d], k) for k, _ in Metrics._fields_} for d in range(self.ndom)]
 
     def store(self):
         torch = self._torch
-        x = torch.empty((self.n, self.dim), dtype=torch.float32, device="cuda")
+        x = torch.empty(self._pos_shape(), dtype=torch.float32, device="cuda")
         t = torch.empty((self.n,), dtype=torch.int32, device="cuda")
         _check(lib().mpsph_store(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr())), "mpsph_store")
         return x, t
 
     def field(self, name: str):
         torch = self._torch
-        shape = (self.n, self.dim) if name in VECTOR_FIELDS else (self.n,)
+        shape = self._pos_shape() if name in VECTOR_FIELDS else (self.n,)
         out = torch.empty(shape, dtype=torch.float32, device="cuda")
         _check(lib().mpsph_debug_fields(self._ctx, FIELDS[name], C.c_void_p(out.data_ptr())),
                f"mpsph_debug_fields({name})")
@@ -251,3 +295,10 @@ class Relaxer:
 def workspace_bytes(spec: dict, n: int, cell_log2: int = -1) -> int:
     p, keep = make_params(spec, cell_log2=cell_log2)
     return int(lib().mpsph_workspace_bytes(C.byref(p), int(n)))
+
+
+def batch_workspace_bytes(specs: list, ns: list, cell_log2: int = -1) -> int:
+    made = [make_params(sp, cell_log2=cell_log2) for sp in specs]
+    ps = (Params * len(specs))(*[m[0] for m in made])
+    cnt = (C.c_int64 * len(specs))(*[int(k) for k in ns])
+    return int(lib().mpsph_batch_workspace_bytes(len(specs), ps, cnt))

@@ -99,3 +99,19 @@ def test_workspace_grows_with_n(lib):
     big = M.workspace_bytes(spec, 1 << 21, cell_log2=6)
     assert 0 < small < big
     assert big >= (1 << 21) * 100
+
+
+def test_batch_workspace(lib):
+    """A batch needs at least the particle state of all its domains and no more than the solo
+    contexts together (plus per-domain tables); a batch of one equals the solo context; bad
+    batches are refused (0 bytes)."""
+    specs = [W.unit_square(5000), W.unit_cube(20000), W.annulus(8000), W.ball(12000)]
+    ns = [s["n"] for s in specs]
+    solo = [M.workspace_bytes(s, k) for s, k in zip(specs, ns)]
+    both = M.batch_workspace_bytes(specs, ns)
+    assert sum(ns) * 100 <= both <= sum(solo) + 65536
+    assert M.batch_workspace_bytes(specs[:1], ns[:1]) == solo[0]
+    assert M.batch_workspace_bytes([], []) == 0
+    bad = dict(specs[1], tau=-1.0)
+    assert M.batch_workspace_bytes([specs[0], bad], ns[:2]) == 0
+    assert M.batch_workspace_bytes(specs[:2], [ns[0], -1]) == 0

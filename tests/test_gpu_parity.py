@@ -228,3 +228,31 @@ def test_coincident_particles(torch_cuda):
     typ[30] = typ[31] = 3
     spec = dict(W.unit_cube(200), n=200)
     PU.check_single_step(spec, 0.12, x32, col, typ)
+
+
+def test_sigma_ramp_follows_device_step_counter(torch_cuda):
+    """The surface-tension ramp (Eq. 25) is evaluated from the step counter in device memory:
+    the second step's acceleration matches the oracle at step index 1 (sigma = sigma0 / 2 for a
+    ramp over (0, 2]) and not at step index 0."""
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    cfg = W.config("square_4k", scale=0.25)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0], sigma0=3.0, t0=0, t1=2)
+    s0 = _s0(spec)
+    R = M.Relaxer(spec, n=x32.shape[0], s0=s0, debug=True)
+    R.load(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    R.step(1)
+    _, t1 = R.store()
+    R.step(1)
+    x0 = R.field("x0").cpu().numpy()
+    a = R.field("a").cpu().numpy().astype(np.float64)
+    m = R.metrics()
+    R.close()
+    assert m["sigma"] == 1.5
+    t1 = t1.cpu().numpy()
+    op = O.OracleParams(spec, s0=s0)
+    _, _, r1 = O.step(op, x0.astype(np.float64), col, t1, 1)
+    _, _, r0 = O.step(op, x0.astype(np.float64), col, t1, 0)
+    assert PU.rel(a, r1["a"]) < 1e-5
+    assert PU.rel(a, r0["a"]) > 1e-3
