@@ -9,7 +9,9 @@ tension, both time steps, viscous pass, integrator, FP64 metrics) on that partic
 Prints one JSON line: pair interactions per second over the timed steps (ordered pairs
 i != j inside the cut-off that pass the type mask, counted on the device each step), the step
 rate, per-kernel times measured with HIP events on the library's stream, the roofline entry of
-the dominant kernel, and the CPU oracle timed on the host on a bounded sample.
+the dominant kernel, the CPU oracle timed on the host on a bounded sample, and (object
+"batched") 64 independent mixed 2D/3D domains relaxed in one batched context against the same
+domains solved one after the other.
 """
 from __future__ import annotations
 
@@ -73,6 +75,64 @@ def cpu_baseline(cfg, x, col, typ):
             "sample": f"1 step (step 0) of the full {x.shape[0]}-particle input, {r['pairs']} pairs, {dt:.1f} s"}
 
 
+def batched_run(torch, M, W, steps: int, warmup: int, graph_steps: int = 10):
+    """64 independent domains (squares, annuli, cubes, balls; 1e4..5e5 particles each, random
+    equal-mass init) relaxed together in one batched context whose steps run as a captured graph,
+    against the same 64 domains solved one after the other, each in its own context (also with
+    captured graphs).  Both start from the same state and take warmup + steps steps; the final
+    states must be bit-identical.  Returns the summary object of the JSON line."""
+    cfgs = W.batched_domains()
+    states = [W.make_state(c) for c in cfgs]
+    specs = [dict(c["spec"], n=st[0].shape[0]) for c, st in zip(cfgs, states)]
+    ns = [st[0].shape[0] for st in states]
+    x_all = np.concatenate([st[0].astype(np.float32).reshape(-1) for st in states])
+    col_all = np.concatenate([st[1] for st in states]).astype(np.int32)
+    typ_all = np.concatenate([st[2] for st in states]).astype(np.int32)
+    print(f"[bench] batched: {len(ns)} domains, {sum(ns)} particles generated", file=sys.stderr, flush=True)
+    g = max(1, min(graph_steps, steps))
+    steps = (steps // g) * g
+
+    def run(R, x, c, t):
+        R.load(torch.from_numpy(x).cuda(), torch.from_numpy(c).cuda(), torch.from_numpy(t).cuda())
+        R.step(warmup)
+        R.step_graph(g)                      # capture outside the timed region
+        torch.cuda.synchronize()
+        m0 = R.domain_metrics()
+        t0 = time.perf_counter()
+        for _ in range(steps // g - 1):
+            R.step_graph(g)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        m1 = R.domain_metrics()
+        return dt, m0, m1
+
+    B = M.Relaxer(specs, n=ns)
+    tb, m0, m1 = run(B, x_all, col_all, typ_all)
+    xb = B.split(B.store()[0].cpu().numpy())
+    B.close()
+    print(f"[bench] batched: {steps + warmup} steps done, {1e3 * tb / (steps - g):.2f} ms/step", file=sys.stderr,
+          flush=True)
+    timed = steps - g
+    pairs_b = sum(b["pairs_total"] - a["pairs_total"] for a, b in zip(m0, m1))
+    ts, pairs_s, same = 0.0, 0, True
+    for k, (spec, st) in enumerate(zip(specs, states)):
+        R = M.Relaxer(spec, n=ns[k])
+        dt, a, b = run(R, st[0].astype(np.float32), st[1], st[2])
+        ts += dt
+        pairs_s += b[0]["pairs_total"] - a[0]["pairs_total"]
+        same = same and np.array_equal(R.store()[0].cpu().numpy(), xb[k])
+        R.close()
+        if k % 16 == 15:
+            print(f"[bench] sequential: {k + 1} domains done", file=sys.stderr, flush=True)
+    n = sum(ns)
+    return {"workload": "batched_64_domains", "domains": len(ns), "particles": n, "dims": "32x2D + 32x3D",
+            "steps_timed": timed, "graph_steps": g,
+            "batched_particle_steps_per_s": n * timed / tb, "sequential_particle_steps_per_s": n * timed / ts,
+            "speedup": ts / tb, "batched_ms_per_step": 1e3 * tb / timed, "sequential_ms_per_step": 1e3 * ts / timed,
+            "batched_pairs_per_s": pairs_b / tb, "pairs_equal": pairs_b == pairs_s,
+            "final_state_bit_identical": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +140,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cell-log2", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-domain batched comparison")
+    ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -166,6 +228,8 @@ def main():
         "roofline": roof,
     }
     R.close()
+    if not args.no_batched:
+        out["batched"] = batched_run(torch, M, W, args.batched_steps, 10)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, x, col, typ)
     print(json.dumps(out))

@@ -815,7 +815,17 @@ double field_integral_unit(const mpsph_params *p) {
   double xg[8], wg[8];
   gauss8(xg, wg);
   const int d = p->dim;
+  const double pi = 3.14159265358979323846;
   double total = 0.0;
+  if (p->field == MPSPH_UNIFORM) {  // s = 1: the measure of the region
+    if (p->geometry == MPSPH_BOX) {
+      double v = 1.0;
+      for (int a = 0; a < d; ++a) v *= p->hi[a] - p->lo[a];
+      return v;
+    }
+    if (p->geometry == MPSPH_ANNULUS) return pi * (p->r_out * p->r_out - p->r_in * p->r_in);
+    return d == 2 ? pi * p->r_out * p->r_out : 4.0 / 3.0 * pi * p->r_out * p->r_out * p->r_out;
+  }
   if (p->geometry == MPSPH_BOX) {
     const int M = d == 2 ? 256 : 48;
     const int np = M * 8;
@@ -853,8 +863,7 @@ double field_integral_unit(const mpsph_params *p) {
     return total;
   }
   const double r0 = p->geometry == MPSPH_ANNULUS ? p->r_in : 0.0, r1 = p->r_out;
-  const int MR = 128, MT = d == 2 ? 64 : 32, MP = 64;
-  const double pi = 3.14159265358979323846;
+  const int MR = d == 2 ? 128 : 64, MT = d == 2 ? 64 : 16, MP = 32;
   for (int mr = 0; mr < MR; ++mr)
     for (int qr = 0; qr < 8; ++qr) {
       double r = r0 + (mr + xg[qr]) * (r1 - r0) / MR, wr = wg[qr] * (r1 - r0) / MR;
