@@ -205,6 +205,14 @@ MPSPH_API int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out);
 MPSPH_API int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cell_start, int64_t *ncells,
                       int32_t *cell_log2);
 
+/* Neighbour pairs of the last step (for testing at small n): the ordered pairs (i, j), j != i,
+ * with |x_i - x_j| < kappa (h_i + h_j) / 2 at the start of that step, before the type mask is
+ * applied (the pair set of Alg. 1's neighbour list; §3.3 Eq. 17-20), as load indices.  Up to
+ * cap pairs are written to d_i[k], d_j[k] (device, uint32) in an unspecified order; *count
+ * (host) receives the total number of pairs, which may exceed cap.  Synchronises.
+ * Errors: MPSPH_E_INVALID (cap < 0, NULL arrays with cap > 0), MPSPH_E_STATE (no step yet). */
+MPSPH_API int mpsph_debug_pairs(mpsph_ctx *ctx, int64_t cap, uint32_t *d_i, uint32_t *d_j, int64_t *count);
+
 /* Per-kernel timing with HIP events on the context's stream.  enable = 1 starts recording
  * (resets the accumulators), 0 stops.  mpsph_profile_read() synchronises and returns, for up
  * to cap kernels, the name, the number of launches and the summed milliseconds. */

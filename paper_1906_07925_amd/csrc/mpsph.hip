@@ -581,6 +581,50 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
 }
 
 
+// Debug: ordered geometric neighbour pairs (i, j != i, r_ij < kappa h_ij, no type mask) of the
+// last step's start-of-step state, enumerated with the same candidate scan and predicate as the
+// pair passes (one lane per particle).  Pairs go to (out_i, out_j) as load indices while the
+// running count stays below cap; *count receives the total.
+template <int D>
+__global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ doms, int ndom, int i0, int i1,
+                                                     const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
+                                                     const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ wid,
+                                                     const uint32_t *__restrict__ cstart, unsigned long long cap,
+                                                     uint32_t *__restrict__ out_i, uint32_t *__restrict__ out_j,
+                                                     unsigned long long *__restrict__ count) {
+  const int i = i0 + blockIdx.x * kBlock + threadIdx.x;
+  if (i >= i1) return;
+  const DomDev &dd = doms[domain_of(doms, ndom, i)];
+  const GridDev &g = dd.g;
+  const StepDev &sp = dd.sp;
+  int ci[3];
+  unpack_key<D>(wkey[i] - dd.cellbase, g.k, g.xmask, ci);
+  const float4 pi = wpos[i];
+  const float oi[3] = {pi.x, pi.y, pi.z};
+  const float hi = pi.w;
+  const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
+  const float kh = 0.5f * sp.kappa;
+  const uint32_t idi = wid[i];
+  scan_group<D, 1>(i, 0, ci, oi, rs, g, dd.cellbase, cstart, [&](int j, uint32_t drw, bool v) {
+    const float4 pj = wpos[j];
+    const uint32_t aj = wjaux[j];
+    const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+    const float dy = row_dy(drw) + (oi[1] - pj.y);
+    float r2 = dx * dx + dy * dy;
+    if constexpr (D == 3) {
+      const float dz = row_dz(drw) + (oi[2] - pj.z);
+      r2 += dz * dz;
+    }
+    const float hij = kh * (hi + pj.w);
+    if (!(v && r2 < hij * hij)) return;
+    const unsigned long long k = atomicAdd(count, 1ull);
+    if (k < cap) {
+      out_i[k] = idi;
+      out_j[k] = wid[j];
+    }
+  });
+}
+
 // Combine partials slot by slot: sums, or min / max for the slots that hold extrema.
 __device__ __forceinline__ double combine_slot(int s, double a, double b) {
   return (s == P_EMAX || s == P_ELRMAX) ? fmax(a, b) : (s == P_ELRMIN ? fmin(a, b) : a + b);
@@ -1120,7 +1164,7 @@ struct Layout {
   size_t n_rbf = 0;
   size_t bytes = 0;
   size_t s_key, s_off, s_ct, s_id, w_key, w_pos, w_jaux, w_id, k0, v0, k1, v1, hist, cstart, acc, rho, nn, aabs, at, v,
-      dr, partials, partials2, groups, metrics, dtslots, stepctr, bad, doms, vscale, rbf_c, rbf_o, rbf_k;
+      dr, partials, partials2, groups, metrics, dtslots, stepctr, bad, paircount, doms, vscale, rbf_c, rbf_o, rbf_k;
 };
 
 // Orders the domains internally (2D before 3D, otherwise as given), assigns particle offsets,
@@ -1221,6 +1265,7 @@ int plan(std::vector<Domain> &doms, Layout *out) {
   L.dtslots = take((size_t)L.ndom * kDtSlots * 4);
   L.stepctr = take(8);
   L.bad = take(4);
+  L.paircount = take(8);
   L.doms = take((size_t)L.ndom * sizeof(DomDev));
   L.vscale = take((size_t)L.ndom * 4);
   L.rbf_c = take(std::max<size_t>(nrbf, 1) * 3 * 4);
@@ -1743,6 +1788,28 @@ int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cell_start, i
     HIP_OK(hipMemcpyAsync(d_cell_start, ctx->at<uint32_t>(L.cstart), 4 * ((size_t)L.ncells + 1),
                           hipMemcpyDeviceToDevice, ctx->stream));
   HIP_OK(hipStreamSynchronize(ctx->stream));
+  return MPSPH_OK;
+}
+
+int mpsph_debug_pairs(mpsph_ctx *ctx, int64_t cap, uint32_t *d_i, uint32_t *d_j, int64_t *count) {
+  if (!ctx || cap < 0 || !count || (cap > 0 && (!d_i || !d_j))) return MPSPH_E_INVALID;
+  if (ctx->poisoned || !ctx->loaded || ctx->steps_done == 0) return MPSPH_E_STATE;
+  const Layout &L = ctx->L;
+  unsigned long long *cnt = ctx->at<unsigned long long>(L.paircount);
+  HIP_OK(hipMemsetAsync(cnt, 0, 8, ctx->stream));
+  for (const Group &gr : L.grp) {
+    if (gr.i1 <= gr.i0) continue;
+    auto kern = gr.D == 2 ? dump_pairs<2> : dump_pairs<3>;
+    kern<<<(gr.i1 - gr.i0 + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
+        ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.i0, gr.i1, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
+        ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart),
+        (unsigned long long)cap, d_i, d_j, cnt);
+    HIP_OK(hipGetLastError());
+  }
+  unsigned long long total = 0;
+  HIP_OK(hipMemcpyAsync(&total, cnt, 8, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  *count = (int64_t)total;
   return MPSPH_OK;
 }
 

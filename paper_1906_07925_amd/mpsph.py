@@ -79,6 +79,7 @@ def lib():
             "mpsph_store": (C.c_int, [V, V, V]),
             "mpsph_debug_fields": (C.c_int, [V, I32, V]),
             "mpsph_debug_cells": (C.c_int, [V, V, V, C.POINTER(I64), C.POINTER(I32)]),
+            "mpsph_debug_pairs": (C.c_int, [V, I64, V, V, C.POINTER(I64)]),
             "mpsph_profile": (C.c_int, [V, I32]),
             "mpsph_profile_read": (C.c_int, [V, I32, C.POINTER(C.c_char_p), C.POINTER(I64),
                                              C.POINTER(C.c_double), C.POINTER(I32)]),
@@ -272,6 +273,19 @@ class Relaxer:
         _check(lib().mpsph_debug_cells(self._ctx, C.c_void_p(keys.data_ptr()), C.c_void_p(cstart.data_ptr()),
                                        C.byref(nc), C.byref(k)), "mpsph_debug_cells")
         return keys, cstart, k.value
+
+    def pairs(self):
+        """Ordered neighbour pairs (i, j) of the last step (load indices, unspecified order)."""
+        torch = self._torch
+        cnt = C.c_int64(0)
+        _check(lib().mpsph_debug_pairs(self._ctx, 0, None, None, C.byref(cnt)), "mpsph_debug_pairs")
+        m = cnt.value
+        pi = torch.empty((max(m, 1),), dtype=torch.int32, device="cuda")
+        pj = torch.empty((max(m, 1),), dtype=torch.int32, device="cuda")
+        _check(lib().mpsph_debug_pairs(self._ctx, m, C.c_void_p(pi.data_ptr()), C.c_void_p(pj.data_ptr()),
+                                       C.byref(cnt)), "mpsph_debug_pairs")
+        assert cnt.value == m
+        return pi[:m], pj[:m]
 
     def cell_log2(self) -> int:
         nc = C.c_int64(0)

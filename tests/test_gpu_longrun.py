@@ -1,0 +1,114 @@
+"""Long runs: the GPU trajectory and the FP64 oracle's diverge chaotically after a few dozen
+steps, so statistics of the relaxed state are compared instead of positions: density residual
+(L2 and L-infinity), edge-length ratio mean / std / 1st and 99th percentile, and the number of
+interface pairs.  Each statistic is averaged over the last fifth of the run (the percentiles
+are taken at the last step).  Oracle and GPU both run an ensemble of four inputs: the seeded
+state and three copies with every coordinate moved by one float32 ulp in a seeded random
+direction.  The ensemble means must agree within max(3 sigma, 1% of the oracle mean), sigma
+being the pooled spread of the two ensembles (the chaotic spread that any FP32 / FP64
+difference causes).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1906_07925_amd import workloads as W
+from tests import parity_util as PU
+
+pytestmark = pytest.mark.gpu
+
+STATS = ("residual_l2", "residual_linf", "elr_mean", "elr_std", "interface_pairs")
+RUNS = [("square_4k", 1.0, 200), ("annulus_262k", 0.02, 2000), ("cube_inclusion_2m", 0.002, 1000)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1906_07925_amd import mpsph as M
+    M.lib()
+    return torch
+
+
+def _elr_percentiles(nn, rho_t, typ, d):
+    elr = nn * rho_t ** (1.0 / d)
+    sel = (typ == 0) & np.isfinite(elr)
+    return np.percentile(elr[sel], [1, 99])
+
+
+def _summary(series, tail):
+    return {k: float(np.mean([m[k] for m in series[-tail:]])) for k in STATS}
+
+
+def oracle_run(spec, s0, x32, col, typ, steps):
+    op = O.OracleParams(spec, s0=s0)
+    x = x32.astype(np.float64)
+    t = typ.copy()
+    series = []
+    for s in range(steps):
+        keep = ("nn", "rho_t") if s == steps - 1 else ()
+        x, t1, r = O.step(op, x, col, t, s, want=keep)
+        series.append(r)
+        last = (r, t)
+        t = t1
+    r, tstart = last
+    return series, _elr_percentiles(r["nn"], r["rho_t"], tstart, spec["dim"])
+
+
+def gpu_run(torch, spec, s0, x32, col, typ, steps):
+    from paper_1906_07925_amd import mpsph as M
+    R = M.Relaxer(spec, n=x32.shape[0], s0=s0, debug=True)
+    R.load(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    series = []
+    for s in range(steps):
+        if s == steps - 1:
+            _, tstart = R.store()
+        R.step(1)
+        series.append(R.metrics())
+    nn = R.field("nn").cpu().numpy().astype(np.float64)
+    rho_t = R.field("rho_t").cpu().numpy().astype(np.float64)
+    R.close()
+    return series, _elr_percentiles(nn, rho_t, tstart.cpu().numpy(), spec["dim"])
+
+
+def _inputs(spec, x32, k=3, seed=11):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo = np.asarray(spec["lo"][:spec["dim"]], np.float32)
+    hi = np.asarray(spec["hi"][:spec["dim"]], np.float32)
+    out = [x32]
+    for _ in range(k):
+        sgn = rng.choice([-1.0, 1.0], size=x32.shape).astype(np.float32)
+        xp = np.nextafter(x32, x32 + sgn * np.float32(1.0)).astype(np.float32)
+        out.append(np.clip(xp, lo, hi))
+    return out
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,scale,steps", RUNS)
+def test_long_run_statistics(torch_cuda, name, scale, steps):
+    cfg = W.config(name, scale=scale)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = O.OracleParams(spec).s0
+    tail = max(steps // 5, 1)
+    ens = {"oracle": ([], []), "gpu": ([], [])}
+    for xin in _inputs(spec, x32):
+        ser, p = oracle_run(spec, s0, xin, col, typ, steps)
+        ens["oracle"][0].append(_summary(ser, tail))
+        ens["oracle"][1].append(p)
+        ser, p = gpu_run(torch_cuda, spec, s0, xin, col, typ, steps)
+        assert all(m["nonfinite"] == 0 for m in ser)
+        ens["gpu"][0].append(_summary(ser, tail))
+        ens["gpu"][1].append(p)
+    report = {}
+    cols = {k: {w: np.array([s[k] for s in ens[w][0]]) for w in ens} for k in STATS}
+    for q, pname in enumerate(("elr_p1", "elr_p99")):
+        cols[pname] = {w: np.array([p[q] for p in ens[w][1]]) for w in ens}
+    for k, v in cols.items():
+        mo, mg = v["oracle"].mean(), v["gpu"].mean()
+        sig = np.sqrt(0.5 * (v["oracle"].var(ddof=1) + v["gpu"].var(ddof=1)))
+        bound = max(3.0 * sig, 0.01 * abs(mo))
+        report[k] = (mg, mo, sig)
+        assert abs(mg - mo) <= bound, (k, mg, mo, sig, bound)
+    print(name, steps, {k: tuple(f"{x:.4g}" for x in v) for k, v in report.items()})

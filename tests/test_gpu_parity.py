@@ -256,3 +256,43 @@ def test_sigma_ramp_follows_device_step_counter(torch_cuda):
     _, _, r0 = O.step(op, x0.astype(np.float64), col, t1, 0)
     assert PU.rel(a, r1["a"]) < 1e-5
     assert PU.rel(a, r0["a"]) > 1e-3
+
+
+@pytest.mark.parametrize("name,scale", [("square_4k", 1.0), ("annulus_262k", 0.01), ("cube_inclusion_2m", 0.002),
+                                        ("rbf_cube_1m", 0.004)])
+def test_neighbour_pair_sets_match_oracle(torch_cuda, name, scale):
+    """The GPU's ordered neighbour pairs (before the type mask) equal the oracle's FP64 pair set,
+    except pairs within 1e-5 of the cut-off kappa h_ij, where FP32 and FP64 may decide
+    differently."""
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    cfg = W.config(name, scale=scale)
+    spec = cfg["spec"]
+    if spec["field"] == "rbf_exp":
+        rng = np.random.Generator(np.random.PCG64(W.BASE_SEED + 40))
+        spec = dict(spec, rbf_coeff=rng.normal(0.0, 0.1, size=spec["n_rbf"]))
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(spec, n=x32.shape[0])
+    s0 = _s0(spec)
+    R = M.Relaxer(spec, n=x32.shape[0], s0=s0)
+    R.load(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    R.step(1)
+    gi, gj = R.pairs()
+    m = R.metrics()
+    R.close()
+    n = x32.shape[0]
+    got = set((gi.cpu().numpy().astype(np.int64) * n + gj.cpu().numpy().astype(np.int64)).tolist())
+    assert len(got) == gi.shape[0]                       # no pair listed twice
+    op = O.OracleParams(spec, s0=s0)
+    x = x32.astype(np.float64)
+    pi, pj = O.pairs(op, x)
+    ref = set((pi * n + pj).tolist())
+    _, h = O.field(op, x)
+    diff = np.array(sorted(got ^ ref), dtype=np.int64)
+    if diff.size:
+        a, b = diff // n, diff % n
+        r = np.linalg.norm(x[a] - x[b], axis=1)
+        rc = spec.get("kappa", 2.0) * 0.5 * (h[a] + h[b])
+        assert np.all(np.abs(r - rc) < 1e-5 * rc), (diff.size, np.max(np.abs(r - rc) / rc))
+    assert m["pairs"] <= len(got)                         # the mask only removes pairs
+    print(name, n, "pairs", len(got), "differing (band)", diff.size)
