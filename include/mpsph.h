@@ -200,7 +200,8 @@ MPSPH_API int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out);
  * original order: cellbase + cx + 2^k cy + 4^k cz, where cellbase is 0 for a single domain and
  * in a batch the first cell of the domain's range of the global cell table), d_cell_start
  * (ncells + 1 uint32: index of the first sorted particle of each cell, last entry n) -- either
- * may be NULL -- and the host values ncells (all domains) and cell_log2 (of domain 0).
+ * may be NULL -- and the host values ncells (all domains) and cell_log2 (of domain 0).  The
+ * two host values are available from creation on; the arrays need a completed step.
  * Synchronises. */
 MPSPH_API int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cell_start, int64_t *ncells,
                       int32_t *cell_log2);
@@ -212,6 +213,36 @@ MPSPH_API int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cel
  * (host) receives the total number of pairs, which may exceed cap.  Synchronises.
  * Errors: MPSPH_E_INVALID (cap < 0, NULL arrays with cap > 0), MPSPH_E_STATE (no step yet). */
 MPSPH_API int mpsph_debug_pairs(mpsph_ctx *ctx, int64_t cap, uint32_t *d_i, uint32_t *d_j, int64_t *count);
+
+/* Replace the RBF coefficients c_k of the size field s = s0 exp(sum_k c_k G_k(x)) of one domain
+ * (n_rbf host doubles, copied).  s0 is kept (the field is not renormalised), the cell grid is
+ * kept and the neighbour search bounds are recomputed for the new field.  Synchronises.
+ * Errors: MPSPH_E_INVALID (domain out of range, field not MPSPH_RBF_EXP, non-finite value),
+ * MPSPH_E_UNSUPPORTED (the new field's slope makes the neighbour bound diverge; the old
+ * coefficients stay in place). */
+MPSPH_API int mpsph_set_field_coeff(mpsph_ctx *ctx, int32_t domain, const double *coeff);
+
+/* Gradient of a relaxation loss by a hand-written adjoint (reverse mode) of the step.
+ * From the current state, runs nsteps steps (the state and step counter advance exactly as
+ * with mpsph_step(ctx, nsteps)), evaluates at the final positions
+ *   L = (1/n) sum_i (rho_i / rho_t,i - 1)^2 + (lambda / n) sum_{i<j, C_i != C_j} W(r_ij, h_ij) / W(0, h_ij)
+ * (density summation of §3.3 Eq. 17 with the target density of Eq. 16; the second term is a
+ * smooth measure of the interface between colours, §3.3 Eq. 23-25), and propagates dL back
+ * through every step of Algorithm 1's loop: the pair forces (Eq. 18, 23), the force mapping
+ * (Eq. 30-31), both time steps (Eq. 29; through the particle that attains the minimum), the
+ * viscous pass (Eq. 20-22), the velocity and drift (Eq. 26-28) and the wall clamp (Eq. 32).
+ * Pair sets, type masks and re-tagging are held fixed (piecewise constant).
+ * Memory: the states at every ckpt_every-th step are kept, and a segment of ckpt_every steps is
+ * recomputed with its per-step record (about 80 bytes per particle and step plus the cell table);
+ * the library allocates this device memory on first use and keeps it until mpsph_destroy.
+ * Outputs (each may be NULL): *loss_out (host), grad_coeff_out[n_rbf] = dL/dc_k (host, only for
+ * MPSPH_RBF_EXP fields), d_grad_pos = dL/dx of the positions at the call (device, n x dim
+ * float32, load order, domain units).  Debug exports after the call refer to a recomputed
+ * step, not to the last one.  Single-domain contexts with a box region and a uniform or RBF
+ * field.  Synchronises.  Errors: MPSPH_E_INVALID (nsteps < 0, ckpt_every < 1), MPSPH_E_STATE,
+ * MPSPH_E_UNSUPPORTED (batched context, other region or field), MPSPH_E_NOMEM. */
+MPSPH_API int mpsph_grad(mpsph_ctx *ctx, int32_t nsteps, int32_t ckpt_every, double lambda, double *loss_out,
+                         double *grad_coeff_out, float *d_grad_pos);
 
 /* Per-kernel timing with HIP events on the context's stream.  enable = 1 starts recording
  * (resets the accumulators), 0 stops.  mpsph_profile_read() synchronises and returns, for up

@@ -214,4 +214,4 @@ def run(pr: Problem, x0: np.ndarray, coeff: np.ndarray, steps: int, lam: float, 
     L.backward()
     gx = x.grad.numpy().copy() if want_x0_grad else None
     gc = c.grad.numpy().copy() if c.grad is not None else np.zeros_like(np.asarray(coeff, dtype=np.float64))
-    return float(L), gc, gx, xs.detach().numpy(), typ, info
+    return float(L.detach()), gc, gx, xs.detach().numpy(), typ, info

@@ -41,6 +41,8 @@
 
 #include "mpsph.h"
 #include "mpsph_device.h"
+#include "adjoint.h"
+#include "pair_scan.h"
 #include "sort.h"
 
 using namespace mpsph;
@@ -125,136 +127,6 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
   wpos[i] = make_float4(o4.x, o4.y, o4.z, dd.sp.tau * spc);
   wjaux[i] = (uint32_t)c[0] | ((ct & 3u) << 12) | ((ct >> 2) << 14);
   wid[i] = sid[s];
-}
-
-// Neighbour candidates
-//
-// Particle i's candidates are the particles of every x-run of cells (fixed y, z) that meets the
-// ball of radius rs around it; in the row-major cell order each run is one contiguous range of
-// the sorted arrays.  A group of L lanes works on one particle: the L lanes take L rows at a
-// time (each reads its row's range from the cell table), form the prefix sum of the run lengths,
-// and then visit the flattened candidates of those rows L at a time, lane l taking every L-th
-// one (its row is found by a binary search over the prefix sums with cross-lane reads).  All
-// lanes of a wave thus run the same loop trip counts whatever the run lengths are.
-// body(j, drow, valid) is called for every slot; drow packs the row offsets (ci[1] - cy) in the
-// low and (ci[2] - cz) in the high 16 bits; invalid slots carry j = i.
-// ------------------------------------------------------------------------------------------
-// Lanes per particle in the pair kernels (measured on the 2M-particle graded cube: 4 is the
-// fastest of 1, 2, 4, 8, 16, 32).
-#ifndef MPSPH_LANES
-#define MPSPH_LANES 4
-#endif
-
-__device__ __forceinline__ float row_dy(uint32_t dr) { return (float)(int)(int16_t)(dr & 0xffffu); }
-__device__ __forceinline__ float row_dz(uint32_t dr) { return (float)((int)dr >> 16); }
-
-template <int D, int L, typename BodyF>
-__device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, const float *oi, float rs,
-                                               const GridDev &g, uint32_t cellbase, const uint32_t *__restrict__ cstart,
-                                               BodyF &&body) {
-  // a finite, non-negative radius keeps every cell range inside [0, gmax] (NaN -> 0)
-  rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
-  const float rs2 = rs * rs;
-  const int z0 = D == 3 ? max(0, ci[2] + (int)floorf(oi[2] - rs)) : 0;
-  const int z1 = D == 3 ? min(g.gmax, ci[2] + (int)floorf(oi[2] + rs)) : 0;
-  const int y0 = max(0, ci[1] + (int)floorf(oi[1] - rs));
-  const int y1 = min(g.gmax, ci[1] + (int)floorf(oi[1] + rs));
-  const int ny = y1 - y0 + 1;
-  const int nrows = ny * (z1 - z0 + 1);
-  const float inv_ny = 1.f / (float)ny;
-  const uint32_t nmax = (uint32_t)g.n;
-  uint32_t ncand = 0;
-  for (int q0 = 0; q0 < nrows; q0 += L) {
-    const int q = q0 + sub;
-    const int qz = (int)(((float)q + 0.5f) * inv_ny);   // q / ny (q, ny < 2^12)
-    const int cz = z0 + qz, cy = y0 + (q - qz * ny);
-    float ez = 0.f;
-    if constexpr (D == 3) {
-      const float lo = (float)(cz - ci[2]) - oi[2], hi = lo + 1.f;
-      ez = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
-    }
-    const float lo = (float)(cy - ci[1]) - oi[1], hi = lo + 1.f;
-    const float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
-    const float d2 = ey * ey + ez * ez;
-    const bool hit = q < nrows && d2 < rs2;
-    const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
-    const int x0 = max(0, ci[0] + (int)floorf(oi[0] - wx));
-    const int x1 = min(g.gmax, ci[0] + (int)floorf(oi[0] + wx));
-    uint32_t kb = (uint32_t)x0 | ((uint32_t)cy << g.k);
-    if constexpr (D == 3) kb |= (uint32_t)cz << (2 * g.k);
-    kb += cellbase;
-    uint32_t a = 0u, b = 0u;
-    if (hit) {
-      a = cstart[kb];
-      b = min(cstart[kb + (uint32_t)(x1 - x0) + 1u], nmax);
-    }
-    const uint32_t len = b > a ? b - a : 0u;
-    const uint32_t drow = ((uint32_t)(ci[1] - cy) & 0xffffu) | ((uint32_t)(D == 3 ? ci[2] - cz : 0) << 16);
-    uint32_t incl = len;
-#pragma unroll
-    for (int o = 1; o < L; o <<= 1) {
-      const uint32_t v = __shfl_up(incl, o, L);
-      if (sub >= o) incl += v;
-    }
-    const uint32_t T = __shfl(incl, L - 1, L);
-    const uint32_t excl = incl - len;
-    for (uint32_t t0 = 0; t0 < T; t0 += L) {
-      const uint32_t t = t0 + (uint32_t)sub;
-      int r = 0;
-#pragma unroll
-      for (int step = L / 2; step > 0; step >>= 1) {
-        const uint32_t v = __shfl(incl, r + step - 1, L);
-        if (v <= t) r += step;
-      }
-      const uint32_t ar = __shfl(a, r, L), er = __shfl(excl, r, L), dr = __shfl(drow, r, L);
-      const uint32_t j = ar + (t - er);
-      const bool valid = t < T && (int)j != i;
-      ncand += valid ? 1u : 0u;
-      body(valid ? (int)j : i, dr, valid);
-    }
-  }
-  return ncand;
-}
-
-// Sum / minimum across the L lanes of a group (fixed butterfly order).
-template <int L>
-__device__ __forceinline__ float group_sum(float x) {
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, L);
-  return x;
-}
-template <int L>
-__device__ __forceinline__ uint32_t group_sum_u(uint32_t x) {
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, L);
-  return x;
-}
-template <int L>
-__device__ __forceinline__ float group_min(float x) {
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, L));
-  return x;
-}
-
-// Minimum of the first time step: one atomic per block, spread over the kDtSlots words of the
-// block's domain.
-__device__ __forceinline__ void block_min_to_slots(float v, int lb, uint32_t *slots) {
-  __shared__ float wmin[kBlock / kWave];
-  for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0) wmin[threadIdx.x / kWave] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float m = wmin[0];
-    for (int w = 1; w < kBlock / kWave; ++w) m = fminf(m, wmin[w]);
-    if (m < INFINITY) atomic_min_pos(&slots[lb & (kDtSlots - 1)], m);
-  }
-}
-
-// First time step (Eq. 29 with v = 0): minimum over the domain's slots, every lane gets it.
-__device__ __forceinline__ float read_dt1(const uint32_t *slots) {
-  float v = __uint_as_float(slots[threadIdx.x & (kDtSlots - 1)]);
-  for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
-  return v < INFINITY ? v : 0.f;
 }
 
 // Pass 1: density (Eq. 17, self term included, radius kappa h_i) and
@@ -1365,6 +1237,10 @@ struct mpsph_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   int32_t graph_steps = 0;
+  // device memory of the gradient driver (checkpoints, step records, adjoint arrays), grown on
+  // demand by mpsph_grad and freed with the context
+  char *gmem = nullptr;
+  size_t gbytes = 0;
   template <typename T>
   T *at(size_t off) {
     return reinterpret_cast<T *>(ws + off);
@@ -1414,16 +1290,19 @@ void launch_pass1(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk
 }
 
 template <int D>
-void launch_pass2(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk) {
+void launch_pass2(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk, float4 *at_rec = nullptr,
+                  float4 *v_rec = nullptr) {
   const Layout &L = ctx->L;
   const bool dbg = ctx->dom[0].p.debug != 0;
+  float4 *at_o = at_rec ? at_rec : (dbg ? ctx->at<float4>(L.at) : nullptr);
+  float4 *v_o = v_rec ? v_rec : (dbg ? ctx->at<float4>(L.v) : nullptr);
   if (hk) hk->begin("pass_viscous_integrate");
   pass_viscous_integrate<D, MPSPH_LANES><<<gr.nb, kBlock, 0, st>>>(
       ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.b0, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
       ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
       ctx->at<uint32_t>(L.dtslots) + (size_t)gr.d0 * kDtSlots, ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off),
-      ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), dbg ? ctx->at<float4>(L.at) : nullptr,
-      dbg ? ctx->at<float4>(L.v) : nullptr, dbg ? ctx->at<float4>(L.dr) : nullptr, ctx->at<double>(L.partials));
+      ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), at_o, v_o, dbg ? ctx->at<float4>(L.dr) : nullptr,
+      ctx->at<double>(L.partials));
   if (hk) hk->end();
 }
 
@@ -1521,6 +1400,309 @@ int build_domains(int32_t ndom, const mpsph_params *params, const int64_t *n, st
   for (int d = 0; d < ndom; ++d)
     if ((rc = make_domain(&params[d], n[d], &(*doms)[d])) != MPSPH_OK) return rc;
   return plan(*doms, L);
+}
+
+
+// ------------------------------------------------------------------------------------------
+// Gradient driver: forward with checkpoints, loss, and the reverse sweep.  A segment of
+// ckpt steps is recomputed from its checkpoint with every step's sorted state and results
+// recorded, then its steps are reversed from last to first.
+// ------------------------------------------------------------------------------------------
+
+struct GradPlan {
+  int nck = 0, ckpt = 0;
+  size_t ck0 = 0, ck_stride = 0, ck_key = 0, ck_off = 0, ck_ct = 0, ck_id = 0;
+  size_t tp0 = 0, tp_stride = 0, tp_perm = 0, tp_wkey = 0, tp_wpos = 0, tp_wjaux = 0, tp_acc = 0, tp_at = 0,
+         tp_v = 0, tp_cstart = 0, tp_dts = 0;
+  size_t xbar = 0, xacc = 0, abv = 0, vtb = 0, abar = 0, fbar = 0, sbar = 0, e = 0, dtc = 0, pa = 0, pb = 0,
+         cpart = 0, cbar = 0, scal = 0, mback = 0;
+  size_t bytes = 0;
+};
+
+GradPlan grad_plan(int64_t n, uint32_t ncells, int nck, int ckpt, int nb1, int nbp) {
+  GradPlan P;
+  P.nck = nck;
+  P.ckpt = ckpt;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(std::max<size_t>(bytes, 4));
+    return at;
+  };
+  // checkpoint: the state arrays (key, offsets, type | colour, id)
+  size_t c = 0;
+  auto ctake = [&](size_t bytes) {
+    size_t at = c;
+    c += align_up(bytes);
+    return at;
+  };
+  P.ck_key = ctake(nn * 4);
+  P.ck_off = ctake(nn * 16);
+  P.ck_ct = ctake(nn * 4);
+  P.ck_id = ctake(nn * 4);
+  P.ck_stride = c;
+  P.ck0 = take(P.ck_stride * nck);
+  size_t t = 0;
+  auto ttake = [&](size_t bytes) {
+    size_t at = t;
+    t += align_up(bytes);
+    return at;
+  };
+  P.tp_perm = ttake(nn * 4);
+  P.tp_wkey = ttake(nn * 4);
+  P.tp_wpos = ttake(nn * 16);
+  P.tp_wjaux = ttake(nn * 4);
+  P.tp_acc = ttake(nn * 16);
+  P.tp_at = ttake(nn * 16);
+  P.tp_v = ttake(nn * 16);
+  P.tp_cstart = ttake(((size_t)ncells + 1) * 4);
+  P.tp_dts = ttake(kDtSlots * 4);
+  P.tp_stride = t;
+  P.tp0 = take(P.tp_stride * ckpt);
+  P.xbar = take(nn * 16);
+  P.xacc = take(nn * 16);
+  P.abv = take(nn * 16);
+  P.vtb = take(nn * 16);
+  P.abar = take(nn * 16);
+  P.fbar = take(nn * 16);
+  P.sbar = take(nn * 4);
+  P.e = take(nn * 4);
+  P.dtc = take(nn * 4);
+  P.pa = take((size_t)std::max(nb1, 1) * kNumPartials * 8);
+  P.pb = take((size_t)std::max(nbp, 1) * kNumPartials * 8);
+  P.cpart = take((size_t)std::max(nb1, 1) * kMaxRbf * 8);
+  P.cbar = take(kMaxRbf * 8);
+  P.scal = take(64);
+  P.mback = take(32 * 8);
+  P.bytes = o;
+  return P;
+}
+
+struct GradRun {
+  mpsph_ctx *ctx;
+  GradPlan P;
+  hipStream_t st;
+  const Group *gr;
+  int nb1;
+  char *g;
+  template <typename T>
+  T *at(size_t off) {
+    return reinterpret_cast<T *>(g + off);
+  }
+  char *ck(int k) { return g + P.ck0 + P.ck_stride * k; }
+  char *tp(int m) { return g + P.tp0 + P.tp_stride * m; }
+  TapeView view(int m) {
+    char *b = tp(m);
+    TapeView v;
+    v.wkey = reinterpret_cast<const uint32_t *>(b + P.tp_wkey);
+    v.wpos = reinterpret_cast<const float4 *>(b + P.tp_wpos);
+    v.wjaux = reinterpret_cast<const uint32_t *>(b + P.tp_wjaux);
+    v.cstart = reinterpret_cast<const uint32_t *>(b + P.tp_cstart);
+    v.perm = reinterpret_cast<const uint32_t *>(b + P.tp_perm);
+    v.acc = reinterpret_cast<const float4 *>(b + P.tp_acc);
+    v.at = reinterpret_cast<const float4 *>(b + P.tp_at);
+    v.v = reinterpret_cast<const float4 *>(b + P.tp_v);
+    v.dts = reinterpret_cast<const uint32_t *>(b + P.tp_dts);
+    return v;
+  }
+};
+
+// Copies the context state arrays to (save) or from (restore) checkpoint k.
+int copy_state(GradRun &R, int k, bool save) {
+  mpsph_ctx *ctx = R.ctx;
+  const Layout &L = ctx->L;
+  const size_t n = (size_t)L.n;
+  char *c = R.ck(k);
+  const size_t off_ws[4] = {L.s_key, L.s_off, L.s_ct, L.s_id};
+  const size_t off_ck[4] = {R.P.ck_key, R.P.ck_off, R.P.ck_ct, R.P.ck_id};
+  const size_t sz[4] = {n * 4, n * 16, n * 4, n * 4};
+  for (int a = 0; a < 4; ++a) {
+    void *ws = ctx->ws + off_ws[a];
+    void *cp = c + off_ck[a];
+    HIP_OK(hipMemcpyAsync(save ? cp : ws, save ? ws : cp, sz[a], hipMemcpyDeviceToDevice, R.st));
+  }
+  return MPSPH_OK;
+}
+
+// One forward step of the single domain with its record in step slot m.
+template <int D>
+int record_step(GradRun &R, int m) {
+  mpsph_ctx *ctx = R.ctx;
+  const Layout &L = ctx->L;
+  const int n = (int)L.n;
+  const uint32_t *skeys = nullptr, *perm = nullptr;
+  if (radix_sort(ctx->at<uint32_t>(L.s_key), ctx->at<uint32_t>(L.k0), ctx->at<uint32_t>(L.v0), ctx->at<uint32_t>(L.k1),
+                 ctx->at<uint32_t>(L.v1), ctx->at<uint32_t>(L.hist), n, L.key_bits, R.st, &skeys, &perm,
+                 nullptr) != hipSuccess)
+    return fail(ctx, MPSPH_E_DEVICE);
+  char *b = R.tp(m);
+  launch_group<D>(ctx, *R.gr, skeys, perm, kDtSlots, R.st, nullptr);
+  launch_pass1<D>(ctx, *R.gr, R.st, nullptr);
+  launch_pass2<D>(ctx, *R.gr, R.st, nullptr, reinterpret_cast<float4 *>(b + R.P.tp_at),
+                  reinterpret_cast<float4 *>(b + R.P.tp_v));
+  if (L.nrows > 0)
+    reduce_partials<<<L.nrows, 256, 0, R.st>>>(ctx->at<int2>(L.groups), ctx->at<double>(L.partials),
+                                                 ctx->at<double>(L.partials2));
+  finalize<<<1, 256, 0, R.st>>>(ctx->at<DomDev>(L.doms), ctx->at<double>(L.partials2), ctx->at<uint32_t>(L.dtslots),
+                                ctx->at<double>(L.metrics), ctx->at<int64_t>(L.stepctr));
+  HIP_OK(hipGetLastError());
+  const size_t nn = (size_t)n;
+  HIP_OK(hipMemcpyAsync(b + R.P.tp_perm, perm, nn * 4, hipMemcpyDeviceToDevice, R.st));
+  HIP_OK(hipMemcpyAsync(b + R.P.tp_wkey, ctx->at<uint32_t>(L.w_key), nn * 4, hipMemcpyDeviceToDevice, R.st));
+  HIP_OK(hipMemcpyAsync(b + R.P.tp_wpos, ctx->at<float4>(L.w_pos), nn * 16, hipMemcpyDeviceToDevice, R.st));
+  HIP_OK(hipMemcpyAsync(b + R.P.tp_wjaux, ctx->at<uint32_t>(L.w_jaux), nn * 4, hipMemcpyDeviceToDevice, R.st));
+  HIP_OK(hipMemcpyAsync(b + R.P.tp_acc, ctx->at<float4>(L.acc), nn * 16, hipMemcpyDeviceToDevice, R.st));
+  HIP_OK(hipMemcpyAsync(b + R.P.tp_cstart, ctx->at<uint32_t>(L.cstart), ((size_t)L.ncells + 1) * 4,
+                        hipMemcpyDeviceToDevice, R.st));
+  HIP_OK(hipMemcpyAsync(b + R.P.tp_dts, ctx->at<uint32_t>(L.dtslots), kDtSlots * 4, hipMemcpyDeviceToDevice, R.st));
+  return MPSPH_OK;
+}
+
+// Adjoint of the loss at the current state: x-bar (previous state order) and c-bar.
+template <int D>
+int loss_backward(GradRun &R, double lam) {
+  mpsph_ctx *ctx = R.ctx;
+  const Layout &L = ctx->L;
+  const Domain &dm = ctx->dom[0];
+  const int n = (int)L.n;
+  const DomDev *dom = ctx->at<DomDev>(L.doms);
+  const uint32_t *skeys = nullptr, *perm = nullptr;
+  if (radix_sort(ctx->at<uint32_t>(L.s_key), ctx->at<uint32_t>(L.k0), ctx->at<uint32_t>(L.v0), ctx->at<uint32_t>(L.k1),
+                 ctx->at<uint32_t>(L.v1), ctx->at<uint32_t>(L.hist), n, L.key_bits, R.st, &skeys, &perm,
+                 nullptr) != hipSuccess)
+    return fail(ctx, MPSPH_E_DEVICE);
+  launch_group<D>(ctx, *R.gr, skeys, perm, kDtSlots, R.st, nullptr);
+  const int nbp = R.gr->nb;
+  loss_density<D, MPSPH_LANES><<<nbp, kBlock, 0, R.st>>>(dom, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
+                                                       ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart),
+                                                       R.at<float>(R.P.e), R.at<double>(R.P.pb));
+  loss_value<<<1, 256, 0, R.st>>>(R.at<double>(R.P.pb), nbp, 1.0 / n, lam, R.at<double>(R.P.scal) + 1);
+  // every neighbour j whose support reaches k: r < kappa h_j <= kappa h_k / (1 - kappa L_h)
+  const double Lh = dm.p.tau * dm.d.lip;
+  const double kl = dm.p.kappa * Lh;
+  const float reach = kl < 0.95 ? (float)(dm.p.kappa / (1.0 - kl) * (1.0 + 1e-4)) : 1e30f;
+  loss_grad<D, MPSPH_LANES><<<nbp, kBlock, 0, R.st>>>(dom, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
+                                                    ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart),
+                                                    R.at<float>(R.P.e), (float)(2.0 / n), (float)(lam / n), reach,
+                                                    R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar));
+  TapeView tv{};
+  tv.wkey = ctx->at<uint32_t>(L.w_key);
+  tv.wpos = ctx->at<float4>(L.w_pos);
+  tv.perm = perm;
+  adj_field<D><<<R.nb1, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar),
+                                           R.at<float4>(R.P.xbar), R.at<double>(R.P.cpart));
+  if (dm.p.field == MPSPH_RBF_EXP && dm.p.n_rbf > 0)
+    adj_sum_coeff<<<1, kMaxRbf, 0, R.st>>>(R.at<double>(R.P.cpart), R.nb1, dm.p.n_rbf, R.at<double>(R.P.cbar));
+  HIP_OK(hipGetLastError());
+  return MPSPH_OK;
+}
+
+// Reverse of the recorded step m (step index t of the run).
+template <int D>
+int step_backward(GradRun &R, int m, int64_t t) {
+  mpsph_ctx *ctx = R.ctx;
+  const Layout &L = ctx->L;
+  const Domain &dm = ctx->dom[0];
+  const DomDev *dom = ctx->at<DomDev>(L.doms);
+  const TapeView tv = R.view(m);
+  const int nbp = R.gr->nb;
+  uint32_t *minbits = reinterpret_cast<uint32_t *>(R.at<char>(R.P.scal) + 32);
+  uint32_t *argmin = minbits + 1;
+  double *t1bar = R.at<double>(R.P.scal);
+  adj_init<<<1, 1, 0, R.st>>>(minbits, argmin);
+  adj_drift<D><<<R.nb1, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.xbar), R.at<float4>(R.P.xacc),
+                                           R.at<float4>(R.P.abv), R.at<float4>(R.P.vtb), R.at<float>(R.P.dtc), minbits,
+                                           R.at<double>(R.P.pa));
+  adj_visc<D, MPSPH_LANES><<<nbp, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.abv), R.at<float4>(R.P.vtb),
+                                                   R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar),
+                                                   R.at<float4>(R.P.abar), R.at<float>(R.P.dtc), minbits, argmin,
+                                                   R.at<double>(R.P.pb));
+  adj_sum_dt<<<1, 256, 0, R.st>>>(R.at<double>(R.P.pa), R.nb1, R.at<double>(R.P.pb), nbp,
+                                  (float)dt2_factor(&dm.p), t1bar);
+  adj_fbar<D><<<R.nb1, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.abar), t1bar, argmin, R.at<float>(R.P.sbar),
+                                          R.at<float4>(R.P.fbar));
+  adj_force<D, MPSPH_LANES><<<nbp, kBlock, 0, R.st>>>(dom, tv, (float)t, R.at<float4>(R.P.fbar),
+                                                    R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar));
+  adj_field<D><<<R.nb1, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar),
+                                           R.at<float4>(R.P.xbar), R.at<double>(R.P.cpart));
+  if (dm.p.field == MPSPH_RBF_EXP && dm.p.n_rbf > 0)
+    adj_sum_coeff<<<1, kMaxRbf, 0, R.st>>>(R.at<double>(R.P.cpart), R.nb1, dm.p.n_rbf, R.at<double>(R.P.cbar));
+  HIP_OK(hipGetLastError());
+  return MPSPH_OK;
+}
+
+template <int D>
+int grad_run(mpsph_ctx *ctx, int nsteps, int ckpt, double lam, double *loss_out, double *grad_coeff,
+             float *d_grad_pos) {
+  const Layout &L = ctx->L;
+  const Domain &dm = ctx->dom[0];
+  const int n = (int)L.n;
+  GradRun R;
+  R.ctx = ctx;
+  R.st = ctx->stream;
+  R.gr = &L.grp[D - 2];
+  R.nb1 = (n + kBlock - 1) / kBlock;
+  const int nseg = nsteps > 0 ? (nsteps + ckpt - 1) / ckpt : 0;
+  const int seg_len = std::min(ckpt, std::max(nsteps, 1));
+  R.P = grad_plan(n, L.ncells, nseg + 1, seg_len, R.nb1, R.gr->nb);
+  if (ctx->gbytes < R.P.bytes) {
+    if (ctx->gmem) (void)hipFree(ctx->gmem);
+    ctx->gmem = nullptr;
+    ctx->gbytes = 0;
+    if (hipMalloc((void **)&ctx->gmem, R.P.bytes) != hipSuccess) return MPSPH_E_NOMEM;
+    ctx->gbytes = R.P.bytes;
+  }
+  R.g = ctx->gmem;
+  const int64_t t0 = ctx->steps_done;
+  EventHook *hk = ctx->hook.on ? &ctx->hook : nullptr;
+  HIP_OK(hipMemsetAsync(R.at<double>(R.P.cbar), 0, kMaxRbf * 8, R.st));
+  // forward: checkpoints at the start of every segment, the final state in slot nseg
+  if (hk) hk->begin("grad_forward");
+  for (int sg = 0; sg < nseg; ++sg) {
+    int rc = copy_state(R, sg, true);
+    if (rc) return rc;
+    const int len = std::min(ckpt, nsteps - sg * ckpt);
+    if ((rc = enqueue(ctx, len, R.st, nullptr)) != MPSPH_OK) return rc;
+  }
+  int rc = copy_state(R, nseg, true);
+  if (rc) return rc;
+  if (hk) hk->end();
+  if (hk) hk->begin("grad_backward");
+  HIP_OK(hipMemcpyAsync(R.at<double>(R.P.mback), ctx->at<double>(L.metrics), 32 * 8, hipMemcpyDeviceToDevice, R.st));
+  if (n > 0) {
+    if ((rc = loss_backward<D>(R, lam)) != MPSPH_OK) return rc;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      const int len = std::min(ckpt, nsteps - sg * ckpt);
+      if ((rc = copy_state(R, sg, false)) != MPSPH_OK) return rc;
+      set_step<<<1, 1, 0, R.st>>>(ctx->at<int64_t>(L.stepctr), t0 + (int64_t)sg * ckpt);
+      for (int m = 0; m < len; ++m)
+        if ((rc = record_step<D>(R, m)) != MPSPH_OK) return rc;
+      for (int m = len - 1; m >= 0; --m)
+        if ((rc = step_backward<D>(R, m, t0 + (int64_t)sg * ckpt + m)) != MPSPH_OK) return rc;
+    }
+    if (d_grad_pos)
+      adj_store_pos<D><<<R.nb1, kBlock, 0, R.st>>>(n, reinterpret_cast<const uint32_t *>(R.ck(0) + R.P.ck_id),
+                                                   R.at<float4>(R.P.xbar), (float)dm.d.inv_cs, d_grad_pos);
+  } else {
+    HIP_OK(hipMemsetAsync(R.at<double>(R.P.scal) + 1, 0, 8, R.st));
+  }
+  // back to the state after the last step
+  if ((rc = copy_state(R, nseg, false)) != MPSPH_OK) return rc;
+  HIP_OK(hipMemcpyAsync(ctx->at<double>(L.metrics), R.at<double>(R.P.mback), 32 * 8, hipMemcpyDeviceToDevice, R.st));
+  set_step<<<1, 1, 0, R.st>>>(ctx->at<int64_t>(L.stepctr), t0 + nsteps);
+  if (hk) hk->end();
+  HIP_OK(hipGetLastError());
+  double loss = 0.0;
+  HIP_OK(hipMemcpyAsync(&loss, R.at<double>(R.P.scal) + 1, 8, hipMemcpyDeviceToHost, R.st));
+  std::vector<double> gc(kMaxRbf, 0.0);
+  HIP_OK(hipMemcpyAsync(gc.data(), R.at<double>(R.P.cbar), kMaxRbf * 8, hipMemcpyDeviceToHost, R.st));
+  HIP_OK(hipStreamSynchronize(R.st));
+  ctx->steps_done = t0 + nsteps;
+  if (loss_out) *loss_out = loss;
+  if (grad_coeff && dm.p.field == MPSPH_RBF_EXP)
+    for (int m = 0; m < dm.p.n_rbf; ++m) grad_coeff[m] = gc[m];
+  return MPSPH_OK;
 }
 
 }  // namespace
@@ -1769,10 +1951,10 @@ int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out) {
 
 int mpsph_debug_cells(mpsph_ctx *ctx, uint32_t *d_key, uint32_t *d_cell_start, int64_t *ncells, int32_t *cell_log2) {
   if (!ctx) return MPSPH_E_INVALID;
-  if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
+  if (ctx->poisoned) return MPSPH_E_STATE;
   if (ncells) *ncells = ctx->L.ncells;
   if (cell_log2) *cell_log2 = ctx->dom[ctx->L.internal[0]].d.k;
-  if ((d_key || d_cell_start) && ctx->steps_done == 0) return MPSPH_E_STATE;
+  if ((d_key || d_cell_start) && (!ctx->loaded || ctx->steps_done == 0)) return MPSPH_E_STATE;
   const Layout &L = ctx->L;
   const int n = (int)L.n;
   if (d_key && n > 0) {
@@ -1813,6 +1995,50 @@ int mpsph_debug_pairs(mpsph_ctx *ctx, int64_t cap, uint32_t *d_i, uint32_t *d_j,
   return MPSPH_OK;
 }
 
+int mpsph_set_field_coeff(mpsph_ctx *ctx, int32_t domain, const double *coeff) {
+  if (!ctx || !coeff || domain < 0 || domain >= ctx->L.ndom) return MPSPH_E_INVALID;
+  if (ctx->poisoned) return MPSPH_E_STATE;
+  const int k = ctx->L.internal[domain];
+  Domain &dm = ctx->dom[k];
+  if (dm.p.field != MPSPH_RBF_EXP) return MPSPH_E_INVALID;
+  for (int m = 0; m < dm.p.n_rbf; ++m)
+    if (!std::isfinite(coeff[m])) return MPSPH_E_INVALID;
+  std::vector<double> saved = dm.rbf_coeff;
+  dm.rbf_coeff.assign(coeff, coeff + dm.p.n_rbf);
+  dm.p.rbf_coeff = dm.rbf_coeff.data();
+  // bounds of the field, search radius and h_max for the new coefficients on the same grid
+  mpsph_params q = dm.p;
+  q.cell_log2 = dm.d.k;
+  Derived nd;
+  if (derive(&q, dm.n, dm.s0, &nd) != MPSPH_OK) {
+    dm.rbf_coeff = saved;
+    dm.p.rbf_coeff = dm.rbf_coeff.data();
+    return MPSPH_E_UNSUPPORTED;
+  }
+  dm.d = nd;
+  const Layout &L = ctx->L;
+  const DomDev dd = domain_device(dm, ctx->at<int>(L.rbf_c), ctx->at<float>(L.rbf_o), ctx->at<float>(L.rbf_k));
+  std::vector<float> rk(std::max(dm.p.n_rbf, 1));
+  for (int m = 0; m < dm.p.n_rbf; ++m) rk[m] = (float)coeff[m];
+  HIP_OK(hipStreamSynchronize(ctx->stream));
+  HIP_OK(hipMemcpy(ctx->at<DomDev>(L.doms) + k, &dd, sizeof(DomDev), hipMemcpyHostToDevice));
+  if (dm.p.n_rbf > 0)
+    HIP_OK(hipMemcpy(ctx->at<float>(L.rbf_k) + dm.rbf0, rk.data(), (size_t)dm.p.n_rbf * 4, hipMemcpyHostToDevice));
+  return MPSPH_OK;
+}
+
+int mpsph_grad(mpsph_ctx *ctx, int32_t nsteps, int32_t ckpt_every, double lambda, double *loss_out,
+               double *grad_coeff_out, float *d_grad_pos) {
+  if (!ctx || nsteps < 0 || ckpt_every < 1 || !std::isfinite(lambda)) return MPSPH_E_INVALID;
+  if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
+  const Domain &dm = ctx->dom[0];
+  if (ctx->L.ndom != 1 || dm.p.geometry != MPSPH_BOX ||
+      (dm.p.field != MPSPH_RBF_EXP && dm.p.field != MPSPH_UNIFORM))
+    return MPSPH_E_UNSUPPORTED;
+  return dm.p.dim == 2 ? grad_run<2>(ctx, nsteps, ckpt_every, lambda, loss_out, grad_coeff_out, d_grad_pos)
+                       : grad_run<3>(ctx, nsteps, ckpt_every, lambda, loss_out, grad_coeff_out, d_grad_pos);
+}
+
 int mpsph_profile(mpsph_ctx *ctx, int32_t enable) {
   if (!ctx) return MPSPH_E_INVALID;
   if (ctx->poisoned) return MPSPH_E_STATE;
@@ -1842,6 +2068,7 @@ void mpsph_destroy(mpsph_ctx *ctx) {
   drop_graph(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->owns && ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->gmem) (void)hipFree(ctx->gmem);
   delete ctx;
 }
 

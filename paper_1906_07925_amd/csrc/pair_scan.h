@@ -1,0 +1,141 @@
+// Neighbour candidate scan and lane-group helpers shared by the forward pair passes and
+// their adjoints (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mpsph_device.h"
+
+namespace mpsph {
+
+// Neighbour candidates
+//
+// Particle i's candidates are the particles of every x-run of cells (fixed y, z) that meets the
+// ball of radius rs around it; in the row-major cell order each run is one contiguous range of
+// the sorted arrays.  A group of L lanes works on one particle: the L lanes take L rows at a
+// time (each reads its row's range from the cell table), form the prefix sum of the run lengths,
+// and then visit the flattened candidates of those rows L at a time, lane l taking every L-th
+// one (its row is found by a binary search over the prefix sums with cross-lane reads).  All
+// lanes of a wave thus run the same loop trip counts whatever the run lengths are.
+// body(j, drow, valid) is called for every slot; drow packs the row offsets (ci[1] - cy) in the
+// low and (ci[2] - cz) in the high 16 bits; invalid slots carry j = i.
+// ------------------------------------------------------------------------------------------
+// Lanes per particle in the pair kernels (measured on the 2M-particle graded cube: 4 is the
+// fastest of 1, 2, 4, 8, 16, 32).
+#ifndef MPSPH_LANES
+#define MPSPH_LANES 4
+#endif
+
+__device__ __forceinline__ float row_dy(uint32_t dr) { return (float)(int)(int16_t)(dr & 0xffffu); }
+__device__ __forceinline__ float row_dz(uint32_t dr) { return (float)((int)dr >> 16); }
+
+template <int D, int L, typename BodyF>
+__device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, const float *oi, float rs,
+                                               const GridDev &g, uint32_t cellbase, const uint32_t *__restrict__ cstart,
+                                               BodyF &&body) {
+  // a finite, non-negative radius keeps every cell range inside [0, gmax] (NaN -> 0)
+  rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
+  const float rs2 = rs * rs;
+  const int z0 = D == 3 ? max(0, ci[2] + (int)floorf(oi[2] - rs)) : 0;
+  const int z1 = D == 3 ? min(g.gmax, ci[2] + (int)floorf(oi[2] + rs)) : 0;
+  const int y0 = max(0, ci[1] + (int)floorf(oi[1] - rs));
+  const int y1 = min(g.gmax, ci[1] + (int)floorf(oi[1] + rs));
+  const int ny = y1 - y0 + 1;
+  const int nrows = ny * (z1 - z0 + 1);
+  const float inv_ny = 1.f / (float)ny;
+  const uint32_t nmax = (uint32_t)g.n;
+  uint32_t ncand = 0;
+  for (int q0 = 0; q0 < nrows; q0 += L) {
+    const int q = q0 + sub;
+    const int qz = (int)(((float)q + 0.5f) * inv_ny);   // q / ny (q, ny < 2^12)
+    const int cz = z0 + qz, cy = y0 + (q - qz * ny);
+    float ez = 0.f;
+    if constexpr (D == 3) {
+      const float lo = (float)(cz - ci[2]) - oi[2], hi = lo + 1.f;
+      ez = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
+    }
+    const float lo = (float)(cy - ci[1]) - oi[1], hi = lo + 1.f;
+    const float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
+    const float d2 = ey * ey + ez * ez;
+    const bool hit = q < nrows && d2 < rs2;
+    const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
+    const int x0 = max(0, ci[0] + (int)floorf(oi[0] - wx));
+    const int x1 = min(g.gmax, ci[0] + (int)floorf(oi[0] + wx));
+    uint32_t kb = (uint32_t)x0 | ((uint32_t)cy << g.k);
+    if constexpr (D == 3) kb |= (uint32_t)cz << (2 * g.k);
+    kb += cellbase;
+    uint32_t a = 0u, b = 0u;
+    if (hit) {
+      a = cstart[kb];
+      b = min(cstart[kb + (uint32_t)(x1 - x0) + 1u], nmax);
+    }
+    const uint32_t len = b > a ? b - a : 0u;
+    const uint32_t drow = ((uint32_t)(ci[1] - cy) & 0xffffu) | ((uint32_t)(D == 3 ? ci[2] - cz : 0) << 16);
+    uint32_t incl = len;
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, L);
+      if (sub >= o) incl += v;
+    }
+    const uint32_t T = __shfl(incl, L - 1, L);
+    const uint32_t excl = incl - len;
+    for (uint32_t t0 = 0; t0 < T; t0 += L) {
+      const uint32_t t = t0 + (uint32_t)sub;
+      int r = 0;
+#pragma unroll
+      for (int step = L / 2; step > 0; step >>= 1) {
+        const uint32_t v = __shfl(incl, r + step - 1, L);
+        if (v <= t) r += step;
+      }
+      const uint32_t ar = __shfl(a, r, L), er = __shfl(excl, r, L), dr = __shfl(drow, r, L);
+      const uint32_t j = ar + (t - er);
+      const bool valid = t < T && (int)j != i;
+      ncand += valid ? 1u : 0u;
+      body(valid ? (int)j : i, dr, valid);
+    }
+  }
+  return ncand;
+}
+
+// Sum / minimum across the L lanes of a group (fixed butterfly order).
+template <int L>
+__device__ __forceinline__ float group_sum(float x) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, L);
+  return x;
+}
+template <int L>
+__device__ __forceinline__ uint32_t group_sum_u(uint32_t x) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, L);
+  return x;
+}
+template <int L>
+__device__ __forceinline__ float group_min(float x) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, L));
+  return x;
+}
+
+// Minimum of the first time step: one atomic per block, spread over the kDtSlots words of the
+// block's domain.
+__device__ __forceinline__ void block_min_to_slots(float v, int lb, uint32_t *slots) {
+  __shared__ float wmin[kBlock / kWave];
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) wmin[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = wmin[0];
+    for (int w = 1; w < kBlock / kWave; ++w) m = fminf(m, wmin[w]);
+    if (m < INFINITY) atomic_min_pos(&slots[lb & (kDtSlots - 1)], m);
+  }
+}
+
+// First time step (Eq. 29 with v = 0): minimum over the domain's slots, every lane gets it.
+__device__ __forceinline__ float read_dt1(const uint32_t *slots) {
+  float v = __uint_as_float(slots[threadIdx.x & (kDtSlots - 1)]);
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+  return v < INFINITY ? v : 0.f;
+}
+
+}  // namespace mpsph

@@ -80,6 +80,8 @@ def lib():
             "mpsph_debug_fields": (C.c_int, [V, I32, V]),
             "mpsph_debug_cells": (C.c_int, [V, V, V, C.POINTER(I64), C.POINTER(I32)]),
             "mpsph_debug_pairs": (C.c_int, [V, I64, V, V, C.POINTER(I64)]),
+            "mpsph_set_field_coeff": (C.c_int, [V, I32, C.POINTER(C.c_double)]),
+            "mpsph_grad": (C.c_int, [V, I32, I32, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), V]),
             "mpsph_profile": (C.c_int, [V, I32]),
             "mpsph_profile_read": (C.c_int, [V, I32, C.POINTER(C.c_char_p), C.POINTER(I64),
                                              C.POINTER(C.c_double), C.POINTER(I32)]),
@@ -293,6 +295,24 @@ class Relaxer:
         _check(lib().mpsph_debug_cells(self._ctx, None, None, C.byref(nc), C.byref(k)), "mpsph_debug_cells")
         return k.value
 
+    def set_field_coeff(self, coeff, domain: int = 0):
+        """New RBF coefficients of one domain's size field (s0 and the cell grid are kept)."""
+        c = np.ascontiguousarray(np.asarray(coeff, dtype=np.float64).reshape(-1))
+        _check(lib().mpsph_set_field_coeff(self._ctx, int(domain), c.ctypes.data_as(C.POINTER(C.c_double))),
+               "mpsph_set_field_coeff")
+
+    def grad(self, nsteps: int, ckpt_every: int = 10, lam: float = 1.0, n_rbf: int = 0, want_pos: bool = False):
+        """Run nsteps steps and return (loss, dL/dcoeff (numpy, n_rbf), dL/dx0 (device tensor or
+        None)) by the library's adjoint."""
+        torch = self._torch
+        loss = C.c_double(0.0)
+        gc = np.zeros(max(int(n_rbf), 1), dtype=np.float64)
+        gx = torch.empty(self._pos_shape(), dtype=torch.float32, device="cuda") if want_pos else None
+        _check(lib().mpsph_grad(self._ctx, int(nsteps), int(ckpt_every), float(lam), C.byref(loss),
+                                gc.ctypes.data_as(C.POINTER(C.c_double)),
+                                C.c_void_p(gx.data_ptr()) if gx is not None else None), "mpsph_grad")
+        return loss.value, gc[:int(n_rbf)], gx
+
     def profile(self, on: bool):
         _check(lib().mpsph_profile(self._ctx, 1 if on else 0), "mpsph_profile")
 
@@ -316,3 +336,27 @@ def batch_workspace_bytes(specs: list, ns: list, cell_log2: int = -1) -> int:
     ps = (Params * len(specs))(*[m[0] for m in made])
     cnt = (C.c_int64 * len(specs))(*[int(k) for k in ns])
     return int(lib().mpsph_batch_workspace_bytes(len(specs), ps, cnt))
+
+
+def relax_loss_function():
+    """A torch.autograd.Function: RelaxLoss.apply(coeff, x0, relaxer, colour, ptype, nsteps,
+    ckpt_every, lam) runs the relaxation from positions x0 with RBF coefficients coeff (float64
+    CPU tensor) and returns the loss; backward supplies dL/dcoeff and dL/dx0 from the library's
+    adjoint, computed together with the forward."""
+    import torch
+
+    class RelaxLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, coeff, x0, relaxer, colour, ptype, nsteps, ckpt_every, lam):
+            relaxer.set_field_coeff(coeff.detach().cpu().numpy())
+            relaxer.load(x0.detach(), colour, ptype)
+            loss, gc, gx = relaxer.grad(nsteps, ckpt_every, lam, n_rbf=coeff.numel(), want_pos=True)
+            fctx.save_for_backward(torch.as_tensor(gc, dtype=coeff.dtype), gx.reshape(x0.shape).to(x0.dtype))
+            return torch.tensor(loss, dtype=torch.float64)
+
+        @staticmethod
+        def backward(fctx, gout):
+            gc, gx = fctx.saved_tensors
+            return (gout.to(gc.dtype) * gc, gout.to(gx.device, gx.dtype) * gx, None, None, None, None, None, None)
+
+    return RelaxLoss
