@@ -11,7 +11,9 @@ i != j inside the cut-off that pass the type mask, counted on the device each st
 rate, per-kernel times measured with HIP events on the library's stream, the roofline entry of
 the dominant kernel, the CPU oracle timed on the host on a bounded sample, and (object
 "batched") 64 independent mixed 2D/3D domains relaxed in one batched context against the same
-domains solved one after the other.
+domains solved one after the other, and (object "adjoint", field "adjoint_forward_ratio") the
+reverse sweep of the gradient of the relaxation loss over 50 steps of the 2^20-particle RBF cube
+against 50 forward steps.
 """
 from __future__ import annotations
 
@@ -42,7 +44,7 @@ PEAK_HBM_GBS = 8000.0
 FLOPS_PER_PAIR = {"pass_density_force": 49, "pass_viscous_integrate": 50}
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1906_07925_amd", "csrc", f)
-                  for f in ("mpsph.hip", "mpsph_device.h", "sort.hip", "sort.h")]
+                  for f in ("mpsph.hip", "mpsph_device.h", "pair_scan.h", "adjoint.h", "sort.hip", "sort.h")]
 
 
 def kernel_source_digest() -> str:
@@ -133,6 +135,44 @@ def batched_run(torch, M, W, steps: int, warmup: int, graph_steps: int = 10):
             "final_state_bit_identical": bool(same)}
 
 
+def adjoint_run(torch, M, W, steps: int = 50, ckpt: int = 10, lam: float = 1.0):
+    """Gradient of the relaxation loss with respect to the 32 RBF coefficients of the size field
+    on the 2^20-particle RBF cube: time of the reverse sweep (loss, segment recomputation from
+    the checkpoints and the adjoint kernels; HIP events on the library stream around it) over
+    the time of the same number of plain forward steps (synchronised wall clock)."""
+    cfg = W.config("rbf_cube_1m")
+    rng = np.random.Generator(np.random.PCG64(W.BASE_SEED + 40))
+    coeff = rng.normal(0.0, 0.1, size=cfg["spec"]["n_rbf"])
+    x, col, typ = W.make_state(cfg)
+    n = x.shape[0]
+    spec = dict(cfg["spec"], n=n, rbf_coeff=coeff)
+    args = (torch.from_numpy(x.astype(np.float32)).cuda(), torch.from_numpy(col).cuda(),
+            torch.from_numpy(typ).cuda())
+    R = M.Relaxer(spec, n=n)
+    R.load(*args)
+    R.grad(steps, ckpt, lam, n_rbf=len(coeff))          # allocation and first-use costs
+    R.load(*args)
+    R.step(steps)
+    torch.cuda.synchronize()
+    R.load(*args)
+    t0 = time.perf_counter()
+    R.step(steps)
+    torch.cuda.synchronize()
+    fwd_ms = 1e3 * (time.perf_counter() - t0)
+    R.profile(True)
+    R.load(*args)
+    loss, gc, _ = R.grad(steps, ckpt, lam, n_rbf=len(coeff))
+    kern = R.profile_read()
+    R.profile(False)
+    R.close()
+    bwd_ms = kern["grad_backward"][1]
+    print(f"[bench] adjoint: forward {fwd_ms:.1f} ms, reverse {bwd_ms:.1f} ms for {steps} steps",
+          file=sys.stderr, flush=True)
+    return {"workload": "rbf_cube_1m", "particles": n, "steps": steps, "checkpoint_every": ckpt, "lambda": lam,
+            "forward_ms": fwd_ms, "grad_forward_ms": kern["grad_forward"][1], "backward_ms": bwd_ms,
+            "ratio": bwd_ms / fwd_ms, "loss": loss, "grad_norm": float(np.linalg.norm(gc))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +182,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-domain batched comparison")
     ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -230,6 +271,9 @@ def main():
     R.close()
     if not args.no_batched:
         out["batched"] = batched_run(torch, M, W, args.batched_steps, 10)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_run(torch, M, W)
+        out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, x, col, typ)
     print(json.dumps(out))
