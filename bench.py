@@ -54,14 +54,17 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
+def load_traffic(kernel: str, cell_log2: int, lanes: int):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, valid only
-    while the kernel sources are unchanged since the counters were taken."""
+    while the kernel sources are unchanged since the counters were taken and for the same cell
+    size and lanes per particle."""
     try:
         t = json.load(open(os.path.join(TRAFFIC_DIR, f"traffic_{kernel}_{WORKLOAD}.json")))
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    if t.get("cell_log2") != cell_log2 or t.get("lanes") != lanes:
         return None
     return t.get("bytes_per_launch")
 
@@ -178,7 +181,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cell-log2", type=int, default=-1)
+    ap.add_argument("--config", type=str, default="",
+                    help="K,L: cells per axis 2^K and L lanes per particle instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-domain batched comparison")
     ap.add_argument("--batched-steps", type=int, default=100)
@@ -202,8 +206,17 @@ def main():
 
     dev_x = torch.from_numpy(x.astype(np.float32)).cuda()
     dev_c = torch.from_numpy(col).cuda()
-    R = M.Relaxer(spec, n=n, cell_log2=args.cell_log2)
-    R.load(dev_x, dev_c)
+    R = M.Relaxer(spec, n=n)
+    if args.config:
+        k, lanes = (int(v) for v in args.config.split(","))
+        R.configure(k, lanes)
+        R.load(dev_x, dev_c)
+        tuned = False
+    else:
+        k, lanes = R.autotune(dev_x, dev_c, probe_steps=10)
+        tuned = True
+    print(f"[bench] configuration: 2^{k} cells per axis, {lanes} lanes per particle"
+          f"{' (autotuned)' if tuned else ''}", file=sys.stderr, flush=True)
 
     if args.copy_calibration_mb > 0:
         nb = args.copy_calibration_mb << 20
@@ -243,7 +256,7 @@ def main():
                     pairs_per_launch=pairs / launches)
     else:
         roof.update(bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s", frac=None)
-    roof["traffic"] = load_traffic(kname)
+    roof["traffic"] = load_traffic(kname, R.cell_log2(), R.lanes)
     roof["avg_launch_ms"] = ms / launches
 
     out = {
@@ -260,7 +273,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "particles": n, "dim": 3, "colours": cfg["n_colours"],
-                   "cell_log2": R.cell_log2(), "field": "sphere_distance 1:4", "init": "jittered 128^3 lattice"},
+                   "cell_log2": R.cell_log2(), "lanes": R.lanes, "autotuned": tuned,
+                   "field": "sphere_distance 1:4", "init": "jittered 128^3 lattice"},
         "steps_per_s": args.steps / elapsed,
         "pairs_per_step": pairs / args.steps,
         "candidates_per_s": cands / elapsed,

@@ -168,6 +168,27 @@ MPSPH_API int mpsph_domain_count(mpsph_ctx *ctx, int32_t *ndom, int64_t *n_total
  * Every position must lie inside the bounding box [lo, hi] (MPSPH_E_INVALID otherwise). */
 MPSPH_API int mpsph_load(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type);
 
+/* Sets the cell exponent (cells per axis 2^cell_log2 for every domain; -1: the library's size
+ * rule, or the value given at creation) and the lanes per particle of the pair kernels (2, 4
+ * or 8; 4 at creation).  The workspace is re-planned (a library-owned workspace grows when
+ * needed); the loaded state is dropped, so call mpsph_load next.  Errors: MPSPH_E_INVALID,
+ * MPSPH_E_STATE, MPSPH_E_UNSUPPORTED (grid too large), MPSPH_E_NOMEM (does not fit a caller
+ * workspace; the context is unchanged). */
+MPSPH_API int mpsph_configure(mpsph_ctx *ctx, int32_t cell_log2, int32_t lanes);
+
+/* Autotuner of the cell size and of the lanes per particle of the pair kernels.  For every
+ * candidate -- cell exponent of the size rule minus one, the rule's, plus one (for domains
+ * whose cell_log2 is -1; a fixed cell_log2 is kept), times 2, 4 or 8 lanes per particle -- the
+ * context is re-planned, the state d_pos / d_colour / d_type (as for mpsph_load) is loaded,
+ * probe_steps steps (1 .. 1000) are run untimed and probe_steps more are timed with HIP events
+ * on the context's stream.  The fastest candidate is kept and the state loaded into it (step counter
+ * 0).  A library-owned workspace grows when a candidate needs more; with a caller workspace,
+ * candidates that do not fit are skipped.  Any captured step graph is dropped.  Outputs (may be
+ * NULL): the chosen cell exponent of domain 0 and lanes.  Synchronises.
+ * Errors: MPSPH_E_INVALID (arguments or state, as mpsph_load), MPSPH_E_STATE, MPSPH_E_DEVICE. */
+MPSPH_API int mpsph_autotune(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type,
+                             int32_t probe_steps, int32_t *cell_log2_out, int32_t *lanes_out);
+
 /* Enqueue nsteps >= 0 relaxation steps on the context's stream; returns without waiting. */
 MPSPH_API int mpsph_step(mpsph_ctx *ctx, int32_t nsteps);
 

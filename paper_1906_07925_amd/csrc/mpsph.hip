@@ -985,6 +985,37 @@ struct Domain {
   size_t rbf0 = 0;  // first RBF term of this domain in the packed RBF arrays
   int uidx = 0;     // index of the domain in the caller's list
   int64_t uoff = 0, xoff = 0;  // first row / first float of the domain in the caller's arrays
+
+  Domain() = default;
+  Domain(const Domain &o) { *this = o; }
+  Domain(Domain &&o) noexcept = default;
+  Domain &operator=(Domain &&o) noexcept = default;
+  // p's RBF pointers refer to this domain's own copies of the arrays
+  Domain &operator=(const Domain &o) {
+    if (this == &o) return *this;
+    p = o.p;
+    rbf_centre = o.rbf_centre;
+    rbf_coeff = o.rbf_coeff;
+    d = o.d;
+    s0 = o.s0;
+    n = o.n;
+    off = o.off;
+    ncells = o.ncells;
+    cellbase = o.cellbase;
+    blk0 = o.blk0;
+    nblk = o.nblk;
+    row0 = o.row0;
+    nrow = o.nrow;
+    rbf0 = o.rbf0;
+    uidx = o.uidx;
+    uoff = o.uoff;
+    xoff = o.xoff;
+    if (!rbf_centre.empty()) {
+      p.rbf_centre = rbf_centre.data();
+      p.rbf_coeff = rbf_coeff.data();
+    }
+    return *this;
+  }
 };
 
 // Domains of one dimension occupy consecutive internal domain, particle and block ranges.
@@ -1032,6 +1063,7 @@ struct Layout {
   uint32_t ncells = 0;  // cells of all domains
   int key_bits = 0;
   int nblocks_pair = 0, nrows = 0;
+  int lanes = MPSPH_LANES;  // lanes per particle in the forward pair kernels
   int64_t chunk = 1;  // block partials per first-level reduction row
   size_t n_rbf = 0;
   size_t bytes = 0;
@@ -1040,10 +1072,12 @@ struct Layout {
 };
 
 // Orders the domains internally (2D before 3D, otherwise as given), assigns particle offsets,
-// cell bases, pair-kernel blocks and reduction rows, and lays out the workspace.
-int plan(std::vector<Domain> &doms, Layout *out) {
+// cell bases, pair-kernel blocks (lanes per particle) and reduction rows, and lays out the
+// workspace.  doms must be in the caller's order.
+int plan(std::vector<Domain> &doms, int lanes, Layout *out) {
   Layout L;
   L.ndom = (int)doms.size();
+  L.lanes = lanes;
   int64_t uoff = 0, xoff = 0;
   for (int d = 0; d < L.ndom; ++d) {
     doms[d].uidx = d;
@@ -1074,7 +1108,7 @@ int plan(std::vector<Domain> &doms, Layout *out) {
     dm.off = n;
     dm.cellbase = (uint32_t)cells;
     dm.blk0 = (int)blocks;
-    dm.nblk = (int)((dm.n * MPSPH_LANES + kBlock - 1) / kBlock);
+    dm.nblk = (int)((dm.n * lanes + kBlock - 1) / kBlock);
     dm.rbf0 = nrbf;
     n += dm.n;
     cells += dm.ncells;
@@ -1228,6 +1262,7 @@ struct mpsph_ctx {
   Layout L;
   hipStream_t stream = nullptr;
   char *ws = nullptr;
+  size_t ws_cap = 0;  // bytes of the workspace
   bool owns = false;
   bool loaded = false;
   bool poisoned = false;
@@ -1275,18 +1310,39 @@ void launch_group(mpsph_ctx *ctx, const Group &gr, const uint32_t *skeys, const 
   if (hk) hk->end();
 }
 
-template <int D>
-void launch_pass1(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk) {
+template <int D, int L_>
+void launch_pass1_l(mpsph_ctx *ctx, const Group &gr, hipStream_t st) {
   const Layout &L = ctx->L;
   const bool dbg = ctx->dom[0].p.debug != 0;
-  if (hk) hk->begin("pass_density_force");
-  pass_density_force<D, MPSPH_LANES><<<gr.nb, kBlock, 0, st>>>(
+  pass_density_force<D, L_><<<gr.nb, kBlock, 0, st>>>(
       ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.b0, ctx->at<int64_t>(L.stepctr), ctx->at<uint32_t>(L.w_key),
       ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
       dbg ? ctx->at<float>(L.rho) : nullptr, dbg ? ctx->at<float>(L.nn) : nullptr,
       dbg ? ctx->at<float>(L.aabs) : nullptr, ctx->at<uint32_t>(L.dtslots) + (size_t)gr.d0 * kDtSlots,
       ctx->at<double>(L.partials));
+}
+
+template <int D>
+void launch_pass1(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk) {
+  if (hk) hk->begin("pass_density_force");
+  switch (ctx->L.lanes) {
+    case 2: launch_pass1_l<D, 2>(ctx, gr, st); break;
+    case 8: launch_pass1_l<D, 8>(ctx, gr, st); break;
+    default: launch_pass1_l<D, 4>(ctx, gr, st);
+  }
   if (hk) hk->end();
+}
+
+template <int D, int L_>
+void launch_pass2_l(mpsph_ctx *ctx, const Group &gr, hipStream_t st, float4 *at_o, float4 *v_o) {
+  const Layout &L = ctx->L;
+  const bool dbg = ctx->dom[0].p.debug != 0;
+  pass_viscous_integrate<D, L_><<<gr.nb, kBlock, 0, st>>>(
+      ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.b0, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
+      ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
+      ctx->at<uint32_t>(L.dtslots) + (size_t)gr.d0 * kDtSlots, ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off),
+      ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), at_o, v_o, dbg ? ctx->at<float4>(L.dr) : nullptr,
+      ctx->at<double>(L.partials));
 }
 
 template <int D>
@@ -1297,12 +1353,11 @@ void launch_pass2(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk
   float4 *at_o = at_rec ? at_rec : (dbg ? ctx->at<float4>(L.at) : nullptr);
   float4 *v_o = v_rec ? v_rec : (dbg ? ctx->at<float4>(L.v) : nullptr);
   if (hk) hk->begin("pass_viscous_integrate");
-  pass_viscous_integrate<D, MPSPH_LANES><<<gr.nb, kBlock, 0, st>>>(
-      ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.b0, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
-      ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
-      ctx->at<uint32_t>(L.dtslots) + (size_t)gr.d0 * kDtSlots, ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off),
-      ctx->at<uint32_t>(L.s_ct), ctx->at<uint32_t>(L.s_id), at_o, v_o, dbg ? ctx->at<float4>(L.dr) : nullptr,
-      ctx->at<double>(L.partials));
+  switch (L.lanes) {
+    case 2: launch_pass2_l<D, 2>(ctx, gr, st, at_o, v_o); break;
+    case 8: launch_pass2_l<D, 8>(ctx, gr, st, at_o, v_o); break;
+    default: launch_pass2_l<D, 4>(ctx, gr, st, at_o, v_o);
+  }
   if (hk) hk->end();
 }
 
@@ -1399,9 +1454,91 @@ int build_domains(int32_t ndom, const mpsph_params *params, const int64_t *n, st
   doms->resize(ndom);
   for (int d = 0; d < ndom; ++d)
     if ((rc = make_domain(&params[d], n[d], &(*doms)[d])) != MPSPH_OK) return rc;
-  return plan(*doms, L);
+  return plan(*doms, MPSPH_LANES, L);
 }
 
+// Re-derives every domain's cell grid -- the cell exponent of the size rule plus kdelta for
+// domains whose cell_log2 was left to the library, the caller's value otherwise -- and plans
+// the workspace for `lanes` lanes per particle.
+int replan(std::vector<Domain> &doms, int kdelta, int lanes, Layout *L, int kabs = -1) {
+  std::stable_sort(doms.begin(), doms.end(), [](const Domain &a, const Domain &b) { return a.uidx < b.uidx; });
+  for (auto &dm : doms) {
+    mpsph_params q = dm.p;
+    if (kabs >= 1) {
+      q.cell_log2 = kabs;
+    } else if (q.cell_log2 < 0) {
+      Derived r;
+      int rc = derive(&q, dm.n, dm.s0, &r);
+      if (rc) return rc;
+      q.cell_log2 = std::min(std::max(r.k + kdelta, 1), q.dim == 3 ? 8 : 12);
+    }
+    int rc = derive(&q, dm.n, dm.s0, &dm.d);
+    if (rc) return rc;
+    dm.ncells = (uint32_t)1u << (q.dim * dm.d.k);
+  }
+  return plan(doms, lanes, L);
+}
+
+
+// Zeroes the workspace and uploads the domain table, the reduction row groups and the RBF
+// terms of the current layout.
+int setup_device(mpsph_ctx *ctx) {
+  const Layout &L = ctx->L;
+  const int ndom = L.ndom;
+  // a zeroed workspace keeps every table entry a valid index before its first write
+  HIP_OK(hipMemset(ctx->ws, 0, L.bytes));
+  std::vector<DomDev> dd(ndom);
+  std::vector<int2> groups;
+  std::vector<int> rc3(3 * std::max<size_t>(L.n_rbf, 1), 0);
+  std::vector<float> ro3(3 * std::max<size_t>(L.n_rbf, 1), 0.f), rk(std::max<size_t>(L.n_rbf, 1), 0.f);
+  for (int d = 0; d < ndom; ++d) {
+    const Domain &dm = ctx->dom[d];
+    dd[d] = domain_device(dm, ctx->at<int>(L.rbf_c), ctx->at<float>(L.rbf_o), ctx->at<float>(L.rbf_k));
+    for (int r = 0; r < dm.nrow; ++r) {
+      const int64_t a = dm.blk0 + (int64_t)r * L.chunk;
+      groups.push_back(make_int2((int)a, (int)std::min<int64_t>(a + L.chunk, dm.blk0 + dm.nblk)));
+    }
+    for (int t = 0; t < dm.p.n_rbf; ++t) {
+      const size_t kk = dm.rbf0 + t;
+      for (int a = 0; a < dm.p.dim; ++a)
+        split_cell((dm.p.rbf_centre[t * dm.p.dim + a] - dm.p.lo[a]) * dm.d.inv_cs, &rc3[kk * 3 + a], &ro3[kk * 3 + a]);
+      rk[kk] = (float)dm.p.rbf_coeff[t];
+    }
+  }
+  HIP_OK(hipMemcpy(ctx->at<DomDev>(L.doms), dd.data(), dd.size() * sizeof(DomDev), hipMemcpyHostToDevice));
+  if (!groups.empty())
+    HIP_OK(hipMemcpy(ctx->at<int2>(L.groups), groups.data(), groups.size() * sizeof(int2), hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(ctx->at<int>(L.rbf_c), rc3.data(), rc3.size() * 4, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(ctx->at<float>(L.rbf_o), ro3.data(), ro3.size() * 4, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(ctx->at<float>(L.rbf_k), rk.data(), rk.size() * 4, hipMemcpyHostToDevice));
+  return MPSPH_OK;
+}
+
+// Re-plans the context for a cell size (rule + kdelta, or kabs >= 1 for every domain) and a
+// lane count, growing a library-owned workspace when needed, and resets the device tables.
+// The loaded state is lost.  A configuration that does not fit a caller workspace returns
+// MPSPH_E_NOMEM and leaves the context unchanged.
+int reconfigure(mpsph_ctx *ctx, const std::vector<Domain> &base, int kdelta, int kabs, int lanes) {
+  std::vector<Domain> doms = base;
+  Layout Lc;
+  int rc = replan(doms, kdelta, lanes, &Lc, kabs);
+  if (rc) return rc;
+  if (Lc.bytes > ctx->ws_cap) {
+    if (!ctx->owns) return MPSPH_E_NOMEM;
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_cap = 0;
+    if (hipMalloc((void **)&ctx->ws, Lc.bytes) != hipSuccess) return fail(ctx, MPSPH_E_DEVICE);
+    ctx->ws_cap = Lc.bytes;
+  }
+  drop_graph(ctx);
+  ctx->dom = doms;
+  ctx->L = Lc;
+  ctx->loaded = false;
+  ctx->steps_done = 0;
+  return setup_device(ctx);
+}
 
 // ------------------------------------------------------------------------------------------
 // Gradient driver: forward with checkpoints, loss, and the reverse sweep.  A segment of
@@ -1485,6 +1622,7 @@ struct GradRun {
   hipStream_t st;
   const Group *gr;
   int nb1;
+  int nbp;  // blocks of the adjoint pair kernels (MPSPH_LANES lanes per particle)
   char *g;
   template <typename T>
   T *at(size_t off) {
@@ -1573,7 +1711,7 @@ int loss_backward(GradRun &R, double lam) {
                  nullptr) != hipSuccess)
     return fail(ctx, MPSPH_E_DEVICE);
   launch_group<D>(ctx, *R.gr, skeys, perm, kDtSlots, R.st, nullptr);
-  const int nbp = R.gr->nb;
+  const int nbp = R.nbp;
   loss_density<D, MPSPH_LANES><<<nbp, kBlock, 0, R.st>>>(dom, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
                                                        ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart),
                                                        R.at<float>(R.P.e), R.at<double>(R.P.pb));
@@ -1606,7 +1744,7 @@ int step_backward(GradRun &R, int m, int64_t t) {
   const Domain &dm = ctx->dom[0];
   const DomDev *dom = ctx->at<DomDev>(L.doms);
   const TapeView tv = R.view(m);
-  const int nbp = R.gr->nb;
+  const int nbp = R.nbp;
   uint32_t *minbits = reinterpret_cast<uint32_t *>(R.at<char>(R.P.scal) + 32);
   uint32_t *argmin = minbits + 1;
   double *t1bar = R.at<double>(R.P.scal);
@@ -1643,9 +1781,10 @@ int grad_run(mpsph_ctx *ctx, int nsteps, int ckpt, double lam, double *loss_out,
   R.st = ctx->stream;
   R.gr = &L.grp[D - 2];
   R.nb1 = (n + kBlock - 1) / kBlock;
+  R.nbp = (int)(((int64_t)n * MPSPH_LANES + kBlock - 1) / kBlock);
   const int nseg = nsteps > 0 ? (nsteps + ckpt - 1) / ckpt : 0;
   const int seg_len = std::min(ckpt, std::max(nsteps, 1));
-  R.P = grad_plan(n, L.ncells, nseg + 1, seg_len, R.nb1, R.gr->nb);
+  R.P = grad_plan(n, L.ncells, nseg + 1, seg_len, R.nb1, R.nbp);
   if (ctx->gbytes < R.P.bytes) {
     if (ctx->gmem) (void)hipFree(ctx->gmem);
     ctx->gmem = nullptr;
@@ -1760,38 +1899,10 @@ int mpsph_batch_create(int32_t ndom, const mpsph_params *params, const int64_t *
     }
     ctx->owns = true;
   }
-  // a zeroed workspace keeps every table entry a valid index before its first write
-  if (hipMemset(ctx->ws, 0, L.bytes) != hipSuccess) {
+  ctx->ws_cap = d_workspace ? workspace_bytes : L.bytes;
+  if ((rc = setup_device(ctx)) != MPSPH_OK) {
     mpsph_destroy(ctx);
-    return MPSPH_E_DEVICE;
-  }
-  // domain table, reduction row groups, RBF terms in cell units
-  std::vector<DomDev> dd(ndom);
-  std::vector<int2> groups;
-  std::vector<int> rc3(3 * std::max<size_t>(L.n_rbf, 1), 0);
-  std::vector<float> ro3(3 * std::max<size_t>(L.n_rbf, 1), 0.f), rk(std::max<size_t>(L.n_rbf, 1), 0.f);
-  for (int d = 0; d < ndom; ++d) {
-    const Domain &dm = ctx->dom[d];
-    dd[d] = domain_device(dm, ctx->at<int>(L.rbf_c), ctx->at<float>(L.rbf_o), ctx->at<float>(L.rbf_k));
-    for (int r = 0; r < dm.nrow; ++r) {
-      const int64_t a = dm.blk0 + (int64_t)r * L.chunk;
-      groups.push_back(make_int2((int)a, (int)std::min<int64_t>(a + L.chunk, dm.blk0 + dm.nblk)));
-    }
-    for (int t = 0; t < dm.p.n_rbf; ++t) {
-      const size_t kk = dm.rbf0 + t;
-      for (int a = 0; a < dm.p.dim; ++a)
-        split_cell((dm.p.rbf_centre[t * dm.p.dim + a] - dm.p.lo[a]) * dm.d.inv_cs, &rc3[kk * 3 + a], &ro3[kk * 3 + a]);
-      rk[kk] = (float)dm.p.rbf_coeff[t];
-    }
-  }
-  if (hipMemcpy(ctx->at<DomDev>(L.doms), dd.data(), dd.size() * sizeof(DomDev), hipMemcpyHostToDevice) != hipSuccess ||
-      (!groups.empty() && hipMemcpy(ctx->at<int2>(L.groups), groups.data(), groups.size() * sizeof(int2),
-                                    hipMemcpyHostToDevice) != hipSuccess) ||
-      hipMemcpy(ctx->at<int>(L.rbf_c), rc3.data(), rc3.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(ctx->at<float>(L.rbf_o), ro3.data(), ro3.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(ctx->at<float>(L.rbf_k), rk.data(), rk.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-    mpsph_destroy(ctx);
-    return MPSPH_E_DEVICE;
+    return rc;
   }
   *out = ctx;
   return MPSPH_OK;
@@ -1800,6 +1911,70 @@ int mpsph_batch_create(int32_t ndom, const mpsph_params *params, const int64_t *
 int mpsph_create(const mpsph_params *params, int64_t n, void *d_workspace, size_t workspace_bytes, void *hip_stream,
                  mpsph_ctx **out) {
   return mpsph_batch_create(1, params, &n, d_workspace, workspace_bytes, hip_stream, out);
+}
+
+int mpsph_configure(mpsph_ctx *ctx, int32_t cell_log2, int32_t lanes) {
+  if (!ctx || (lanes != 2 && lanes != 4 && lanes != 8) || cell_log2 == 0 || cell_log2 < -1 || cell_log2 > 12)
+    return MPSPH_E_INVALID;
+  if (ctx->poisoned) return MPSPH_E_STATE;
+  for (const Domain &dm : ctx->dom)
+    if (cell_log2 > 0 && dm.p.dim * cell_log2 > 24) return MPSPH_E_UNSUPPORTED;
+  const std::vector<Domain> base = ctx->dom;
+  return reconfigure(ctx, base, 0, cell_log2, lanes);
+}
+
+int mpsph_autotune(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type,
+                   int32_t probe_steps, int32_t *cell_log2_out, int32_t *lanes_out) {
+  if (!ctx || probe_steps < 1 || probe_steps > 1000) return MPSPH_E_INVALID;
+  if (ctx->poisoned) return MPSPH_E_STATE;
+  bool rule = false;
+  for (const Domain &dm : ctx->dom) rule |= dm.p.cell_log2 < 0;
+  const std::vector<Domain> base = ctx->dom;
+  struct Pick {
+    int kd, lanes;
+    float ms;
+  } best{0, MPSPH_LANES, INFINITY};
+  // applies a configuration: plan, workspace, device tables, and the caller's state loaded
+  auto apply = [&](int kd, int lanes) -> int {
+    int rc = reconfigure(ctx, base, kd, -1, lanes);
+    if (rc) return rc;
+    return mpsph_load(ctx, d_pos, d_colour, d_type);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(ctx, MPSPH_E_DEVICE);
+  int rc = MPSPH_OK;
+  const int lanes_c[3] = {2, 4, 8};
+  for (int kd = rule ? -1 : 0; kd <= (rule ? 1 : 0) && rc == MPSPH_OK; ++kd) {
+    for (int li = 0; li < 3; ++li) {
+      int a = apply(kd, lanes_c[li]);
+      if (a == MPSPH_E_NOMEM || a == MPSPH_E_UNSUPPORTED) continue;  // does not fit: not a candidate
+      if (a != MPSPH_OK) {
+        rc = a;
+        break;
+      }
+      // untimed steps first: the first steps after a load (state still in load order, dense
+      // initial neighbourhoods) are not representative of a run
+      if ((a = enqueue(ctx, probe_steps, ctx->stream, nullptr)) != MPSPH_OK) {
+        rc = a;
+        break;
+      }
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess || enqueue(ctx, probe_steps, ctx->stream, nullptr) ||
+          hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(ctx, MPSPH_E_DEVICE);
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best.ms) best = Pick{kd, lanes_c[li], ms};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == MPSPH_OK) rc = apply(best.kd, best.lanes);
+  if (rc != MPSPH_OK) return rc;
+  if (cell_log2_out) *cell_log2_out = ctx->dom[ctx->L.internal[0]].d.k;
+  if (lanes_out) *lanes_out = ctx->L.lanes;
+  return MPSPH_OK;
 }
 
 int mpsph_load(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type) {

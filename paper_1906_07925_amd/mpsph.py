@@ -81,6 +81,8 @@ def lib():
             "mpsph_debug_cells": (C.c_int, [V, V, V, C.POINTER(I64), C.POINTER(I32)]),
             "mpsph_debug_pairs": (C.c_int, [V, I64, V, V, C.POINTER(I64)]),
             "mpsph_set_field_coeff": (C.c_int, [V, I32, C.POINTER(C.c_double)]),
+            "mpsph_autotune": (C.c_int, [V, V, V, V, I32, C.POINTER(I32), C.POINTER(I32)]),
+            "mpsph_configure": (C.c_int, [V, I32, I32]),
             "mpsph_grad": (C.c_int, [V, I32, I32, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), V]),
             "mpsph_profile": (C.c_int, [V, I32]),
             "mpsph_profile_read": (C.c_int, [V, I32, C.POINTER(C.c_char_p), C.POINTER(I64),
@@ -177,6 +179,7 @@ class Relaxer:
         self.nfloat = sum(k * d for k, d in zip(ns, self.dims))   # floats of a position array
         made = [make_params(sp, s0=z, cell_log2=cell_log2, debug=debug) for sp, z in zip(specs, s0s)]
         self.params = (Params * self.ndom)(*[m[0] for m in made])
+        self.lanes = 4
         self._keep = [m[1] for m in made]
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -230,6 +233,27 @@ class Relaxer:
         self._hold = (x, c, t)
         _check(lib().mpsph_load(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(c.data_ptr()),
                                 C.c_void_p(t.data_ptr()) if t is not None else None), "mpsph_load")
+
+    def configure(self, cell_log2: int = -1, lanes: int = 4):
+        """Set the cell exponent (-1: size rule) and the lanes per particle; load again after."""
+        _check(lib().mpsph_configure(self._ctx, int(cell_log2), int(lanes)), "mpsph_configure")
+        self.lanes = int(lanes)
+
+    def autotune(self, x, colour, ptype=None, probe_steps: int = 5):
+        """Pick the cell size and lanes per particle by timing probe_steps steps (after as many
+        untimed ones) from this state; the state is loaded afterwards.  Returns (cell_log2, lanes)."""
+        torch = self._torch
+        x = self._dev(x, torch.float32)
+        c = self._dev(colour, torch.int32)
+        assert x.numel() == self.nfloat and c.shape == (self.n,)
+        t = None if ptype is None else self._dev(ptype, torch.int32)
+        self._hold = (x, c, t)
+        k, ln = C.c_int32(0), C.c_int32(0)
+        _check(lib().mpsph_autotune(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(c.data_ptr()),
+                                    C.c_void_p(t.data_ptr()) if t is not None else None, int(probe_steps),
+                                    C.byref(k), C.byref(ln)), "mpsph_autotune")
+        self.lanes = ln.value
+        return k.value, ln.value
 
     def step(self, nsteps: int = 1):
         _check(lib().mpsph_step(self._ctx, int(nsteps)), "mpsph_step")

@@ -3,6 +3,8 @@ launch of one kernel, calibrated against a plain device copy of known size recor
 same runs (the bench's --copy-calibration-mb option).
 
 usage: python -m paper_1906_07925_amd.traffic <fetch.csv> <write.csv> <kernel> <copy_MiB> <out.json> <command>
+       <bench output of the counter run>
+The bench output (its JSON line) gives the cell size and lanes per particle of the run.
 """
 from __future__ import annotations
 
@@ -32,7 +34,14 @@ def calibration(rows, copy_bytes: int) -> float:
 
 
 def main():
-    fetch_csv, write_csv, kernel, copy_mib, out, command = sys.argv[1:7]
+    fetch_csv, write_csv, kernel, copy_mib, out, command, bench_out = sys.argv[1:8]
+    cfg = None
+    for line in open(bench_out):
+        line = line.strip()
+        if line.startswith("{") and '"metric"' in line:
+            cfg = json.loads(line)["config"]
+    if cfg is None:
+        raise SystemExit("no benchmark line in " + bench_out)
     copy_bytes = int(copy_mib) << 20
     f = per_dispatch(fetch_csv, "FETCH_SIZE")
     w = per_dispatch(write_csv, "WRITE_SIZE")
@@ -44,6 +53,7 @@ def main():
     sys.path.insert(0, ROOT)
     import bench
     rec = {"kernel": kernel, "workload": bench.WORKLOAD, "kernel_source_digest": bench.kernel_source_digest(),
+           "cell_log2": cfg["cell_log2"], "lanes": cfg["lanes"],
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "bytes_per_launch": fetch + write, "fetch_scale": cf, "write_scale": cw,
            "launches": len(fk), "command": command}

@@ -125,7 +125,7 @@ def test_autograd_function(torch_cuda):
     R2 = M.Relaxer(dict(spec, rbf_coeff=coeff), n=x32.shape[0])
     R2.load(x0.detach(), colour, ptype)
     L, gc, gx = R2.grad(3, 2, LAM, n_rbf=len(coeff), want_pos=True)
-    assert float(loss) == L
+    assert float(loss.detach()) == L
     assert np.array_equal(c.grad.numpy(), 2.0 * gc)
     assert torch.equal(x0.grad, 2.0 * gx)
     R.close()

@@ -296,3 +296,53 @@ def test_neighbour_pair_sets_match_oracle(torch_cuda, name, scale):
         assert np.all(np.abs(r - rc) < 1e-5 * rc), (diff.size, np.max(np.abs(r - rc) / rc))
     assert m["pairs"] <= len(got)                         # the mask only removes pairs
     print(name, n, "pairs", len(got), "differing (band)", diff.size)
+
+
+@pytest.mark.parametrize("name,scale", [("cube_inclusion_2m", 0.01), ("annulus_262k", 0.02)])
+def test_autotune_keeps_the_step(torch_cuda, name, scale):
+    """The autotuner tries cell exponents rule - 1 .. rule + 1 and 2, 4, 8 lanes per particle
+    (every candidate runs steps), keeps the fastest, and the tuned context computes the same
+    step as the oracle."""
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    cfg = W.config(name, scale=scale)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    rule = M.Relaxer(spec, n=x32.shape[0], s0=s0).cell_log2()
+    R = M.Relaxer(spec, n=x32.shape[0], s0=s0, debug=True)
+    k, lanes = R.autotune(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda(),
+                          torch.from_numpy(typ).cuda(), probe_steps=2)
+    assert lanes in (2, 4, 8) and abs(k - rule) <= 1 and R.cell_log2() == k
+    R.step(1)
+    a = R.field("a").cpu().numpy().astype(np.float64)
+    x1 = R.store()[0].cpu().numpy().astype(np.float64)
+    m = R.metrics()
+    R.close()
+    _, xo, _, r = PU.oracle_step(spec, s0, x32, col, typ)
+    assert PU.rel(a, r["a"]) <= 1e-5
+    assert abs(m["pairs"] - r["pairs"]) <= r["band_pairs"]
+    assert PU.rel(x1 - x32, xo - x32) <= 1e-4
+    print(name, "rule k", rule, "chosen", k, lanes)
+
+
+@pytest.mark.parametrize("lanes", [2, 8])
+def test_configured_lanes_keep_the_step(torch_cuda, lanes):
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    cfg = W.config("cube_inclusion_2m", scale=0.008)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    R = M.Relaxer(spec, n=x32.shape[0], s0=s0, debug=True)
+    k = R.cell_log2()
+    R.configure(k + 1, lanes)
+    assert R.cell_log2() == k + 1
+    R.load(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    R.step(1)
+    a = R.field("a").cpu().numpy().astype(np.float64)
+    m = R.metrics()
+    R.close()
+    _, _, _, r = PU.oracle_step(spec, s0, x32, col, typ)
+    assert PU.rel(a, r["a"]) <= 1e-5
+    assert abs(m["pairs"] - r["pairs"]) <= r["band_pairs"]
