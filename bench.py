@@ -213,7 +213,8 @@ def main():
         R.load(dev_x, dev_c)
         tuned = False
     else:
-        k, lanes = R.autotune(dev_x, dev_c, probe_steps=10)
+        # tuned for the relaxed stage the timed steps mostly see: 50 untimed steps, 10 timed
+        k, lanes = R.autotune(dev_x, dev_c, probe_steps=10, warm_steps=50)
         tuned = True
     print(f"[bench] configuration: 2^{k} cells per axis, {lanes} lanes per particle"
           f"{' (autotuned)' if tuned else ''}", file=sys.stderr, flush=True)

@@ -103,11 +103,15 @@ typedef struct {
   double rbf_width;
   double tau, kappa;       /* h = tau s; cut-off r_c = kappa h (support of the kernel) */
   double p0, sigma0;       /* EOS constant (Eq. 18); initial surface-tension strength (Eq. 25) */
-  int64_t t0, t1;          /* ramp of sigma over steps (t0, t1]; t0 < 0: sigma constant */
+  int64_t t0, t1;          /* ramp of sigma over steps (t0, t1]; t0 = -1: sigma constant; t0 = -2:
+                              automatic (t0 detected, t1 = t0 + max(1, round(theta t0)), §3.3) */
   double nu_coeff;         /* nu = nu_coeff r_c |v~| (Eq. 21), 0.1 in the paper */
   double c_acc, c_vel, c_visc; /* constants of Eq. 29: 0.25, 1/40, 0.125 */
   int32_t cell_log2;       /* cells per axis = 2^cell_log2; -1: chosen from the field */
   int32_t debug;           /* 1: keep rho, sum|term|, a~, v, dr, nearest distance of the last step */
+  int32_t t0_window;       /* automatic t0: steps the topology must stay static (<= 0: 50) */
+  double t0_tol;           /* automatic t0: relative tolerance of "static" (<= 0: 1e-3) */
+  double theta;            /* automatic t0: ramp length as a fraction of t0 (<= 0: 0.2) */
 } mpsph_params;
 
 typedef struct {
@@ -127,6 +131,9 @@ typedef struct {
   double dt1, dt2;         /* the two time steps of Eq. 29 */
   double sigma;            /* sigma(t) used in the step */
   double elr_mean, elr_std, elr_min, elr_max; /* nearest distance x rho_t^(1/d), normal particles */
+  int64_t interface_particles; /* particles with at least one interface pair */
+  int64_t t0;              /* start of the sigma ramp in effect: params t0, or the detected step
+                              (-1 while automatic detection has not fired) */
 } mpsph_metrics_t;
 
 /* Field scale s0 for which the integral over the meshing region of rho_t = s^-dim equals n
@@ -180,14 +187,15 @@ MPSPH_API int mpsph_configure(mpsph_ctx *ctx, int32_t cell_log2, int32_t lanes);
  * candidate -- cell exponent of the size rule minus one, the rule's, plus one (for domains
  * whose cell_log2 is -1; a fixed cell_log2 is kept), times 2, 4 or 8 lanes per particle -- the
  * context is re-planned, the state d_pos / d_colour / d_type (as for mpsph_load) is loaded,
- * probe_steps steps (1 .. 1000) are run untimed and probe_steps more are timed with HIP events
- * on the context's stream.  The fastest candidate is kept and the state loaded into it (step counter
+ * max(warm_steps, 1) steps (warm_steps <= 10000) are run untimed -- the best lane count changes
+ * while a lattice relaxes, so warm_steps chooses the stage of the run to tune for -- and
+ * probe_steps steps (1 .. 1000) are timed with HIP events on the context's stream.  The fastest candidate is kept and the state loaded into it (step counter
  * 0).  A library-owned workspace grows when a candidate needs more; with a caller workspace,
  * candidates that do not fit are skipped.  Any captured step graph is dropped.  Outputs (may be
  * NULL): the chosen cell exponent of domain 0 and lanes.  Synchronises.
  * Errors: MPSPH_E_INVALID (arguments or state, as mpsph_load), MPSPH_E_STATE, MPSPH_E_DEVICE. */
 MPSPH_API int mpsph_autotune(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type,
-                             int32_t probe_steps, int32_t *cell_log2_out, int32_t *lanes_out);
+                             int32_t warm_steps, int32_t probe_steps, int32_t *cell_log2_out, int32_t *lanes_out);
 
 /* Enqueue nsteps >= 0 relaxation steps on the context's stream; returns without waiting. */
 MPSPH_API int mpsph_step(mpsph_ctx *ctx, int32_t nsteps);

@@ -632,10 +632,11 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
    * neighbour distance over the local target spacing rho_t^(-1/d) ("edge-length ratio"). */
   {
     double s2 = 0.0, linf = 0.0, em = 0.0, em2 = 0.0, emin = INFINITY, emax = 0.0;
-    int64_t nnorm = 0, nelr = 0, pairs = 0, ifc = 0, band = 0;
+    int64_t nnorm = 0, nelr = 0, pairs = 0, ifc = 0, band = 0, ifcp = 0;
     for (int64_t i = 0; i < n; ++i) {
       pairs += npair[i];
       ifc += nifc[i];
+      ifcp += nifc[i] > 0;
       band += nband[i];
       if (type0[i] == ORC_NORMAL) {
         double e = rho[i] / rho_t[i] - 1.0;
@@ -674,6 +675,7 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
     out->elr_max = emax;
     out->pairs = pairs;
     out->interface_pairs = ifc / 2;
+    out->interface_particles = ifcp;
     out->band_pairs = band;
     out->nonfinite = nonfinite;
     out->kinetic = ke;

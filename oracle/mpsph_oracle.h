@@ -55,6 +55,7 @@ typedef struct {
   double dt1, dt2, sigma, residual_l2, residual_linf, kinetic;
   double elr_mean, elr_std, elr_min, elr_max;
   int64_t pairs, interface_pairs, band_pairs, n_normal, n_elr, nonfinite;
+  int64_t interface_particles; /* particles with at least one pair of a different colour */
 } orc_out;
 
 double orc_kernel_w(double r, double h, int32_t dim);

@@ -59,7 +59,7 @@ class Out(C.Structure):
         (k, C.c_double) for k in ("dt1", "dt2", "sigma", "residual_l2", "residual_linf", "kinetic",
                                   "elr_mean", "elr_std", "elr_min", "elr_max")] + [
         (k, C.c_int64) for k in ("pairs", "interface_pairs", "band_pairs", "n_normal", "n_elr",
-                                 "nonfinite")]
+                                 "nonfinite", "interface_particles")]
 
 
 _lib = None

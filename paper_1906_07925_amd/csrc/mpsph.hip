@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
     const DomDev *__restrict__ doms, int ndom, int b0, const int64_t *__restrict__ stepctr, const uint32_t *__restrict__ wkey,
     const float4 *__restrict__ wpos, const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ cstart,
     float4 *__restrict__ acc, float *__restrict__ rho_out, float *__restrict__ nn_out, float *__restrict__ aabs_out,
-    uint32_t *__restrict__ dtslots, double *__restrict__ partials) {
+    uint32_t *__restrict__ dtslots, const double *__restrict__ metrics, double *__restrict__ partials) {
   const int lb = b0 + xcd_block(blockIdx.x, gridDim.x);
   const int d = domain_of_block(doms, ndom, lb);
   const GridDev g = doms[d].g;
@@ -151,8 +151,10 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
   const int li = local / L, sub = local % L;
   const int i = doms[d].off + li;
   const bool active = li < doms[d].n;
-  const float sigma = sigma_of(sp, (float)*stepctr);
+  const float sigma = sigma_of(sp, (float)*stepctr, metrics[(size_t)d * 32 + kAutoT0]);
   double part[12];
+  double ifcp[1] = {0.0};
+  const int ops1[1] = {0};
   const int ops[12] = {0, 2, 0, 0, 0, 1, 2, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < 12; ++s) part[s] = 0.0;
@@ -259,10 +261,12 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
       part[9] = (double)nifc;
       part[10] = (double)ncand;
       part[11] = fin ? 0.0 : 1.0;
+      ifcp[0] = nifc > 0 ? 1.0 : 0.0;
     }
   }
   block_min_to_slots(dtc, lb, dtslots + d * kDtSlots);
   block_reduce_write<12>(part, ops, partials + (size_t)lb * kNumPartials);
+  block_reduce_write<1>(ifcp, ops1, partials + (size_t)lb * kNumPartials + P_IFCP);
 }
 
 
@@ -294,8 +298,8 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
   const int local = (lb - doms[d].blk0) * kBlock + threadIdx.x;
   const int li = local / L, sub = local % L;
   const int i = doms[d].off + li;
-  double part[4] = {0.0, 0.0, 0.0, 0.0};
-  const int ops[4] = {0, 0, 0, 0};
+  double part[3] = {0.0, 0.0, 0.0};
+  const int ops[3] = {0, 0, 0};
   const float dt1 = read_dt1(dtslots + d * kDtSlots);
   const float hdt = 0.5f * dt1;
   const float dt2 = dt1 * sp.dt2_factor;
@@ -449,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
       part[2] = ti != 0 ? 1.0 : 0.0;
     }
   }
-  block_reduce_write<4>(part, ops, partials + (size_t)lb * kNumPartials + P_KE);
+  block_reduce_write<3>(part, ops, partials + (size_t)lb * kNumPartials + P_KE);
 }
 
 
@@ -557,6 +561,23 @@ __global__ __launch_bounds__(256) void finalize(const DomDev *__restrict__ doms,
     md[18] += red[P_PAIRS][0];
     md[19] += red[P_CAND][0];
     md[20] += 1.0;
+    // automatic t0 (reading of the paper's "topology static for some iterations"): the
+    // interface-pair count and the number of particles with an interface pair stay within
+    // t0_tol of a reference for t0_window steps; otherwise the reference restarts here
+    const StepDev &sp = doms[d].sp;
+    if (sp.auto_t0 && !(md[kAutoT0] > 0.0)) {
+      const double t = md[20] - 1.0;  // index of this step since the load
+      const double I = red[P_IFC][0] * 0.5, P = red[P_IFCP][0];
+      const double tol = (double)sp.t0_tol;
+      if (t == 0.0 || fabs(I - md[kAutoT0 + 1]) > tol * md[kAutoT0 + 1] ||
+          fabs(P - md[kAutoT0 + 2]) > tol * md[kAutoT0 + 2]) {
+        md[kAutoT0 + 1] = I;
+        md[kAutoT0 + 2] = P;
+        md[kAutoT0 + 3] = t;
+      } else if (t - md[kAutoT0 + 3] >= (double)sp.t0_window) {
+        md[kAutoT0] = t + 1.0;
+      }
+    }
     if (d == 0) *stepctr += 1;
   }
 }
@@ -659,6 +680,7 @@ bool valid_params(const mpsph_params *p) {
                                     !(p->rbf_width > 0)))
     return false;
   if (!(p->tau > 0) || !(p->kappa > 0) || !(p->p0 > 0) || !(p->sigma0 >= 0)) return false;
+  if (p->t0 < -2 || (p->t0 >= 0 && p->t1 < p->t0)) return false;
   if (!(p->nu_coeff >= 0) || !(p->c_acc > 0) || !(p->c_vel > 0) || !(p->c_visc > 0)) return false;
   if (p->geometry != MPSPH_BOX && !(p->r_out > 0)) return false;
   if (p->geometry == MPSPH_ANNULUS && !(p->r_in > 0 && p->r_in < p->r_out)) return false;
@@ -955,9 +977,17 @@ void split_cell(double X, int *c, float *o) {
 }
 
 // Surface-tension strength reported for a step (the kernels evaluate the same ramp in FP32).
-double sigma_at(const mpsph_params *p, int64_t step) {
-  if (p->t0 < 0) return p->sigma0;
-  double t = (double)step, t0 = (double)p->t0, t1 = (double)p->t1;
+double sigma_at(const mpsph_params *p, int64_t step, int64_t t0_auto = -1) {
+  int64_t t0i = p->t0, t1i = p->t1;
+  if (p->t0 == -2) {
+    if (t0_auto < 0) return p->sigma0;
+    const double th = p->theta > 0 ? p->theta : 0.2;
+    t0i = t0_auto;
+    // the same single-precision rounding as the kernels (round half to even)
+    t1i = t0_auto + std::max<int64_t>(1, (int64_t)std::rint((float)th * (float)t0_auto));
+  }
+  if (t0i < 0) return p->sigma0;
+  double t = (double)step, t0 = (double)t0i, t1 = (double)t1i;
   if (t <= t0) return p->sigma0;
   if (t <= t1) return p->sigma0 * (1.0 - (t - t0) / (t1 - t0));
   return 0.0;
@@ -1237,6 +1267,10 @@ DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, con
   sp.sigma0 = (float)p.sigma0;
   sp.t0 = p.t0 < 0 ? -1.f : (float)p.t0;
   sp.t1 = (float)p.t1;
+  sp.auto_t0 = p.t0 == -2 ? 1 : 0;
+  sp.t0_window = p.t0_window > 0 ? p.t0_window : 50;
+  sp.t0_tol = (float)(p.t0_tol > 0 ? p.t0_tol : 1e-3);
+  sp.theta = (float)(p.theta > 0 ? p.theta : 0.2);
   dd.cellbase = dm.cellbase;
   dd.off = (int)dm.off;
   dd.n = (int)dm.n;
@@ -1319,7 +1353,7 @@ void launch_pass1_l(mpsph_ctx *ctx, const Group &gr, hipStream_t st) {
       ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
       dbg ? ctx->at<float>(L.rho) : nullptr, dbg ? ctx->at<float>(L.nn) : nullptr,
       dbg ? ctx->at<float>(L.aabs) : nullptr, ctx->at<uint32_t>(L.dtslots) + (size_t)gr.d0 * kDtSlots,
-      ctx->at<double>(L.partials));
+      ctx->at<double>(L.metrics) + (size_t)gr.d0 * 32, ctx->at<double>(L.partials));
 }
 
 template <int D>
@@ -1429,7 +1463,10 @@ void fill_metrics(const mpsph_ctx *ctx, int dmi, const double *m, mpsph_metrics_
   out->kinetic = m[P_KE] * cs * cs;
   out->dt1 = m[16];
   out->dt2 = m[17];
-  out->sigma = sigma_at(&dm.p, std::max<int64_t>(ctx->steps_done - 1, 0));
+  const int64_t t0a = m[kAutoT0] > 0 ? (int64_t)m[kAutoT0] - 1 : -1;
+  out->sigma = sigma_at(&dm.p, std::max<int64_t>(ctx->steps_done - 1, 0), t0a);
+  out->interface_particles = (int64_t)m[P_IFCP];
+  out->t0 = dm.p.t0 == -2 ? t0a : dm.p.t0;
   if (m[P_NELR] > 0) {
     double mean = m[P_ELR] / m[P_NELR];
     out->elr_mean = mean;
@@ -1924,8 +1961,8 @@ int mpsph_configure(mpsph_ctx *ctx, int32_t cell_log2, int32_t lanes) {
 }
 
 int mpsph_autotune(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type,
-                   int32_t probe_steps, int32_t *cell_log2_out, int32_t *lanes_out) {
-  if (!ctx || probe_steps < 1 || probe_steps > 1000) return MPSPH_E_INVALID;
+                   int32_t warm_steps, int32_t probe_steps, int32_t *cell_log2_out, int32_t *lanes_out) {
+  if (!ctx || probe_steps < 1 || probe_steps > 1000 || warm_steps < 0 || warm_steps > 10000) return MPSPH_E_INVALID;
   if (ctx->poisoned) return MPSPH_E_STATE;
   bool rule = false;
   for (const Domain &dm : ctx->dom) rule |= dm.p.cell_log2 < 0;
@@ -1954,7 +1991,7 @@ int mpsph_autotune(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, 
       }
       // untimed steps first: the first steps after a load (state still in load order, dense
       // initial neighbourhoods) are not representative of a run
-      if ((a = enqueue(ctx, probe_steps, ctx->stream, nullptr)) != MPSPH_OK) {
+      if ((a = enqueue(ctx, std::max(warm_steps, 1), ctx->stream, nullptr)) != MPSPH_OK) {
         rc = a;
         break;
       }
@@ -2207,7 +2244,7 @@ int mpsph_grad(mpsph_ctx *ctx, int32_t nsteps, int32_t ckpt_every, double lambda
   if (!ctx || nsteps < 0 || ckpt_every < 1 || !std::isfinite(lambda)) return MPSPH_E_INVALID;
   if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
   const Domain &dm = ctx->dom[0];
-  if (ctx->L.ndom != 1 || dm.p.geometry != MPSPH_BOX ||
+  if (ctx->L.ndom != 1 || dm.p.geometry != MPSPH_BOX || dm.p.t0 == -2 ||
       (dm.p.field != MPSPH_RBF_EXP && dm.p.field != MPSPH_UNIFORM))
     return MPSPH_E_UNSUPPORTED;
   return dm.p.dim == 2 ? grad_run<2>(ctx, nsteps, ckpt_every, lambda, loss_out, grad_coeff_out, d_grad_pos)

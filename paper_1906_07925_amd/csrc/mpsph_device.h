@@ -29,7 +29,7 @@ enum : int {
   P_KE = 12,     // sum 1/2 |v|^2 (cell units)
   P_NONFIN2 = 13,
   P_NFEAT = 14,  // particles of type >= 1 after the step
-  P_SPARE = 15
+  P_IFCP = 15   // particles with at least one interface pair
 };
 
 // Geometry of the cell grid and of the meshing region, in cell units.  Positions are held as
@@ -73,7 +73,15 @@ struct StepDev {
   float dt2_factor;  // dt2 / dt1 implied by Eq. 29 after the velocity reset
   float sigma0;      // surface-tension strength before the ramp (Eq. 25)
   float t0, t1;      // ramp over steps (t0, t1]; t0 < 0: constant
+  int auto_t0;       // 1: t0 detected on the device (slot kAutoT0 of the domain's metrics)
+  int t0_window;     // steps the topology must stay static
+  float t0_tol;      // relative tolerance of "static"
+  float theta;       // t1 = t0 + max(1, round(theta t0))
 };
+
+// Slots of a domain's metrics block used by the automatic t0: detected t0 + 1 (0: not yet),
+// reference interface-pair count, reference interface-particle count, reference step.
+constexpr int kAutoT0 = 21;
 
 // One domain of a (possibly batched) context.  Domains occupy contiguous particle ranges
 // [off, off + n) in every internal particle array, contiguous ranges of the global cell index space
@@ -95,9 +103,16 @@ struct DomDev {
 };
 
 // Surface-tension strength at step t (Eq. 25): sigma0 up to t0, linear ramp to 0 on (t0, t1].
-__device__ __forceinline__ float sigma_of(const StepDev &sp, float t) {
-  if (sp.t0 < 0.f || t <= sp.t0) return sp.sigma0;
-  if (t <= sp.t1) return sp.sigma0 * (1.f - (t - sp.t0) / (sp.t1 - sp.t0));
+// t0_slot: the domain's detected t0 + 1 (automatic mode; 0 while undetected).
+__device__ __forceinline__ float sigma_of(const StepDev &sp, float t, double t0_slot = 0.0) {
+  float t0 = sp.t0, t1 = sp.t1;
+  if (sp.auto_t0) {
+    if (!(t0_slot > 0.0)) return sp.sigma0;
+    t0 = (float)(t0_slot - 1.0);
+    t1 = t0 + fmaxf(1.f, rintf(sp.theta * t0));
+  }
+  if (t0 < 0.f || t <= t0) return sp.sigma0;
+  if (t <= t1) return sp.sigma0 * (1.f - (t - t0) / (t1 - t0));
   return 0.f;
 }
 

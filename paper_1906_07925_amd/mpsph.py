@@ -42,6 +42,7 @@ class Params(C.Structure):
         ("t0", C.c_int64), ("t1", C.c_int64), ("nu_coeff", C.c_double),
         ("c_acc", C.c_double), ("c_vel", C.c_double), ("c_visc", C.c_double),
         ("cell_log2", C.c_int32), ("debug", C.c_int32),
+        ("t0_window", C.c_int32), ("t0_tol", C.c_double), ("theta", C.c_double),
     ]
 
 
@@ -49,7 +50,8 @@ class Metrics(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("step", "pairs", "interface_pairs", "candidates", "n_normal",
                                          "n_elr", "nonfinite", "n_feature", "pairs_total", "candidates_total")] + \
                [(k, C.c_double) for k in ("residual_l2", "residual_linf", "kinetic", "dt1", "dt2", "sigma",
-                                          "elr_mean", "elr_std", "elr_min", "elr_max")]
+                                          "elr_mean", "elr_std", "elr_min", "elr_max")] + \
+               [(k, C.c_int64) for k in ("interface_particles", "t0")]
 
 
 _lib = None
@@ -81,7 +83,7 @@ def lib():
             "mpsph_debug_cells": (C.c_int, [V, V, V, C.POINTER(I64), C.POINTER(I32)]),
             "mpsph_debug_pairs": (C.c_int, [V, I64, V, V, C.POINTER(I64)]),
             "mpsph_set_field_coeff": (C.c_int, [V, I32, C.POINTER(C.c_double)]),
-            "mpsph_autotune": (C.c_int, [V, V, V, V, I32, C.POINTER(I32), C.POINTER(I32)]),
+            "mpsph_autotune": (C.c_int, [V, V, V, V, I32, I32, C.POINTER(I32), C.POINTER(I32)]),
             "mpsph_configure": (C.c_int, [V, I32, I32]),
             "mpsph_grad": (C.c_int, [V, I32, I32, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), V]),
             "mpsph_profile": (C.c_int, [V, I32]),
@@ -147,6 +149,9 @@ def make_params(spec: dict, s0: float | None = None, cell_log2: int = -1, debug:
     p.s0 = float(s0) if s0 is not None else 0.0
     p.cell_log2 = int(cell_log2)
     p.debug = 1 if debug else 0
+    p.t0_window = int(spec.get("t0_window", 50))
+    p.t0_tol = float(spec.get("t0_tol", 1e-3))
+    p.theta = float(spec.get("theta", 0.2))
     return p, keep
 
 
@@ -239,9 +244,10 @@ class Relaxer:
         _check(lib().mpsph_configure(self._ctx, int(cell_log2), int(lanes)), "mpsph_configure")
         self.lanes = int(lanes)
 
-    def autotune(self, x, colour, ptype=None, probe_steps: int = 5):
-        """Pick the cell size and lanes per particle by timing probe_steps steps (after as many
-        untimed ones) from this state; the state is loaded afterwards.  Returns (cell_log2, lanes)."""
+    def autotune(self, x, colour, ptype=None, probe_steps: int = 5, warm_steps: int | None = None):
+        """Pick the cell size and lanes per particle by timing probe_steps steps after warm_steps
+        untimed ones (default: probe_steps) from this state; the state is loaded afterwards.
+        Returns (cell_log2, lanes)."""
         torch = self._torch
         x = self._dev(x, torch.float32)
         c = self._dev(colour, torch.int32)
@@ -249,9 +255,10 @@ class Relaxer:
         t = None if ptype is None else self._dev(ptype, torch.int32)
         self._hold = (x, c, t)
         k, ln = C.c_int32(0), C.c_int32(0)
+        warm = probe_steps if warm_steps is None else warm_steps
         _check(lib().mpsph_autotune(self._ctx, C.c_void_p(x.data_ptr()), C.c_void_p(c.data_ptr()),
-                                    C.c_void_p(t.data_ptr()) if t is not None else None, int(probe_steps),
-                                    C.byref(k), C.byref(ln)), "mpsph_autotune")
+                                    C.c_void_p(t.data_ptr()) if t is not None else None, int(warm),
+                                    int(probe_steps), C.byref(k), C.byref(ln)), "mpsph_autotune")
         self.lanes = ln.value
         return k.value, ln.value
 
