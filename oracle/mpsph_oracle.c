@@ -83,8 +83,50 @@ static double dist_to(const double *x, const double *c, int dim) {
   return sqrt(s);
 }
 
+/* Multilinear interpolation on the Cartesian background mesh (§3.1: the level set and the
+ * target information live on that mesh and are interpolated at the particle positions).  The
+ * cell is the one containing x (the edge cell outside the mesh); the gradient is the exact
+ * derivative of the interpolant in that cell. */
+double orc_grid_interp(const orc_params *p, const double *nodes, const double *x, double *grad) {
+  int d = p->dim;
+  int base[3] = {0, 0, 0};
+  double f[3] = {0, 0, 0}, hh[3] = {1, 1, 1};
+  for (int a = 0; a < d; ++a) {
+    int na = p->grid_n[a];
+    hh[a] = (p->hi[a] - p->lo[a]) / (double)(na - 1);
+    double u = (x[a] - p->lo[a]) / hh[a];
+    int i = (int)floor(u);
+    if (i < 0) i = 0;
+    if (i > na - 2) i = na - 2;
+    base[a] = i;
+    f[a] = u - i;
+  }
+  double val = 0.0, g[3] = {0, 0, 0};
+  int corners = 1 << d;
+  for (int c = 0; c < corners; ++c) {
+    int64_t idx = 0, stride = 1;
+    double w = 1.0, dw[3] = {1, 1, 1};
+    for (int a = 0; a < d; ++a) {
+      int bit = (c >> a) & 1;
+      idx += (int64_t)(base[a] + bit) * stride;
+      stride *= p->grid_n[a];
+      double wa = bit ? f[a] : 1.0 - f[a];
+      double da = bit ? 1.0 / hh[a] : -1.0 / hh[a];
+      for (int b = 0; b < d; ++b) dw[b] *= (b == a) ? da : wa;
+      w *= wa;
+    }
+    val += w * nodes[idx];
+    for (int b = 0; b < d; ++b) g[b] += dw[b] * nodes[idx];
+  }
+  if (grad)
+    for (int a = 0; a < 3; ++a) grad[a] = a < d ? g[a] : 0.0;
+  return val;
+}
+
 double orc_spacing(const orc_params *p, const double *x) {
   switch (p->field) {
+    case ORC_GRID: /* target information interpolated from the background mesh (§3.2) */
+      return p->s0 * orc_grid_interp(p, p->grid_s, x, NULL);
     case ORC_UNIFORM:
       return p->s0;
     case ORC_RADIAL_LINEAR: /* s = s0 (1 + fa (|x - c| - fb)) */
@@ -134,6 +176,8 @@ double orc_level_set(const orc_params *p, const double *x) {
     }
     case ORC_BALL:
       return p->r_out - dist_to(x, p->centre, d);
+    case ORC_LEVELSET:
+      return orc_grid_interp(p, p->grid_phi, x, NULL);
   }
   return NAN;
 }
@@ -145,7 +189,7 @@ double orc_level_set(const orc_params *p, const double *x) {
 double orc_field_integral(const orc_params *p, int32_t nq) {
   int d = p->dim;
   double total = 0.0;
-  if (p->geometry == ORC_PERIODIC || p->geometry == ORC_BOX) {
+  if (p->geometry == ORC_PERIODIC || p->geometry == ORC_BOX || p->geometry == ORC_LEVELSET) {
     double dx[3], vol = 1.0;
     for (int a = 0; a < d; ++a) {
       dx[a] = (p->hi[a] - p->lo[a]) / nq;
@@ -161,6 +205,8 @@ double orc_field_integral(const orc_params *p, int32_t nq) {
         x[a] = p->lo[a] + ((double)(r % nq) + 0.5) * dx[a];
         r /= nq;
       }
+      /* indicator of Eq. 5: only the positive phase of the level set counts */
+      if (p->geometry == ORC_LEVELSET && !(orc_level_set(p, x) > 0.0)) continue;
       total += pow(orc_spacing(p, x), -d);
     }
     return total * vol;
@@ -366,6 +412,15 @@ static void project_vector(const orc_params *p, const double *xi, int32_t type, 
   if (p->geometry == ORC_BOX) {
     for (int a = 0; a < d; ++a)
       if (xi[a] == p->lo[a] || xi[a] == p->hi[a]) f[a] = 0.0;
+  } else if (p->geometry == ORC_LEVELSET) {
+    /* Eq. 31 with the unit normal N = grad phi / |grad phi| */
+    double g[3], gn = 0.0, dot = 0.0;
+    orc_grid_interp(p, p->grid_phi, xi, g);
+    for (int a = 0; a < d; ++a) gn += g[a] * g[a];
+    gn = sqrt(gn);
+    if (!(gn > 0.0)) return;
+    for (int a = 0; a < d; ++a) dot += g[a] / gn * f[a];
+    for (int a = 0; a < d; ++a) f[a] -= dot * g[a] / gn;
   } else if (p->geometry == ORC_ANNULUS || p->geometry == ORC_BALL) {
     double nrm[3], r = dist_to(xi, p->centre, d), dot = 0.0;
     for (int a = 0; a < d; ++a) {
@@ -408,6 +463,19 @@ static void project_position(const orc_params *p, double *xi, int32_t *type) {
     int32_t t = type_from_faces(nf, d);
     if (*type == ORC_NORMAL && orc_level_set(p, xi) > 0.0) return;
     if (t > *type) *type = t;
+    return;
+  }
+  if (p->geometry == ORC_LEVELSET) {
+    /* Eq. 32: r <- r - phi N, for surface particles and for normal particles that left the
+     * positive phase (which become surface particles) */
+    double g[3], gn = 0.0;
+    double phi = orc_grid_interp(p, p->grid_phi, xi, g);
+    if (*type == ORC_NORMAL && !(phi < 0.0)) return;
+    for (int a = 0; a < d; ++a) gn += g[a] * g[a];
+    gn = sqrt(gn);
+    if (gn > 0.0)
+      for (int a = 0; a < d; ++a) xi[a] -= phi * g[a] / gn;
+    if (*type < ORC_SURFACE) *type = ORC_SURFACE;
     return;
   }
   double r = dist_to(xi, p->centre, d);

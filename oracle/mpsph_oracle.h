@@ -19,8 +19,8 @@
 extern "C" {
 #endif
 
-enum { ORC_PERIODIC = 0, ORC_BOX = 1, ORC_ANNULUS = 2, ORC_BALL = 3 };
-enum { ORC_UNIFORM = 0, ORC_RADIAL_LINEAR = 1, ORC_SPHERE_DISTANCE = 2, ORC_RBF_EXP = 3 };
+enum { ORC_PERIODIC = 0, ORC_BOX = 1, ORC_ANNULUS = 2, ORC_BALL = 3, ORC_LEVELSET = 4 };
+enum { ORC_UNIFORM = 0, ORC_RADIAL_LINEAR = 1, ORC_SPHERE_DISTANCE = 2, ORC_RBF_EXP = 3, ORC_GRID = 4 };
 enum { ORC_NORMAL = 0, ORC_SURFACE = 1, ORC_CURVE = 2, ORC_FIXED = 3 };
 enum { ORC_OK = 0, ORC_E_INVALID = 1, ORC_E_NOMEM = 2 };
 
@@ -43,6 +43,12 @@ typedef struct {
   double nu_coeff, c_acc, c_vel, c_visc;
   int32_t search;       /* 0: cell grid, 1: brute force over all pairs */
   int32_t pad_;
+  /* Cartesian background mesh (§3.1-3.2): grid_n[a] nodes per axis spanning [lo, hi], node
+   * (i, j, k) at index i + n0 (j + n1 k); values interpolated multilinearly. */
+  int32_t grid_n[3];
+  int32_t pad2_;
+  const double *grid_phi; /* level set of ORC_LEVELSET (positive inside), domain units */
+  const double *grid_s;   /* relative spacing of ORC_GRID: s = s0 * interpolated value */
 } orc_params;
 
 typedef struct {
@@ -59,6 +65,9 @@ typedef struct {
 } orc_out;
 
 double orc_kernel_w(double r, double h, int32_t dim);
+/* Multilinear interpolation of node values on the background mesh, with its gradient (may be
+ * NULL). */
+double orc_grid_interp(const orc_params *p, const double *nodes, const double *x, double *grad);
 double orc_kernel_dw(double r, double h, int32_t dim);
 double orc_sigma(const orc_params *p, int64_t step);
 double orc_spacing(const orc_params *p, const double *x);

@@ -18,8 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
-GEOMETRY = {"periodic": 0, "box": 1, "annulus": 2, "ball": 3}
-FIELD = {"uniform": 0, "radial_linear": 1, "sphere_distance": 2, "rbf_exp": 3}
+GEOMETRY = {"periodic": 0, "box": 1, "annulus": 2, "ball": 3, "levelset": 4}
+FIELD = {"uniform": 0, "radial_linear": 1, "sphere_distance": 2, "rbf_exp": 3, "grid": 4}
 NORMAL, SURFACE, CURVE, FIXED = 0, 1, 2, 3
 
 
@@ -47,6 +47,8 @@ class Params(C.Structure):
         ("t0", C.c_int64), ("t1", C.c_int64),
         ("nu_coeff", C.c_double), ("c_acc", C.c_double), ("c_vel", C.c_double),
         ("c_visc", C.c_double), ("search", C.c_int32), ("pad_", C.c_int32),
+        ("grid_n", C.c_int32 * 3), ("pad2_", C.c_int32),
+        ("grid_phi", C.POINTER(C.c_double)), ("grid_s", C.POINTER(C.c_double)),
     ]
 
 
@@ -135,6 +137,14 @@ class OracleParams:
         p.c_vel = spec.get("c_vel", 1.0 / 40.0)
         p.c_visc = spec.get("c_visc", 0.125)
         p.search = 1 if search == "brute" else 0
+        # background mesh: node values, x index fastest
+        gn = spec.get("grid_n", (2, 2, 2))
+        for a in range(3):
+            p.grid_n[a] = int(gn[a]) if a < d else 1
+        self._gphi = np.ascontiguousarray(np.asarray(spec.get("grid_phi", np.zeros(1)), dtype=np.float64).reshape(-1))
+        self._gs = np.ascontiguousarray(np.asarray(spec.get("grid_s", np.zeros(1)), dtype=np.float64).reshape(-1))
+        p.grid_phi = _dp(self._gphi)
+        p.grid_s = _dp(self._gs)
         p.s0 = 1.0
         self.p = p
         self.dim = d
@@ -147,6 +157,21 @@ class OracleParams:
     @property
     def s0(self) -> float:
         return self.p.s0
+
+
+def grid_interp(op: OracleParams, which: str, x: np.ndarray):
+    """Interpolated background-mesh value ('phi' or 's') and gradient at each row of x."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    nodes = op.p.grid_phi if which == "phi" else op.p.grid_s
+    v = np.empty(x.shape[0])
+    g = np.zeros((x.shape[0], 3))
+    lib().orc_grid_interp.restype = C.c_double
+    lib().orc_grid_interp.argtypes = [C.POINTER(Params), _DP, _DP, _DP]
+    for i in range(x.shape[0]):
+        gi = np.zeros(3)
+        v[i] = lib().orc_grid_interp(C.byref(op.p), nodes, _dp(np.ascontiguousarray(x[i])), _dp(gi))
+        g[i] = gi
+    return v, g[:, :x.shape[1]]
 
 
 def field_integral(op: OracleParams, nq: int = 2048) -> float:

@@ -92,8 +92,29 @@ def rbf_cube(n: int, n_rbf: int = 32, width: float = 0.15, seed: int = BASE_SEED
 # Initial particle sets
 # ---------------------------------------------------------------------------------------
 
+def levelset_ball(n: int, dim: int = 3, radius: float = 0.4, nodes: int = 48, ratio: float = 3.0, **kw) -> dict:
+    """A ball given only through a background mesh: the level set R - |x - c| and the relative
+    spacing 1 + (ratio - 1) |x - c| / R (graded from the centre out) sampled at nodes^dim
+    nodes over the unit box; both are interpolated from the mesh.  The analytic ball is kept
+    as ``shape`` to draw initial positions."""
+    c = np.full(dim, 0.5)
+    ax = np.linspace(0.0, 1.0, nodes)
+    grids = np.meshgrid(*([ax] * dim), indexing="ij")
+    # node (i, j, k) at index i + n (j + n k): x index fastest
+    pts = np.stack([g.transpose(*reversed(range(dim))).reshape(-1) for g in grids], axis=1)
+    r = np.linalg.norm(pts - c, axis=1)
+    s = dict(dim=dim, geometry="levelset", lo=(0.0,) * dim, hi=(1.0,) * dim, field="grid",
+             grid_n=(nodes,) * dim + (1,) * (3 - dim), grid_phi=radius - r,
+             grid_s=1.0 + (ratio - 1.0) * np.minimum(r / radius, 1.5), shape=("ball", tuple(c), radius), n=n)
+    s.update(kw)
+    return s
+
+
 def _inside(spec: dict, x: np.ndarray) -> np.ndarray:
     g = spec["geometry"]
+    if g == "levelset":
+        _, c, rad = spec["shape"]
+        return np.linalg.norm(x - np.asarray(c), axis=1) < rad
     if g in ("box", "periodic"):
         lo = np.asarray(spec["lo"]); hi = np.asarray(spec["hi"])
         return np.all((x >= lo) & (x <= hi), axis=1)
