@@ -59,15 +59,18 @@ enum {
   MPSPH_E_UNSUPPORTED = 6  /* valid but unsupported configuration */
 };
 
-/* Meshing region: the positive phase of the level set (§3.1, Eq. 14). */
-enum { MPSPH_BOX = 1, MPSPH_ANNULUS = 2, MPSPH_BALL = 3 };
+/* Meshing region: the positive phase of the level set (§3.1, Eq. 14).  MPSPH_LEVELSET: the
+ * level set is given at the nodes of a Cartesian background mesh over [lo, hi] (§3.1-3.2) and
+ * interpolated multilinearly; particles leaving it are projected by r <- r - phi N (Eq. 32). */
+enum { MPSPH_BOX = 1, MPSPH_ANNULUS = 2, MPSPH_BALL = 3, MPSPH_LEVELSET = 4 };
 
 /* Target size field s(x); rho_t = s^-dim (unit particle mass, Eq. 15), h = tau s (Eq. 16). */
 enum {
   MPSPH_UNIFORM = 0,         /* s = s0 */
   MPSPH_RADIAL_LINEAR = 1,   /* s = s0 (1 + fa (|x - fcentre| - fb)) */
   MPSPH_SPHERE_DISTANCE = 2, /* s = s0 (1 + fa | |x - fcentre| - fb |) */
-  MPSPH_RBF_EXP = 3          /* s = s0 exp(sum_k c_k exp(-|x - mu_k|^2 / (2 w^2))) */
+  MPSPH_RBF_EXP = 3,         /* s = s0 exp(sum_k c_k exp(-|x - mu_k|^2 / (2 w^2))) */
+  MPSPH_GRID = 4             /* s = s0 g(x), g interpolated from the background mesh (§3.2) */
 };
 
 /* Per-particle quantities that mpsph_debug_fields() can export (values of the last step). */
@@ -112,6 +115,10 @@ typedef struct {
   int32_t t0_window;       /* automatic t0: steps the topology must stay static (<= 0: 50) */
   double t0_tol;           /* automatic t0: relative tolerance of "static" (<= 0: 1e-3) */
   double theta;            /* automatic t0: ramp length as a fraction of t0 (<= 0: 0.2) */
+  int32_t grid_n[3];       /* background mesh: nodes per axis (>= 2) spanning [lo, hi] */
+  const double *grid_phi;  /* host, prod(grid_n[0..dim)) level-set values (MPSPH_LEVELSET), domain
+                              units, positive inside; node (i, j, k) at i + n0 (j + n1 k); copied */
+  const double *grid_s;    /* host, node values g of the MPSPH_GRID field (> 0); copied */
 } mpsph_params;
 
 typedef struct {

@@ -398,6 +398,29 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
             if ((c[a] == 0 && o[a] == 0.f) || (c[a] == g.whi_c[a] && o[a] == g.whi_o[a])) ++nf;
           }
           ti = max(ti, type_from_faces(nf, D));
+        } else if (g.geometry == 4) {
+          // level set on the background mesh: r <- r - phi N (Eq. 32) for feature particles
+          // and for normal particles that left the positive phase (re-tagged as surface)
+          float gr[3];
+          const float phi = mesh_interp<D>(g.phi, g.gn, g.ginv, c, o, gr);
+          if (ti != 0 || phi < 0.f) {
+            const float gn2 = gr[0] * gr[0] + gr[1] * gr[1] + (D == 3 ? gr[2] * gr[2] : 0.f);
+            if (gn2 > 0.f) {
+              const float sc = phi * fast_rsq(gn2);
+#pragma unroll
+              for (int a = 0; a < D; ++a) {
+                const float x = o[a] - sc * gr[a];
+                const float fl = floorf(x);
+                c[a] += (int)fl;
+                o[a] = x - fl;
+                if (o[a] >= 1.f) {
+                  o[a] = 0.f;
+                  c[a] += 1;
+                }
+              }
+            }
+            ti = max(ti, 1);
+          }
         } else {
           // annulus / ball: radial projection onto the nearest boundary circle / sphere
           float rel[3], r2 = 0.f;
@@ -671,18 +694,32 @@ const char *kErr[] = {"ok", "invalid argument", "out of memory", "device error",
 bool valid_params(const mpsph_params *p) {
   if (!p) return false;
   if (p->dim != 2 && p->dim != 3) return false;
-  if (p->geometry < MPSPH_BOX || p->geometry > MPSPH_BALL) return false;
+  if (p->geometry < MPSPH_BOX || p->geometry > MPSPH_LEVELSET) return false;
+  if (p->geometry == MPSPH_LEVELSET || p->field == MPSPH_GRID) {
+    int64_t nodes = 1;
+    for (int a = 0; a < p->dim; ++a) {
+      if (p->grid_n[a] < 2 || p->grid_n[a] > (1 << 14)) return false;
+      nodes *= p->grid_n[a];
+    }
+    if (nodes > ((int64_t)1 << 27)) return false;
+    if (p->geometry == MPSPH_LEVELSET && !p->grid_phi) return false;
+    if (p->field == MPSPH_GRID) {
+      if (!p->grid_s) return false;
+      for (int64_t k = 0; k < nodes; ++k)
+        if (!(p->grid_s[k] > 0) || !std::isfinite(p->grid_s[k])) return false;
+    }
+  }
   if (p->geometry == MPSPH_ANNULUS && p->dim != 2) return false;
   for (int a = 0; a < p->dim; ++a)
     if (!(p->hi[a] > p->lo[a]) || !std::isfinite(p->lo[a]) || !std::isfinite(p->hi[a])) return false;
-  if (p->field < MPSPH_UNIFORM || p->field > MPSPH_RBF_EXP) return false;
+  if (p->field < MPSPH_UNIFORM || p->field > MPSPH_GRID) return false;
   if (p->field == MPSPH_RBF_EXP && (p->n_rbf < 0 || p->n_rbf > 64 || (p->n_rbf > 0 && (!p->rbf_centre || !p->rbf_coeff)) ||
                                     !(p->rbf_width > 0)))
     return false;
   if (!(p->tau > 0) || !(p->kappa > 0) || !(p->p0 > 0) || !(p->sigma0 >= 0)) return false;
   if (p->t0 < -2 || (p->t0 >= 0 && p->t1 < p->t0)) return false;
   if (!(p->nu_coeff >= 0) || !(p->c_acc > 0) || !(p->c_vel > 0) || !(p->c_visc > 0)) return false;
-  if (p->geometry != MPSPH_BOX && !(p->r_out > 0)) return false;
+  if ((p->geometry == MPSPH_ANNULUS || p->geometry == MPSPH_BALL) && !(p->r_out > 0)) return false;
   if (p->geometry == MPSPH_ANNULUS && !(p->r_in > 0 && p->r_in < p->r_out)) return false;
   if (p->cell_log2 != -1 && (p->cell_log2 < 1 || p->cell_log2 > 12)) return false;
   return true;
@@ -701,8 +738,41 @@ double box_dist_range(const mpsph_params *p, const double *c, double *dmax) {
   return std::sqrt(dmin2);
 }
 
+// Multilinear interpolation on the background mesh (host, FP64), optional gradient.
+double host_mesh(const mpsph_params *p, const double *nodes, const double *x, double *grad = nullptr) {
+  const int d = p->dim;
+  int base[3] = {0, 0, 0};
+  double f[3] = {0, 0, 0}, inv[3] = {1, 1, 1};
+  for (int a = 0; a < d; ++a) {
+    inv[a] = (double)(p->grid_n[a] - 1) / (p->hi[a] - p->lo[a]);
+    const double u = (x[a] - p->lo[a]) * inv[a];
+    const int i = std::min(std::max((int)std::floor(u), 0), p->grid_n[a] - 2);
+    base[a] = i;
+    f[a] = u - i;
+  }
+  double val = 0.0, g[3] = {0, 0, 0};
+  for (int cn = 0; cn < (1 << d); ++cn) {
+    size_t idx = 0, stride = 1;
+    double w = 1.0, dw[3] = {1, 1, 1};
+    for (int a = 0; a < d; ++a) {
+      const int bit = (cn >> a) & 1;
+      idx += (size_t)(base[a] + bit) * stride;
+      stride *= (size_t)p->grid_n[a];
+      const double wa = bit ? f[a] : 1.0 - f[a];
+      for (int b = 0; b < d; ++b) dw[b] *= b == a ? (bit ? inv[a] : -inv[a]) : wa;
+      w *= wa;
+    }
+    val += w * nodes[idx];
+    for (int b = 0; b < d; ++b) g[b] += dw[b] * nodes[idx];
+  }
+  if (grad)
+    for (int a = 0; a < 3; ++a) grad[a] = a < d ? g[a] : 0.0;
+  return val;
+}
+
 // Spacing of the field in domain units at a point (host, FP64), with scale s0.
 double host_spacing(const mpsph_params *p, double s0, const double *x) {
+  if (p->field == MPSPH_GRID) return s0 * host_mesh(p, p->grid_s, x);
   auto dist = [&](const double *c) {
     double s = 0;
     for (int a = 0; a < p->dim; ++a) s += (x[a] - c[a]) * (x[a] - c[a]);
@@ -728,6 +798,7 @@ double host_spacing(const mpsph_params *p, double s0, const double *x) {
 
 bool inside_region(const mpsph_params *p, const double *x) {
   if (p->geometry == MPSPH_BOX) return true;
+  if (p->geometry == MPSPH_LEVELSET) return host_mesh(p, p->grid_phi, x) > 0.0;
   double r = 0;
   for (int a = 0; a < p->dim; ++a) r += (x[a] - p->centre[a]) * (x[a] - p->centre[a]);
   r = std::sqrt(r);
@@ -755,6 +826,27 @@ double field_integral_unit(const mpsph_params *p) {
   const int d = p->dim;
   const double pi = 3.14159265358979323846;
   double total = 0.0;
+  if (p->geometry == MPSPH_LEVELSET) {
+    // midpoint rule over sub-cells of the bounding box with the indicator of the positive phase
+    const int M = d == 2 ? 1024 : 160;
+    double h[3] = {0, 0, 0}, vol = 1.0;
+    for (int a = 0; a < d; ++a) {
+      h[a] = (p->hi[a] - p->lo[a]) / M;
+      vol *= h[a];
+    }
+    const int64_t cells = d == 2 ? (int64_t)M * M : (int64_t)M * M * M;
+    for (int64_t cidx = 0; cidx < cells; ++cidx) {
+      double x[3];
+      int64_t r = cidx;
+      for (int a = 0; a < d; ++a) {
+        x[a] = p->lo[a] + ((double)(r % M) + 0.5) * h[a];
+        r /= M;
+      }
+      if (!(host_mesh(p, p->grid_phi, x) > 0.0)) continue;
+      total += std::pow(host_spacing(p, 1.0, x), -d);
+    }
+    return total * vol;
+  }
   if (p->field == MPSPH_UNIFORM) {  // s = 1: the measure of the region
     if (p->geometry == MPSPH_BOX) {
       double v = 1.0;
@@ -765,7 +857,7 @@ double field_integral_unit(const mpsph_params *p) {
     return d == 2 ? pi * p->r_out * p->r_out : 4.0 / 3.0 * pi * p->r_out * p->r_out * p->r_out;
   }
   if (p->geometry == MPSPH_BOX) {
-    const int M = d == 2 ? 256 : 48;
+    const int M = d == 2 ? 256 : (p->field == MPSPH_GRID ? 24 : 48);
     const int np = M * 8;
     std::vector<double> node[3], wt[3];
     for (int a = 0; a < d; ++a) {
@@ -827,6 +919,33 @@ double field_integral_unit(const mpsph_params *p) {
 
 // Bounds of s over the bounding box, and a Lipschitz constant of s (domain units).
 bool spacing_bounds(const mpsph_params *p, double s0, double *smin, double *smax, double *lip) {
+  if (p->field == MPSPH_GRID) {
+    // the interpolant stays within the node extremes; its slope along an axis is bounded by the
+    // largest node difference along that axis over the spacing
+    const int d = p->dim;
+    size_t nodes = 1;
+    for (int a = 0; a < d; ++a) nodes *= (size_t)p->grid_n[a];
+    double lo = INFINITY, hi = 0.0, l2 = 0.0;
+    for (size_t k = 0; k < nodes; ++k) {
+      lo = std::min(lo, p->grid_s[k]);
+      hi = std::max(hi, p->grid_s[k]);
+    }
+    size_t stride = 1;
+    for (int a = 0; a < d; ++a) {
+      const double hs = (p->hi[a] - p->lo[a]) / (p->grid_n[a] - 1);
+      double m = 0.0;
+      for (size_t k = 0; k < nodes; ++k) {
+        const size_t ia = (k / stride) % (size_t)p->grid_n[a];
+        if (ia + 1 < (size_t)p->grid_n[a]) m = std::max(m, std::fabs(p->grid_s[k + stride] - p->grid_s[k]));
+      }
+      l2 += (m / hs) * (m / hs);
+      stride *= (size_t)p->grid_n[a];
+    }
+    *smin = s0 * lo;
+    *smax = s0 * hi;
+    *lip = s0 * std::sqrt(l2);
+    return *smin > 0 && std::isfinite(*smax);
+  }
   switch (p->field) {
     case MPSPH_UNIFORM:
       *smin = *smax = s0;
@@ -1013,6 +1132,8 @@ struct Domain {
   uint32_t ncells = 0, cellbase = 0;
   int blk0 = 0, nblk = 0, row0 = 0, nrow = 0;
   size_t rbf0 = 0;  // first RBF term of this domain in the packed RBF arrays
+  std::vector<double> gphi, gs;  // background-mesh node values (level set, field)
+  size_t gphi0 = 0, gs0 = 0;     // first node of this domain in the packed device arrays
   int uidx = 0;     // index of the domain in the caller's list
   int64_t uoff = 0, xoff = 0;  // first row / first float of the domain in the caller's arrays
 
@@ -1037,6 +1158,10 @@ struct Domain {
     row0 = o.row0;
     nrow = o.nrow;
     rbf0 = o.rbf0;
+    gphi = o.gphi;
+    gs = o.gs;
+    gphi0 = o.gphi0;
+    gs0 = o.gs0;
     uidx = o.uidx;
     uoff = o.uoff;
     xoff = o.xoff;
@@ -1044,6 +1169,8 @@ struct Domain {
       p.rbf_centre = rbf_centre.data();
       p.rbf_coeff = rbf_coeff.data();
     }
+    p.grid_phi = gphi.empty() ? nullptr : gphi.data();
+    p.grid_s = gs.empty() ? nullptr : gs.data();
     return *this;
   }
 };
@@ -1071,6 +1198,14 @@ int make_domain(const mpsph_params *params, int64_t n, Domain *dm) {
     dm->p.rbf_centre = nullptr;
     dm->p.rbf_coeff = nullptr;
   }
+  size_t nodes = 1;
+  for (int a = 0; a < params->dim; ++a) nodes *= (size_t)std::max(params->grid_n[a], 1);
+  dm->gphi.clear();
+  dm->gs.clear();
+  if (params->geometry == MPSPH_LEVELSET) dm->gphi.assign(params->grid_phi, params->grid_phi + nodes);
+  if (params->field == MPSPH_GRID) dm->gs.assign(params->grid_s, params->grid_s + nodes);
+  dm->p.grid_phi = dm->gphi.empty() ? nullptr : dm->gphi.data();
+  dm->p.grid_s = dm->gs.empty() ? nullptr : dm->gs.data();
   double s0 = params->s0;
   if (!(s0 > 0)) {
     double I = field_integral_unit(&dm->p);
@@ -1098,7 +1233,8 @@ struct Layout {
   size_t n_rbf = 0;
   size_t bytes = 0;
   size_t s_key, s_off, s_ct, s_id, w_key, w_pos, w_jaux, w_id, k0, v0, k1, v1, hist, cstart, acc, rho, nn, aabs, at, v,
-      dr, partials, partials2, groups, metrics, dtslots, stepctr, bad, paircount, doms, vscale, rbf_c, rbf_o, rbf_k;
+      dr, partials, partials2, groups, metrics, dtslots, stepctr, bad, paircount, doms, vscale, rbf_c, rbf_o, rbf_k,
+      gphi, gs;
 };
 
 // Orders the domains internally (2D before 3D, otherwise as given), assigns particle offsets,
@@ -1122,7 +1258,7 @@ int plan(std::vector<Domain> &doms, int lanes, Layout *out) {
   uint64_t cells = 0;
   int64_t n = 0;
   int64_t blocks = 0;
-  size_t nrbf = 0;
+  size_t nrbf = 0, ngphi = 0, ngs = 0;
   for (int gi = 0; gi < 2; ++gi) {
     L.grp[gi].D = 2 + gi;
     L.grp[gi].d0 = 0;
@@ -1140,6 +1276,10 @@ int plan(std::vector<Domain> &doms, int lanes, Layout *out) {
     dm.blk0 = (int)blocks;
     dm.nblk = (int)((dm.n * lanes + kBlock - 1) / kBlock);
     dm.rbf0 = nrbf;
+    dm.gphi0 = ngphi;
+    dm.gs0 = ngs;
+    ngphi += dm.gphi.size();
+    ngs += dm.gs.size();
     n += dm.n;
     cells += dm.ncells;
     blocks += dm.nblk;
@@ -1207,13 +1347,16 @@ int plan(std::vector<Domain> &doms, int lanes, Layout *out) {
   L.rbf_c = take(std::max<size_t>(nrbf, 1) * 3 * 4);
   L.rbf_o = take(std::max<size_t>(nrbf, 1) * 3 * 4);
   L.rbf_k = take(std::max<size_t>(nrbf, 1) * 4);
+  L.gphi = take(std::max<size_t>(ngphi, 1) * 4);
+  L.gs = take(std::max<size_t>(ngs, 1) * 4);
   L.bytes = o;
   *out = L;
   return MPSPH_OK;
 }
 
 // Device constants of a domain (grid, region and field in cell units; step constants).
-DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, const float *rbf_k) {
+DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, const float *rbf_k, const float *gphi,
+                     const float *gsv) {
   const mpsph_params &p = dm.p;
   const double cs = dm.d.cs, ics = dm.d.inv_cs;
   const int D = p.dim;
@@ -1237,6 +1380,13 @@ DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, con
   }
   g.r_in = (float)(p.r_in * ics);
   g.r_out = (float)(p.r_out * ics);
+  // background mesh: node spacing (hi - lo) / (n - 1) in cell units
+  for (int a = 0; a < 3; ++a) {
+    const int na = a < D ? std::max(p.grid_n[a], 2) : 2;
+    g.gn[a] = na;
+    g.ginv[a] = a < D ? (double)(na - 1) / ((p.hi[a] - p.lo[a]) * ics) : 1.0;
+  }
+  g.phi = p.geometry == MPSPH_LEVELSET ? gphi + dm.gphi0 : nullptr;
   FieldDev &f = dd.f;
   f.kind = p.field;
   f.s0 = (float)(dm.s0 * ics);
@@ -1251,6 +1401,11 @@ DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, con
   f.rbf_c = rbf_c + 3 * dm.rbf0;
   f.rbf_o = rbf_o + 3 * dm.rbf0;
   f.rbf_k = rbf_k + dm.rbf0;
+  for (int a = 0; a < 3; ++a) {
+    f.gn[a] = g.gn[a];
+    f.ginv[a] = g.ginv[a];
+  }
+  f.gs = p.field == MPSPH_GRID ? gsv + dm.gs0 : nullptr;
   StepDev &sp = dd.sp;
   sp.kappa = (float)p.kappa;
   sp.tau = (float)p.tau;
@@ -1530,7 +1685,8 @@ int setup_device(mpsph_ctx *ctx) {
   std::vector<float> ro3(3 * std::max<size_t>(L.n_rbf, 1), 0.f), rk(std::max<size_t>(L.n_rbf, 1), 0.f);
   for (int d = 0; d < ndom; ++d) {
     const Domain &dm = ctx->dom[d];
-    dd[d] = domain_device(dm, ctx->at<int>(L.rbf_c), ctx->at<float>(L.rbf_o), ctx->at<float>(L.rbf_k));
+    dd[d] = domain_device(dm, ctx->at<int>(L.rbf_c), ctx->at<float>(L.rbf_o), ctx->at<float>(L.rbf_k),
+                          ctx->at<float>(L.gphi), ctx->at<float>(L.gs));
     for (int r = 0; r < dm.nrow; ++r) {
       const int64_t a = dm.blk0 + (int64_t)r * L.chunk;
       groups.push_back(make_int2((int)a, (int)std::min<int64_t>(a + L.chunk, dm.blk0 + dm.nblk)));
@@ -1548,6 +1704,19 @@ int setup_device(mpsph_ctx *ctx) {
   HIP_OK(hipMemcpy(ctx->at<int>(L.rbf_c), rc3.data(), rc3.size() * 4, hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(ctx->at<float>(L.rbf_o), ro3.data(), ro3.size() * 4, hipMemcpyHostToDevice));
   HIP_OK(hipMemcpy(ctx->at<float>(L.rbf_k), rk.data(), rk.size() * 4, hipMemcpyHostToDevice));
+  // background-mesh values: the level set in cell units, the field's relative spacing as given
+  for (int d = 0; d < ndom; ++d) {
+    const Domain &dm = ctx->dom[d];
+    if (!dm.gphi.empty()) {
+      std::vector<float> v(dm.gphi.size());
+      for (size_t k = 0; k < v.size(); ++k) v[k] = (float)(dm.gphi[k] * dm.d.inv_cs);
+      HIP_OK(hipMemcpy(ctx->at<float>(L.gphi) + dm.gphi0, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+    }
+    if (!dm.gs.empty()) {
+      std::vector<float> v(dm.gs.begin(), dm.gs.end());
+      HIP_OK(hipMemcpy(ctx->at<float>(L.gs) + dm.gs0, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+    }
+  }
   return MPSPH_OK;
 }
 
@@ -2229,7 +2398,8 @@ int mpsph_set_field_coeff(mpsph_ctx *ctx, int32_t domain, const double *coeff) {
   }
   dm.d = nd;
   const Layout &L = ctx->L;
-  const DomDev dd = domain_device(dm, ctx->at<int>(L.rbf_c), ctx->at<float>(L.rbf_o), ctx->at<float>(L.rbf_k));
+  const DomDev dd = domain_device(dm, ctx->at<int>(L.rbf_c), ctx->at<float>(L.rbf_o), ctx->at<float>(L.rbf_k),
+                                  ctx->at<float>(L.gphi), ctx->at<float>(L.gs));
   std::vector<float> rk(std::max(dm.p.n_rbf, 1));
   for (int m = 0; m < dm.p.n_rbf; ++m) rk[m] = (float)coeff[m];
   HIP_OK(hipStreamSynchronize(ctx->stream));

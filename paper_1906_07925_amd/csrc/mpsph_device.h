@@ -45,6 +45,9 @@ struct GridDev {
   int gc_c[3];       // annulus / ball centre: cell + offset
   float gc_o[3];
   float r_in, r_out; // radii in cell units
+  const float *phi;  // MPSPH_LEVELSET: level set at the background-mesh nodes (cell units)
+  int gn[3];         // background-mesh nodes per axis
+  double ginv[3];    // 1 / node spacing in cell units
 };
 
 // Target size field in cell units: s_cell(x) = s(x) / cs.
@@ -60,7 +63,56 @@ struct FieldDev {
   const int *rbf_c;  // n_rbf x 3 cell coordinates of the centres
   const float *rbf_o;// n_rbf x 3 offsets
   const float *rbf_k;// n_rbf coefficients
+  const float *gs;   // MPSPH_GRID: relative spacing at the background-mesh nodes
+  int gn[3];
+  double ginv[3];
 };
+
+// Multilinear interpolation of node values on a background mesh (nodes at multiples of the
+// node spacing from the box corner, x index fastest) at a position given as cell + offset.
+// The node coordinate is formed in FP64 so that it keeps the offset's precision on any grid;
+// weights and sums are FP32.  grad (may be null) receives the derivative of the interpolant
+// in cell units.
+template <int D>
+__device__ __forceinline__ float mesh_interp(const float *nodes, const int *gn, const double *ginv, const int *c,
+                                             const float *o, float *grad) {
+  int base[3] = {0, 0, 0};
+  float f[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double u = ((double)c[a] + (double)o[a]) * ginv[a];
+    int i = (int)floor(u);
+    i = min(max(i, 0), gn[a] - 2);
+    base[a] = i;
+    f[a] = (float)(u - (double)i);
+  }
+  float val = 0.f, g[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int cn = 0; cn < (1 << D); ++cn) {
+    size_t idx = 0, stride = 1;
+    float w = 1.f, dw[3] = {1.f, 1.f, 1.f};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int bit = (cn >> a) & 1;
+      idx += (size_t)(base[a] + bit) * stride;
+      stride *= (size_t)gn[a];
+      const float wa = bit ? f[a] : 1.f - f[a];
+      const float da = bit ? (float)ginv[a] : -(float)ginv[a];
+#pragma unroll
+      for (int b = 0; b < D; ++b) dw[b] *= (b == a) ? da : wa;
+      w *= wa;
+    }
+    const float v = nodes[idx];
+    val = fmaf(w, v, val);
+#pragma unroll
+    for (int b = 0; b < D; ++b) g[b] = fmaf(dw[b], v, g[b]);
+  }
+  if (grad) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) grad[a] = a < D ? g[a] : 0.f;
+  }
+  return val;
+}
 
 // Constants of one step (cell units; time in the caller's units).
 struct StepDev {
@@ -159,6 +211,7 @@ __device__ __forceinline__ float powd(float s) {  // s^D
 template <int D>
 __device__ __forceinline__ float field_spacing(const FieldDev &f, const int *c, const float *o) {
   if (f.kind == 0) return f.s0;
+  if (f.kind == 4) return f.s0 * mesh_interp<D>(f.gs, f.gn, f.ginv, c, o, nullptr);
   if (f.kind == 1 || f.kind == 2) {
     float r2 = 0.f;
 #pragma unroll
@@ -215,6 +268,22 @@ __device__ __forceinline__ void project_feature(const GridDev &g, int type, cons
       bool hi = c[a] == g.whi_c[a] && o[a] == g.whi_o[a];
       if (lo || hi) v[a] = 0.f;
     }
+  } else if (g.geometry == 4) {
+    // level set: N = grad phi / |grad phi| (Eq. 31)
+    float n[3], dot = 0.f;
+    mesh_interp<D>(g.phi, g.gn, g.ginv, c, o, n);
+    float n2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < D; ++a) n2 += n[a] * n[a];
+    if (!(n2 > 0.f)) return;
+    const float inv = fast_rsq(n2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      n[a] *= inv;
+      dot += n[a] * v[a];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] -= dot * n[a];
   } else {
     float n[3], r2 = 0.f, dot = 0.f;
 #pragma unroll

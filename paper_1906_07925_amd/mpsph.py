@@ -14,8 +14,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpsph.so")
 
-GEOMETRY = {"box": 1, "annulus": 2, "ball": 3}
-FIELD = {"uniform": 0, "radial_linear": 1, "sphere_distance": 2, "rbf_exp": 3}
+GEOMETRY = {"box": 1, "annulus": 2, "ball": 3, "levelset": 4}
+FIELD = {"uniform": 0, "radial_linear": 1, "sphere_distance": 2, "rbf_exp": 3, "grid": 4}
 FIELDS = {"rho": 0, "rho_t": 1, "h": 2, "a": 3, "a_abs": 4, "vt": 5, "at": 6, "v": 7, "dr": 8, "nn": 9,
           "x0": 10}
 VECTOR_FIELDS = {"a", "vt", "at", "v", "dr", "x0"}
@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("c_acc", C.c_double), ("c_vel", C.c_double), ("c_visc", C.c_double),
         ("cell_log2", C.c_int32), ("debug", C.c_int32),
         ("t0_window", C.c_int32), ("t0_tol", C.c_double), ("theta", C.c_double),
+        ("grid_n", C.c_int32 * 3), ("grid_phi", C.POINTER(C.c_double)), ("grid_s", C.POINTER(C.c_double)),
     ]
 
 
@@ -149,6 +150,14 @@ def make_params(spec: dict, s0: float | None = None, cell_log2: int = -1, debug:
     p.s0 = float(s0) if s0 is not None else 0.0
     p.cell_log2 = int(cell_log2)
     p.debug = 1 if debug else 0
+    gn = spec.get("grid_n", (0, 0, 0))
+    for a in range(3):
+        p.grid_n[a] = int(gn[a]) if a < d and a < len(gn) else 0
+    for key in ("grid_phi", "grid_s"):
+        if key in spec:
+            arr = np.ascontiguousarray(np.asarray(spec[key], dtype=np.float64).reshape(-1))
+            keep.append(arr)
+            setattr(p, key, arr.ctypes.data_as(C.POINTER(C.c_double)))
     p.t0_window = int(spec.get("t0_window", 50))
     p.t0_tol = float(spec.get("t0_tol", 1e-3))
     p.theta = float(spec.get("theta", 0.2))
