@@ -13,7 +13,8 @@ the dominant kernel, the CPU oracle timed on the host on a bounded sample, and (
 "batched") 64 independent mixed 2D/3D domains relaxed in one batched context against the same
 domains solved one after the other, and (object "adjoint", field "adjoint_forward_ratio") the
 reverse sweep of the gradient of the relaxation loss over 50 steps of the 2^20-particle RBF cube
-against 50 forward steps.
+against 50 forward steps, and (object "mesh") the ball given on a background mesh, with the
+state-gather kernel that interpolates the field measured against HBM bandwidth.
 """
 from __future__ import annotations
 
@@ -176,6 +177,39 @@ def adjoint_run(torch, M, W, steps: int = 50, ckpt: int = 10, lam: float = 1.0):
             "ratio": bwd_ms / fwd_ms, "loss": loss, "grad_norm": float(np.linalg.norm(gc))}
 
 
+def mesh_run(torch, M, W, steps: int = 50, warmup: int = 20):
+    """The ball given as a level set and a graded field on a 48^3 background mesh, 2^20
+    particles (random equal-mass init, 16 colours): step time and the state-gather kernel that
+    interpolates the field (HIP events on the library stream).  Its algorithmic HBM bytes per
+    particle: 28 read (permutation, offsets, flags, id) and 28 written (key, position + h, flags,
+    id); the 442 KB mesh stays in cache."""
+    spec = W.levelset_ball(1 << 20)
+    x, col, typ = W.make_state(dict(spec=spec, seed=W.BASE_SEED + 50, init="random", n_colours=16))
+    n = x.shape[0]
+    R = M.Relaxer(dict(spec, n=n), n=n)
+    R.load(torch.from_numpy(x.astype(np.float32)).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    R.step(warmup)
+    torch.cuda.synchronize()
+    R.profile(True)
+    t0 = time.perf_counter()
+    R.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = R.profile_read()
+    R.profile(False)
+    m = R.metrics()
+    R.close()
+    launches, ms = kern["reorder_field"]
+    avg_s = ms / launches / 1e3
+    gbs = 56.0 * n / avg_s / 1e9
+    print(f"[bench] mesh: {1e3 * dt / steps:.2f} ms/step, field gather {1e3 * avg_s:.3f} ms", file=sys.stderr, flush=True)
+    return {"workload": "levelset_ball_1m", "particles": n, "mesh_nodes": "48^3", "steps": steps,
+            "ms_per_step": 1e3 * dt / steps, "field_gather_ms": 1e3 * avg_s,
+            "field_gather_roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                      "frac": gbs / PEAK_HBM_GBS, "bytes_per_particle": 56},
+            "n_feature": m["n_feature"], "nonfinite": m["nonfinite"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +221,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-domain batched comparison")
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the background-mesh workload")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -286,6 +321,8 @@ def main():
     R.close()
     if not args.no_batched:
         out["batched"] = batched_run(torch, M, W, args.batched_steps, 10)
+    if not args.no_mesh:
+        out["mesh"] = mesh_run(torch, M, W)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_run(torch, M, W)
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]

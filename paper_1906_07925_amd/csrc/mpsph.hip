@@ -93,6 +93,30 @@ __global__ __launch_bounds__(kBlock) void load_kernel(const DomDev *__restrict__
   id[i] = (uint32_t)u;
 }
 
+// Empty-cell runs of at least this length are filled by fill_gaps instead of one thread.
+constexpr uint32_t kShortGap = 64;
+constexpr int kGapBlocks = 256;
+
+// Fills the long empty-cell runs listed by reorder_field: block b takes runs b, b + grid, ...,
+// its threads stride over the cells of a run.  The last block to finish resets the list (no
+// memset, so the launch can be captured in a graph).
+__global__ __launch_bounds__(256) void fill_gaps(const uint4 *__restrict__ gaps, uint32_t *__restrict__ gcount,
+                                                 uint32_t *__restrict__ gdone, uint32_t *__restrict__ cstart) {
+  const uint32_t cnt = *(volatile uint32_t *)gcount;
+  for (uint32_t g = blockIdx.x; g < cnt; g += gridDim.x) {
+    const uint4 r = gaps[g];
+    for (uint32_t c = r.x + threadIdx.x; c <= r.y; c += blockDim.x) cstart[c] = r.z;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(gdone, 1u) == gridDim.x - 1) {
+      *gcount = 0u;
+      *gdone = 0u;
+    }
+  }
+}
+
 // Gather the state in sorted order, evaluate the size field (h = tau s, Eq. 16) and build the
 // cell table: cstart[c] = first sorted index with key >= c, cstart[ncells] = n.  Sorted keys are
 // grouped by domain, so the sorted range of domain d is [off_d, off_d + n_d); one launch covers
@@ -104,15 +128,23 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
     const uint32_t *__restrict__ skey, const uint32_t *__restrict__ perm, const float4 *__restrict__ soff,
     const uint32_t *__restrict__ sct, const uint32_t *__restrict__ sid, uint32_t *__restrict__ wkey,
     float4 *__restrict__ wpos, uint32_t *__restrict__ wjaux, uint32_t *__restrict__ wid,
-    uint32_t *__restrict__ cstart, uint32_t *__restrict__ dtslots) {
+    uint32_t *__restrict__ cstart, uint32_t *__restrict__ dtslots, uint4 *__restrict__ gaps,
+    uint32_t *__restrict__ gcount) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t < nreset) dtslots[t] = kInfBits;
   const int i = i0 + t;
   if (i > i1 || (i == i1 && i1 != n)) return;
-  // cells (key[i-1], key[i]] start at sorted index i; the sentinel thread i = n closes the table
+  // cells (key[i-1], key[i]] start at sorted index i; the sentinel thread i = n closes the table.
+  // Long runs of empty cells (regions without particles) go to a list that fill_gaps spreads
+  // over many threads.
   const uint32_t lo = i == 0 ? 0u : skey[i - 1] + 1u;
   const uint32_t hi = i == n ? ncells : min(skey[i], ncells);
-  for (uint32_t c = lo; c <= hi; ++c) cstart[c] = (uint32_t)i;
+  if (hi >= lo && hi - lo >= kShortGap) {
+    const uint32_t slot = atomicAdd(gcount, 1u);
+    gaps[slot] = make_uint4(lo, hi, (uint32_t)i, 0u);
+  } else {
+    for (uint32_t c = lo; c <= hi; ++c) cstart[c] = (uint32_t)i;
+  }
   if (i == n) return;
   const DomDev &dd = doms[domain_of(doms, ndom, i)];
   const uint32_t s = perm[i];
@@ -1234,7 +1266,7 @@ struct Layout {
   size_t bytes = 0;
   size_t s_key, s_off, s_ct, s_id, w_key, w_pos, w_jaux, w_id, k0, v0, k1, v1, hist, cstart, acc, rho, nn, aabs, at, v,
       dr, partials, partials2, groups, metrics, dtslots, stepctr, bad, paircount, doms, vscale, rbf_c, rbf_o, rbf_k,
-      gphi, gs;
+      gphi, gs, gaps, gcount;
 };
 
 // Orders the domains internally (2D before 3D, otherwise as given), assigns particle offsets,
@@ -1327,6 +1359,8 @@ int plan(std::vector<Domain> &doms, int lanes, Layout *out) {
   L.v1 = take(nn * 4);
   L.hist = take(radix_hist_words((int)n) * 4);
   L.cstart = take(((size_t)L.ncells + 1) * 4);
+  L.gaps = take((nn + 1) * sizeof(uint4));   // at most one empty-cell run per sorted particle
+  L.gcount = take(8);                       // run count, finished blocks of fill_gaps
   L.acc = take(nn * 16);
   L.rho = take(nn * 4);
   L.nn = take(nn * 4);
@@ -1495,7 +1529,10 @@ void launch_group(mpsph_ctx *ctx, const Group &gr, const uint32_t *skeys, const 
   reorder_field<D><<<(nthr + kBlock - 1) / kBlock, kBlock, 0, st>>>(
       doms, gr.nd, gr.i0, gr.i1, n, L.ncells, nreset, skeys, perm, ctx->at<float4>(L.s_off), ctx->at<uint32_t>(L.s_ct),
       ctx->at<uint32_t>(L.s_id), ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux),
-      ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<uint32_t>(L.dtslots));
+      ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<uint32_t>(L.dtslots), ctx->at<uint4>(L.gaps),
+      ctx->at<uint32_t>(L.gcount));
+  fill_gaps<<<kGapBlocks, 256, 0, st>>>(ctx->at<uint4>(L.gaps), ctx->at<uint32_t>(L.gcount),
+                                        ctx->at<uint32_t>(L.gcount) + 1, ctx->at<uint32_t>(L.cstart));
   if (hk) hk->end();
 }
 
