@@ -62,7 +62,9 @@ enum {
 /* Meshing region: the positive phase of the level set (§3.1, Eq. 14).  MPSPH_LEVELSET: the
  * level set is given at the nodes of a Cartesian background mesh over [lo, hi] (§3.1-3.2) and
  * interpolated multilinearly; particles leaving it are projected by r <- r - phi N (Eq. 32). */
-enum { MPSPH_BOX = 1, MPSPH_ANNULUS = 2, MPSPH_BALL = 3, MPSPH_LEVELSET = 4 };
+enum { MPSPH_PERIODIC = 0, MPSPH_BOX = 1, MPSPH_ANNULUS = 2, MPSPH_BALL = 3, MPSPH_LEVELSET = 4 };
+/* MPSPH_PERIODIC: a cube (square) [lo, hi) without walls, periodic in every axis (minimum-image
+ * separations); the cut-off kappa h must stay below half the side (MPSPH_E_UNSUPPORTED). */
 
 /* Target size field s(x); rho_t = s^-dim (unit particle mass, Eq. 15), h = tau s (Eq. 16). */
 enum {

@@ -71,8 +71,9 @@ __global__ __launch_bounds__(kBlock) void load_kernel(const DomDev *__restrict__
   float o[3] = {0.f, 0.f, 0.f};
   bool ok = true;
   for (int a = 0; a < D; ++a) {
-    const double X = ((double)x[a] - dd.lo[a]) * dd.inv_cs;
+    double X = ((double)x[a] - dd.lo[a]) * dd.inv_cs;
     if (!(X >= 0.0 && X <= dd.xhi[a])) ok = false;
+    if (dd.g.geometry == 0 && X >= dd.xhi[a]) X -= dd.xhi[a];   // periodic: hi is lo
     double f = floor(X);
     float fo = (float)(X - f);
     if (fo >= 1.0f) {
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
 // Writes acc = (a after the force mapping of Eq. 30-31, e_i) with e_i = rho_t nu_coeff r_c |a_i|,
 // the viscosity of Eq. 21-22 per unit of dt1/2, and the first time-step candidate (Eq. 29).
 // L lanes per particle (group); lane 0 of the group writes the particle's results.
-template <int D, int L>
+template <int D, int L, bool PER>
 __global__ __launch_bounds__(kBlock) void pass_density_force(
     const DomDev *__restrict__ doms, int ndom, int b0, const int64_t *__restrict__ stepctr, const uint32_t *__restrict__ wkey,
     const float4 *__restrict__ wpos, const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ cstart,
@@ -211,10 +212,10 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
     const float opb = 1.f + sigma;
     float wsum = 0.f, ax = 0.f, ay = 0.f, az = 0.f, A = 0.f, nn2 = INFINITY;
     uint32_t npair = 0, nifc = 0;
-    uint32_t ncand = scan_group<D, L>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](int j, uint32_t drw, bool v) {
+    uint32_t ncand = scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](int j, uint32_t drw, bool v) {
       const float4 pj = wpos[j];
       const uint32_t aj = wjaux[j];
-      const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+      const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
       const float dy = row_dy(drw) + (oi[1] - pj.y);
       float r2 = dx * dx + dy * dy;
       float dz = 0.f;
@@ -315,7 +316,7 @@ __device__ __forceinline__ int type_from_faces(int nf, int d) {
 // feature projection / re-tagging (Eq. 32); the new state is written in this step's order.
 // With v~ = a dt1/2 the three criteria of Eq. 29 are increasing functions of r_c/|a| and give
 // dt2 = dt1 min(1, 2 min(c_vel, c_visc / nu_coeff) / c_acc^2) (sp.dt2_factor).
-template <int D, int L>
+template <int D, int L, bool PER>
 __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
     const DomDev *__restrict__ doms, int ndom, int b0, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
     const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ wid, const uint32_t *__restrict__ cstart,
@@ -353,10 +354,10 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
     float bx = 0.f, by = 0.f, bz = 0.f;
     // with eta_i = 0 every harmonic-mean viscosity of particle i vanishes: nothing to sum
     if (ei > 0.f) {
-      scan_group<D, L>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](int j, uint32_t drw, bool v) {
+      scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](int j, uint32_t drw, bool v) {
         const float4 pj = wpos[j];
         const uint32_t aj = wjaux[j];
-        const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+        const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
         const float dy = row_dy(drw) + (oi[1] - pj.y);
         float r2 = dx * dx + dy * dy;
         if constexpr (D == 3) {
@@ -414,7 +415,11 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
             c[a] += 1;
           }
         }
-        if (g.geometry == 1) {
+        if (PER && g.geometry == 0) {
+          // periodic box: wrap into [0, P)
+#pragma unroll
+          for (int a = 0; a < D; ++a) c[a] = ((c[a] % (g.gmax + 1)) + (g.gmax + 1)) % (g.gmax + 1);
+        } else if (g.geometry == 1) {
           // box: closest-point projection is a clamp to the walls; type from the faces touched
           int nf = 0;
 #pragma unroll
@@ -516,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
 // last step's start-of-step state, enumerated with the same candidate scan and predicate as the
 // pair passes (one lane per particle).  Pairs go to (out_i, out_j) as load indices while the
 // running count stays below cap; *count receives the total.
-template <int D>
+template <int D, bool PER>
 __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ doms, int ndom, int i0, int i1,
                                                      const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
                                                      const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ wid,
@@ -536,10 +541,10 @@ __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ 
   const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
   const float kh = 0.5f * sp.kappa;
   const uint32_t idi = wid[i];
-  scan_group<D, 1>(i, 0, ci, oi, rs, g, dd.cellbase, cstart, [&](int j, uint32_t drw, bool v) {
+  scan_group<D, 1, PER>(i, 0, ci, oi, rs, g, dd.cellbase, cstart, [&](int j, uint32_t drw, bool v) {
     const float4 pj = wpos[j];
     const uint32_t aj = wjaux[j];
-    const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+    const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
     const float dy = row_dy(drw) + (oi[1] - pj.y);
     float r2 = dx * dx + dy * dy;
     if constexpr (D == 3) {
@@ -726,7 +731,10 @@ const char *kErr[] = {"ok", "invalid argument", "out of memory", "device error",
 bool valid_params(const mpsph_params *p) {
   if (!p) return false;
   if (p->dim != 2 && p->dim != 3) return false;
-  if (p->geometry < MPSPH_BOX || p->geometry > MPSPH_LEVELSET) return false;
+  if (p->geometry < MPSPH_PERIODIC || p->geometry > MPSPH_LEVELSET) return false;
+  if (p->geometry == MPSPH_PERIODIC)  // periodic: a cube (a square in 2D), every side one period
+    for (int a = 1; a < p->dim; ++a)
+      if (p->hi[a] - p->lo[a] != p->hi[0] - p->lo[0]) return false;
   if (p->geometry == MPSPH_LEVELSET || p->field == MPSPH_GRID) {
     int64_t nodes = 1;
     for (int a = 0; a < p->dim; ++a) {
@@ -829,7 +837,7 @@ double host_spacing(const mpsph_params *p, double s0, const double *x) {
 }
 
 bool inside_region(const mpsph_params *p, const double *x) {
-  if (p->geometry == MPSPH_BOX) return true;
+  if (p->geometry == MPSPH_BOX || p->geometry == MPSPH_PERIODIC) return true;
   if (p->geometry == MPSPH_LEVELSET) return host_mesh(p, p->grid_phi, x) > 0.0;
   double r = 0;
   for (int a = 0; a < p->dim; ++a) r += (x[a] - p->centre[a]) * (x[a] - p->centre[a]);
@@ -879,8 +887,9 @@ double field_integral_unit(const mpsph_params *p) {
     }
     return total * vol;
   }
+  const bool boxlike = p->geometry == MPSPH_BOX || p->geometry == MPSPH_PERIODIC;
   if (p->field == MPSPH_UNIFORM) {  // s = 1: the measure of the region
-    if (p->geometry == MPSPH_BOX) {
+    if (boxlike) {
       double v = 1.0;
       for (int a = 0; a < d; ++a) v *= p->hi[a] - p->lo[a];
       return v;
@@ -888,7 +897,7 @@ double field_integral_unit(const mpsph_params *p) {
     if (p->geometry == MPSPH_ANNULUS) return pi * (p->r_out * p->r_out - p->r_in * p->r_in);
     return d == 2 ? pi * p->r_out * p->r_out : 4.0 / 3.0 * pi * p->r_out * p->r_out * p->r_out;
   }
-  if (p->geometry == MPSPH_BOX) {
+  if (boxlike) {
     const int M = d == 2 ? 256 : (p->field == MPSPH_GRID ? 24 : 48);
     const int np = M * 8;
     std::vector<double> node[3], wt[3];
@@ -1037,8 +1046,10 @@ int derive(const mpsph_params *p, int64_t n, double s0, Derived *d) {
   if (p->dim * k > 24) return MPSPH_E_UNSUPPORTED;
   d->k = k;
   d->gmax = (1 << k) - 1;
-  d->cs = L / (double)d->gmax;
-  d->inv_cs = (double)d->gmax / L;
+  // walls at cells 0 and 2^k - 1 (offset 0); a periodic box wraps after 2^k cells
+  const double span = p->geometry == MPSPH_PERIODIC ? (double)(1 << k) : (double)d->gmax;
+  d->cs = L / span;
+  d->inv_cs = span / L;
   for (int a = 0; a < 3; ++a) d->xhi[a] = a < p->dim ? (p->hi[a] - p->lo[a]) * d->inv_cs : 0.0;
   // neighbour search bound: j interacts only if r < kappa (h_i + h_j)/2 and h_j <= h_i + L_h r
   // (L_h = tau * Lipschitz(s)), so r < kappa h_i / (1 - kappa L_h / 2).
@@ -1046,6 +1057,8 @@ int derive(const mpsph_params *p, int64_t n, double s0, Derived *d) {
   double fac = 1e30;
   if (p->kappa * Lh / 2 < 0.95) fac = p->kappa / (1.0 - p->kappa * Lh / 2);
   d->search_fac = std::max(fac, p->kappa) * (1.0 + 1e-4);
+  // minimum images are unique only while the cut-off stays below half the period
+  if (p->geometry == MPSPH_PERIODIC && !(p->kappa * p->tau * d->smax < 0.5 * L)) return MPSPH_E_UNSUPPORTED;
   return MPSPH_OK;
 }
 
@@ -1210,6 +1223,7 @@ struct Domain {
 // Domains of one dimension occupy consecutive internal domain, particle and block ranges.
 struct Group {
   int D = 0;
+  bool periodic = false;  // some domain of the group is a periodic box
   int d0 = 0, nd = 0;   // internal domains
   int i0 = 0, i1 = 0;   // internal particles
   int b0 = 0, nb = 0;   // pair-kernel blocks
@@ -1321,6 +1335,7 @@ int plan(std::vector<Domain> &doms, int lanes, Layout *out) {
     g.nd += 1;
     g.i1 = (int)n;
     g.nb += dm.nblk;
+    g.periodic |= dm.p.geometry == MPSPH_PERIODIC;
   }
   // first-level reduction: rows of at most `chunk` block partials, never straddling domains
   const int64_t chunk = std::max<int64_t>(1, (blocks + kReduceBlocks - 1) / kReduceBlocks);
@@ -1536,11 +1551,11 @@ void launch_group(mpsph_ctx *ctx, const Group &gr, const uint32_t *skeys, const 
   if (hk) hk->end();
 }
 
-template <int D, int L_>
+template <int D, int L_, bool PER>
 void launch_pass1_l(mpsph_ctx *ctx, const Group &gr, hipStream_t st) {
   const Layout &L = ctx->L;
   const bool dbg = ctx->dom[0].p.debug != 0;
-  pass_density_force<D, L_><<<gr.nb, kBlock, 0, st>>>(
+  pass_density_force<D, L_, PER><<<gr.nb, kBlock, 0, st>>>(
       ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.b0, ctx->at<int64_t>(L.stepctr), ctx->at<uint32_t>(L.w_key),
       ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
       dbg ? ctx->at<float>(L.rho) : nullptr, dbg ? ctx->at<float>(L.nn) : nullptr,
@@ -1551,19 +1566,23 @@ void launch_pass1_l(mpsph_ctx *ctx, const Group &gr, hipStream_t st) {
 template <int D>
 void launch_pass1(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk) {
   if (hk) hk->begin("pass_density_force");
-  switch (ctx->L.lanes) {
-    case 2: launch_pass1_l<D, 2>(ctx, gr, st); break;
-    case 8: launch_pass1_l<D, 8>(ctx, gr, st); break;
-    default: launch_pass1_l<D, 4>(ctx, gr, st);
+  const int sel = ctx->L.lanes * 2 + (gr.periodic ? 1 : 0);
+  switch (sel) {
+    case 4: launch_pass1_l<D, 2, false>(ctx, gr, st); break;
+    case 5: launch_pass1_l<D, 2, true>(ctx, gr, st); break;
+    case 16: launch_pass1_l<D, 8, false>(ctx, gr, st); break;
+    case 17: launch_pass1_l<D, 8, true>(ctx, gr, st); break;
+    case 9: launch_pass1_l<D, 4, true>(ctx, gr, st); break;
+    default: launch_pass1_l<D, 4, false>(ctx, gr, st);
   }
   if (hk) hk->end();
 }
 
-template <int D, int L_>
+template <int D, int L_, bool PER>
 void launch_pass2_l(mpsph_ctx *ctx, const Group &gr, hipStream_t st, float4 *at_o, float4 *v_o) {
   const Layout &L = ctx->L;
   const bool dbg = ctx->dom[0].p.debug != 0;
-  pass_viscous_integrate<D, L_><<<gr.nb, kBlock, 0, st>>>(
+  pass_viscous_integrate<D, L_, PER><<<gr.nb, kBlock, 0, st>>>(
       ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.b0, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
       ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
       ctx->at<uint32_t>(L.dtslots) + (size_t)gr.d0 * kDtSlots, ctx->at<uint32_t>(L.s_key), ctx->at<float4>(L.s_off),
@@ -1579,10 +1598,14 @@ void launch_pass2(mpsph_ctx *ctx, const Group &gr, hipStream_t st, EventHook *hk
   float4 *at_o = at_rec ? at_rec : (dbg ? ctx->at<float4>(L.at) : nullptr);
   float4 *v_o = v_rec ? v_rec : (dbg ? ctx->at<float4>(L.v) : nullptr);
   if (hk) hk->begin("pass_viscous_integrate");
-  switch (L.lanes) {
-    case 2: launch_pass2_l<D, 2>(ctx, gr, st, at_o, v_o); break;
-    case 8: launch_pass2_l<D, 8>(ctx, gr, st, at_o, v_o); break;
-    default: launch_pass2_l<D, 4>(ctx, gr, st, at_o, v_o);
+  const int sel = L.lanes * 2 + (gr.periodic ? 1 : 0);
+  switch (sel) {
+    case 4: launch_pass2_l<D, 2, false>(ctx, gr, st, at_o, v_o); break;
+    case 5: launch_pass2_l<D, 2, true>(ctx, gr, st, at_o, v_o); break;
+    case 16: launch_pass2_l<D, 8, false>(ctx, gr, st, at_o, v_o); break;
+    case 17: launch_pass2_l<D, 8, true>(ctx, gr, st, at_o, v_o); break;
+    case 9: launch_pass2_l<D, 4, true>(ctx, gr, st, at_o, v_o); break;
+    default: launch_pass2_l<D, 4, false>(ctx, gr, st, at_o, v_o);
   }
   if (hk) hk->end();
 }
@@ -2399,7 +2422,8 @@ int mpsph_debug_pairs(mpsph_ctx *ctx, int64_t cap, uint32_t *d_i, uint32_t *d_j,
   HIP_OK(hipMemsetAsync(cnt, 0, 8, ctx->stream));
   for (const Group &gr : L.grp) {
     if (gr.i1 <= gr.i0) continue;
-    auto kern = gr.D == 2 ? dump_pairs<2> : dump_pairs<3>;
+    auto kern = gr.D == 2 ? (gr.periodic ? dump_pairs<2, true> : dump_pairs<2, false>)
+                          : (gr.periodic ? dump_pairs<3, true> : dump_pairs<3, false>);
     kern<<<(gr.i1 - gr.i0 + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
         ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.i0, gr.i1, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
         ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart),

@@ -261,6 +261,7 @@ __device__ __forceinline__ void project_feature(const GridDev &g, int type, cons
     for (int a = 0; a < D; ++a) v[a] = 0.f;
     return;
   }
+  if (g.geometry == 0) return;  // periodic box: no walls
   if (g.geometry == 1) {
 #pragma unroll
     for (int a = 0; a < D; ++a) {

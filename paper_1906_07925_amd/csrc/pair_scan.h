@@ -26,20 +26,54 @@ namespace mpsph {
 #define MPSPH_LANES 4
 #endif
 
+// x separation in cell units with the minimum image of a periodic box (period P cells); the
+// y and z separations come from unwrapped row offsets and need none.
+// PER: the launch may contain periodic domains (otherwise the periodic code is compiled out).
+template <bool PER>
+__device__ __forceinline__ float sep_x(const GridDev &g, int cxi, int cxj, float oxi, float oxj) {
+  float dx = (float)(cxi - cxj) + (oxi - oxj);
+  if (PER && g.geometry == 0) {
+    const float P = (float)(g.gmax + 1);
+    dx = dx > 0.5f * P ? dx - P : (dx < -0.5f * P ? dx + P : dx);
+  }
+  return dx;
+}
+
 __device__ __forceinline__ float row_dy(uint32_t dr) { return (float)(int)(int16_t)(dr & 0xffffu); }
 __device__ __forceinline__ float row_dz(uint32_t dr) { return (float)((int)dr >> 16); }
 
-template <int D, int L, typename BodyF>
+template <int D, int L, bool PER = false, typename BodyF>
 __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, const float *oi, float rs,
                                                const GridDev &g, uint32_t cellbase, const uint32_t *__restrict__ cstart,
                                                BodyF &&body) {
   // a finite, non-negative radius keeps every cell range inside [0, gmax] (NaN -> 0)
   rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
   const float rs2 = rs * rs;
-  const int z0 = D == 3 ? max(0, ci[2] + (int)floorf(oi[2] - rs)) : 0;
-  const int z1 = D == 3 ? min(g.gmax, ci[2] + (int)floorf(oi[2] + rs)) : 0;
-  const int y0 = max(0, ci[1] + (int)floorf(oi[1] - rs));
-  const int y1 = min(g.gmax, ci[1] + (int)floorf(oi[1] + rs));
+  // periodic box (period P = 2^k cells): rows are taken unwrapped around the particle, at most
+  // P of them, so that each row is visited once and its unwrapped offset is the minimum image
+  const bool per = PER && g.geometry == 0;
+  const int P = g.gmax + 1;
+  int z0 = D == 3 ? ci[2] + (int)floorf(oi[2] - rs) : 0;
+  int z1 = D == 3 ? ci[2] + (int)floorf(oi[2] + rs) : 0;
+  int y0 = ci[1] + (int)floorf(oi[1] - rs);
+  int y1 = ci[1] + (int)floorf(oi[1] + rs);
+  if (per) {
+    if (y1 - y0 + 1 > P) {
+      y0 = ci[1] - P / 2;
+      y1 = y0 + P - 1;
+    }
+    if (D == 3 && z1 - z0 + 1 > P) {
+      z0 = ci[2] - P / 2;
+      z1 = z0 + P - 1;
+    }
+  } else {
+    y0 = max(0, y0);
+    y1 = min(g.gmax, y1);
+    if (D == 3) {
+      z0 = max(0, z0);
+      z1 = min(g.gmax, z1);
+    }
+  }
   const int ny = y1 - y0 + 1;
   const int nrows = ny * (z1 - z0 + 1);
   const float inv_ny = 1.f / (float)ny;
@@ -59,10 +93,17 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
     const float d2 = ey * ey + ez * ez;
     const bool hit = q < nrows && d2 < rs2;
     const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
-    const int x0 = max(0, ci[0] + (int)floorf(oi[0] - wx));
-    const int x1 = min(g.gmax, ci[0] + (int)floorf(oi[0] + wx));
-    uint32_t kb = (uint32_t)x0 | ((uint32_t)cy << g.k);
-    if constexpr (D == 3) kb |= (uint32_t)cz << (2 * g.k);
+    int x0 = ci[0] + (int)floorf(oi[0] - wx);
+    int x1 = ci[0] + (int)floorf(oi[0] + wx);
+    if (per && (x0 < 0 || x1 > g.gmax)) {  // a run across the period: the whole row, once
+      x0 = 0;
+      x1 = g.gmax;
+    }
+    x0 = max(0, x0);
+    x1 = min(g.gmax, x1);
+    const int cyw = per ? (cy + P) & g.gmax : cy;   // |cy - ci| < P: one wrap at most
+    uint32_t kb = (uint32_t)x0 | ((uint32_t)cyw << g.k);
+    if constexpr (D == 3) kb |= (uint32_t)(per ? (cz + P) & g.gmax : cz) << (2 * g.k);
     kb += cellbase;
     uint32_t a = 0u, b = 0u;
     if (hit) {

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpsph.so")
 
-GEOMETRY = {"box": 1, "annulus": 2, "ball": 3, "levelset": 4}
+GEOMETRY = {"periodic": 0, "box": 1, "annulus": 2, "ball": 3, "levelset": 4}
 FIELD = {"uniform": 0, "radial_linear": 1, "sphere_distance": 2, "rbf_exp": 3, "grid": 4}
 FIELDS = {"rho": 0, "rho_t": 1, "h": 2, "a": 3, "a_abs": 4, "vt": 5, "at": 6, "v": 7, "dr": 8, "nn": 9,
           "x0": 10}
