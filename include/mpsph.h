@@ -171,7 +171,8 @@ MPSPH_API int mpsph_create(const mpsph_params *params, int64_t n, void *d_worksp
  * exactly (bit for bit) as it would in a context of its own; domains never interact.
  * Workspace and stream as in mpsph_create (mpsph_batch_workspace_bytes gives the size).
  * Errors: MPSPH_E_INVALID (bad params or counts, mixed debug flags, ndom outside [1, 4096]),
- * MPSPH_E_NOMEM, MPSPH_E_DEVICE, MPSPH_E_UNSUPPORTED (more than 2^30 particles or 2^28 cells). */
+ * MPSPH_E_NOMEM, MPSPH_E_DEVICE, MPSPH_E_UNSUPPORTED (more than 2^30 particles, particles x lanes
+ * per particle of 2^31 or more, or more than 2^28 cells). */
 MPSPH_API size_t mpsph_batch_workspace_bytes(int32_t ndom, const mpsph_params *params, const int64_t *n);
 MPSPH_API int mpsph_batch_create(int32_t ndom, const mpsph_params *params, const int64_t *n, void *d_workspace,
                                  size_t workspace_bytes, void *hip_stream, mpsph_ctx **out);

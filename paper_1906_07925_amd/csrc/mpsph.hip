@@ -1330,7 +1330,9 @@ int plan(std::vector<Domain> &doms, int lanes, Layout *out) {
     cells += dm.ncells;
     blocks += dm.nblk;
     nrbf += (size_t)dm.p.n_rbf;
-    if (n > ((int64_t)1 << 30) || cells > ((uint64_t)1 << 28) || blocks > ((int64_t)1 << 30))
+    // thread indices of the pair kernels (particles x lanes) stay below 2^31
+    if (n > ((int64_t)1 << 30) || n * lanes >= ((int64_t)1 << 31) || cells > ((uint64_t)1 << 28) ||
+        blocks > ((int64_t)1 << 30))
       return MPSPH_E_UNSUPPORTED;
     g.nd += 1;
     g.i1 = (int)n;
