@@ -94,11 +94,11 @@ typedef struct mpsph_ctx mpsph_ctx;
 
 typedef struct {
   int32_t dim;             /* 2 or 3 */
-  int32_t geometry;        /* MPSPH_BOX | MPSPH_ANNULUS | MPSPH_BALL */
+  int32_t geometry;        /* MPSPH_PERIODIC ... MPSPH_LEVELSET */
   double lo[3], hi[3];     /* box, or bounding box of the annulus / ball, domain units */
   double centre[3];        /* annulus / ball centre */
   double r_in, r_out;      /* annulus radii; ball radius is r_out */
-  int32_t field;           /* MPSPH_UNIFORM ... MPSPH_RBF_EXP */
+  int32_t field;           /* MPSPH_UNIFORM ... MPSPH_GRID */
   double s0;               /* field scale; <= 0: normalise so that the integral of rho_t is n */
   double fcentre[3];
   double fa, fb;           /* slope and reference radius of the radial fields */
@@ -149,6 +149,42 @@ typedef struct {
  * (total mass of Eq. 4 with unit particle mass, used to fix the field constant).  Host-only
  * quadrature; params->s0 is ignored.  Errors: MPSPH_E_INVALID for bad params or n <= 0. */
 MPSPH_API int mpsph_field_scale(const mpsph_params *params, int64_t n, double *s0_out);
+
+/* Particle budget of a region whose boundary features carry their own particles (§2.3, Eq. 4-6,
+ * with unit particle mass, Eq. 15, so that the particle count equals the total mass M_t).
+ *
+ * The boundary mass of Eq. 6 is read with the density of the boundary's own dimension at the
+ * local target size: a feature surface carries s^-(dim-1) particles per unit area, a feature curve
+ * s^-1 per unit length, and a singularity (a box corner) one particle.  The field scale s0 then
+ * solves  n = s0^-dim I_v + s0^-(dim-1) I_s + s0^-1 I_c + N_sing  (I_* the integrals at s0 = 1).
+ *
+ * Features, in this order (each with its mass at s0, its rounded particle count and the type
+ * its particles carry):
+ *   box, dim 3: 6 faces, face 2a + h lying on coordinate a = (h ? hi : lo) (MPSPH_SURFACE);
+ *               then 12 edges, edge 4a + hb + 2 hc running along axis a with the lower-numbered
+ *               other axis b at (hb ? hi : lo) and the higher-numbered one c at (hc ? hi : lo)
+ *               (MPSPH_CURVE); then 8 corners, corner c having coordinate a at hi when bit a of c
+ *               is set (MPSPH_FIXED);
+ *   box, dim 2: 4 sides, side 2a + h on coordinate a = (h ? hi : lo) (MPSPH_SURFACE), then the 4
+ *               corners numbered as in 3D (MPSPH_FIXED);
+ *   ball:       its sphere (dim 3) or circle (dim 2); annulus: the inner, then the outer circle;
+ *   periodic:   none.
+ * The remaining particles are the interior (MPSPH_NORMAL) ones.  Host-only FP64 quadrature
+ * (composite Gauss-Legendre); params->s0 is ignored.  Errors: MPSPH_E_INVALID for bad params,
+ * or a count that leaves no interior particle; MPSPH_E_UNSUPPORTED for a level-set region (its
+ * zero level is not reconstructed as a surface). */
+#define MPSPH_MAX_FEATURES 26
+enum { MPSPH_NORMAL = 0, MPSPH_SURFACE = 1, MPSPH_CURVE = 2, MPSPH_FIXED = 3 };
+typedef struct {
+  double s0;                       /* field scale with the boundary mass included */
+  double mass_volume;              /* s0^-dim I_v */
+  int64_t n_volume;                /* interior particles: n minus every feature count */
+  int32_t n_features;
+  int32_t type[MPSPH_MAX_FEATURES];
+  double mass[MPSPH_MAX_FEATURES]; /* per feature at s0 (1 for a corner) */
+  int64_t count[MPSPH_MAX_FEATURES]; /* rounded mass */
+} mpsph_features_t;
+MPSPH_API int mpsph_feature_budget(const mpsph_params *params, int64_t n, mpsph_features_t *out);
 
 /* Device bytes a context for n particles needs (state, sort buffers, cell table, partials). */
 MPSPH_API size_t mpsph_workspace_bytes(const mpsph_params *params, int64_t n);

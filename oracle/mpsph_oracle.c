@@ -242,6 +242,106 @@ double orc_field_integral(const orc_params *p, int32_t nq) {
 }
 
 /* ------------------------------------------------------------------------------------
+ * Boundary mass (§2.3, Eq. 5-6, unit particle mass Eq. 15).  Reading: the integrand of Eq. 6
+ * is the density of the feature's own dimension at the local target size, s^-(dim-1) on a
+ * feature surface and s^-1 on a feature curve; a singularity (a box corner) holds one particle.
+ * Midpoint rule with nq intervals per parameter; the sphere is parametrised by (z, phi), whose
+ * area element R dz dphi is constant.  Features in the order of the public header.
+ * ------------------------------------------------------------------------------------ */
+
+/* integral of s^-k over the segment from a along the vector e (midpoint rule) */
+static double segment_integral(const orc_params *p, const double *a, const double *e, int k, int nq) {
+  double len = 0.0, total = 0.0;
+  for (int c = 0; c < p->dim; ++c) len += e[c] * e[c];
+  len = sqrt(len);
+  for (int i = 0; i < nq; ++i) {
+    double t = (i + 0.5) / nq, x[3] = {0, 0, 0};
+    for (int c = 0; c < p->dim; ++c) x[c] = a[c] + t * e[c];
+    total += pow(orc_spacing(p, x), -k);
+  }
+  return total * len / nq;
+}
+
+/* integral of s^-2 over the face of the 3D box with coordinate `axis` fixed at `at` */
+static double face_integral(const orc_params *p, int axis, double at, int nq) {
+  int b = axis == 0 ? 1 : 0, c = axis == 2 ? 1 : 2;
+  double db = (p->hi[b] - p->lo[b]) / nq, dc = (p->hi[c] - p->lo[c]) / nq, total = 0.0;
+#pragma omp parallel for reduction(+ : total) schedule(static)
+  for (int i = 0; i < nq; ++i)
+    for (int j = 0; j < nq; ++j) {
+      double x[3];
+      x[axis] = at;
+      x[b] = p->lo[b] + (i + 0.5) * db;
+      x[c] = p->lo[c] + (j + 0.5) * dc;
+      total += pow(orc_spacing(p, x), -2.0);
+    }
+  return total * db * dc;
+}
+
+/* integral of s^-(dim-1) over the sphere (circle) of radius R about the region centre */
+static double round_integral(const orc_params *p, double R, int nq) {
+  double total = 0.0;
+  if (p->dim == 2) {
+    for (int i = 0; i < nq; ++i) {
+      double th = (i + 0.5) * 2.0 * PI / nq;
+      double x[3] = {p->centre[0] + R * cos(th), p->centre[1] + R * sin(th), 0.0};
+      total += pow(orc_spacing(p, x), -1.0);
+    }
+    return total * R * 2.0 * PI / nq;
+  }
+#pragma omp parallel for reduction(+ : total) schedule(static)
+  for (int i = 0; i < nq; ++i)
+    for (int j = 0; j < 2 * nq; ++j) {
+      double z = -1.0 + (i + 0.5) * 2.0 / nq, ph = (j + 0.5) * PI / nq;
+      double rho = sqrt(1.0 - z * z);
+      double x[3] = {p->centre[0] + R * rho * cos(ph), p->centre[1] + R * rho * sin(ph), p->centre[2] + R * z};
+      total += pow(orc_spacing(p, x), -2.0);
+    }
+  return total * R * R * (2.0 / nq) * (PI / nq);
+}
+
+int32_t orc_features(const orc_params *p, int32_t nq, double *I, int32_t *type, int32_t *power) {
+  int d = p->dim, m = 0;
+  if (p->geometry == ORC_PERIODIC || p->geometry == ORC_LEVELSET) return 0;
+  if (p->geometry == ORC_BALL || p->geometry == ORC_ANNULUS) {
+    if (p->geometry == ORC_ANNULUS) {
+      I[m] = round_integral(p, p->r_in, nq); type[m] = ORC_SURFACE; power[m++] = d - 1;
+    }
+    I[m] = round_integral(p, p->r_out, nq); type[m] = ORC_SURFACE; power[m++] = d - 1;
+    return m;
+  }
+  if (d == 2) {
+    for (int a = 0; a < 2; ++a)
+      for (int side = 0; side < 2; ++side) {
+        double x0[3] = {p->lo[0], p->lo[1], 0.0}, e[3] = {0, 0, 0};
+        x0[a] = side ? p->hi[a] : p->lo[a];
+        e[1 - a] = p->hi[1 - a] - p->lo[1 - a];
+        I[m] = segment_integral(p, x0, e, 1, nq); type[m] = ORC_SURFACE; power[m++] = 1;
+      }
+  } else {
+    for (int a = 0; a < 3; ++a)
+      for (int side = 0; side < 2; ++side) {
+        I[m] = face_integral(p, a, side ? p->hi[a] : p->lo[a], nq); type[m] = ORC_SURFACE; power[m++] = 2;
+      }
+    for (int a = 0; a < 3; ++a) {
+      int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+      for (int k = 0; k < 4; ++k) {
+        double x0[3], e[3] = {0, 0, 0};
+        x0[a] = p->lo[a];
+        x0[b] = (k & 1) ? p->hi[b] : p->lo[b];
+        x0[c] = (k & 2) ? p->hi[c] : p->lo[c];
+        e[a] = p->hi[a] - p->lo[a];
+        I[m] = segment_integral(p, x0, e, 1, 64 * nq); type[m] = ORC_CURVE; power[m++] = 1;
+      }
+    }
+  }
+  for (int c = 0; c < (1 << d); ++c) {
+    I[m] = 1.0; type[m] = ORC_FIXED; power[m++] = 0;
+  }
+  return m;
+}
+
+/* ------------------------------------------------------------------------------------
  * Neighbour candidates.  A plain uniform grid over the bounding box of the particles with
  * cells of side kappa * min(h); a particle visits every cell of the cube that covers its
  * largest possible interaction radius, skipping a cell only when the nearest point of the

@@ -74,6 +74,11 @@ double orc_spacing(const orc_params *p, const double *x);
 double orc_level_set(const orc_params *p, const double *x);
 int orc_field(const orc_params *p, int64_t n, const double *x, double *rho_t, double *h);
 double orc_field_integral(const orc_params *p, int32_t nq);
+/* Boundary features of the region (§2.3, Eq. 6), in the order of the public header: for each,
+ * the integral of s^-power over it with the current s0 (power dim-1 on a surface, 1 on a curve,
+ * 0 and integral 1 at a corner) and the particle type it carries.  Returns the feature count
+ * (at most 26; 0 for a periodic box or a level set).  Midpoint rule, nq intervals per axis. */
+int32_t orc_features(const orc_params *p, int32_t nq, double *I, int32_t *type, int32_t *power);
 int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, int32_t *type,
              int64_t step, orc_out *out);
 int orc_pairs(const orc_params *p, int64_t n, const double *x, int64_t cap,

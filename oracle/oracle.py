@@ -191,6 +191,51 @@ def normalised_s0(op: OracleParams, n: int, nq: int | None = None) -> float:
     return (integral / n) ** (1.0 / op.dim)
 
 
+def features(op: OracleParams, nq: int = 1024):
+    """Boundary features of the region (Eq. 6 with the reading of orc_features): arrays of the
+    integral of s^-power over each feature at the current s0, its particle type and its power."""
+    I = np.zeros(26)
+    typ = np.zeros(26, dtype=np.int32)
+    pw = np.zeros(26, dtype=np.int32)
+    lib().orc_features.restype = C.c_int32
+    lib().orc_features.argtypes = [C.POINTER(Params), C.c_int32, _DP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    m = lib().orc_features(C.byref(op.p), int(nq), _dp(I), typ.ctypes.data_as(C.POINTER(C.c_int32)),
+                           pw.ctypes.data_as(C.POINTER(C.c_int32)))
+    return I[:m], typ[:m], pw[:m]
+
+
+def feature_budget(op: OracleParams, n: int, nq: int = 1024, nq_volume: int | None = None) -> dict:
+    """Particle budget with the boundary features seeded explicitly: with unit particle mass
+    (Eq. 15) the count is the total mass M_v + M_s (Eq. 4-6), so u = 1/s0 solves
+    n = sum over terms of I u^power (volume: power dim).  Solved by bisection on u."""
+    saved = op.p.s0
+    op.p.s0 = 1.0
+    if nq_volume is None:
+        nq_volume = 4096 if op.dim == 2 else 400
+    Iv = field_integral(op, nq_volume)
+    I, typ, pw = features(op, nq)
+    op.p.s0 = saved
+    d = op.dim
+
+    def total(u):
+        return Iv * u ** d + float(np.sum(I * u ** pw.astype(np.float64)))
+
+    lo_u, hi_u = 0.0, 1.0
+    while total(hi_u) < n:
+        hi_u *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo_u + hi_u)
+        if total(mid) < n:
+            lo_u = mid
+        else:
+            hi_u = mid
+    u = 0.5 * (lo_u + hi_u)
+    mass = I * u ** pw.astype(np.float64)
+    count = np.where(pw == 0, 1, np.rint(mass)).astype(np.int64)
+    return {"s0": 1.0 / u, "mass_volume": Iv * u ** d, "n_volume": int(n - count.sum()), "type": typ,
+            "mass": mass, "count": count, "power": pw}
+
+
 def kernel_w(r: float, h: float, dim: int) -> float:
     return lib().orc_kernel_w(r, h, dim)
 

@@ -958,6 +958,148 @@ double field_integral_unit(const mpsph_params *p) {
   return total;
 }
 
+// Boundary features of a region (the order the header documents) with the integral, at s0 = 1,
+// of s^-k over each: k = dim - 1 on a feature surface, 1 on a feature curve, 0 at a corner.
+struct FeatureList {
+  int n = 0;
+  int type[MPSPH_MAX_FEATURES];
+  int power[MPSPH_MAX_FEATURES];
+  double I[MPSPH_MAX_FEATURES];
+  void add(int t, int k, double v) {
+    type[n] = t;
+    power[n] = k;
+    I[n] = v;
+    ++n;
+  }
+};
+
+// Panels per axis of the composite rule along box axis a: one per background-mesh cell for a
+// gridded field (the interpolant is smooth inside a cell), else the given count.
+int feature_panels(const mpsph_params *p, int a, int dflt) {
+  return p->field == MPSPH_GRID ? std::max(p->grid_n[a] - 1, 1) : dflt;
+}
+
+// Integral of s^-k over the parallelogram o + u e1 + v e2 (u, v in [0,1]; e2 = 0 for a segment)
+// with m1 x m2 panels of the 8-point Gauss-Legendre rule, s0 = 1.
+double flat_integral(const mpsph_params *p, const double *o, const double *e1, const double *e2, int k, int m1,
+                     int m2) {
+  double xg[8], wg[8];
+  gauss8(xg, wg);
+  const int d = p->dim;
+  double l1 = 0, l2 = 0;
+  for (int a = 0; a < d; ++a) {
+    l1 += e1[a] * e1[a];
+    l2 += e2[a] * e2[a];
+  }
+  const bool seg = l2 == 0.0;
+  const double meas = seg ? std::sqrt(l1) : std::sqrt(l1) * std::sqrt(l2);  // e1, e2 orthogonal
+  if (!seg && m2 < 1) m2 = 1;
+  const int n2 = seg ? 1 : 8 * m2;
+  double total = 0.0;
+  for (int i = 0; i < 8 * m1; ++i) {
+    const double u = ((i >> 3) + xg[i & 7]) / m1, wu = wg[i & 7] / m1;
+    double acc = 0.0;
+    for (int j = 0; j < n2; ++j) {
+      const double v = seg ? 0.0 : ((j >> 3) + xg[j & 7]) / m2, wv = seg ? 1.0 : wg[j & 7] / m2;
+      double x[3] = {0, 0, 0};
+      for (int a = 0; a < d; ++a) x[a] = o[a] + u * e1[a] + v * e2[a];
+      acc += wv * std::pow(host_spacing(p, 1.0, x), -(double)k);
+    }
+    total += wu * acc;
+  }
+  return total * meas;
+}
+
+// Integral of s^-k over the sphere (dim 3) or circle (dim 2) of radius R about the region's
+// centre, s0 = 1.
+double round_integral(const mpsph_params *p, double R, int k) {
+  double xg[8], wg[8];
+  gauss8(xg, wg);
+  const double pi = 3.14159265358979323846;
+  const double *c = p->centre;
+  double total = 0.0;
+  if (p->dim == 2) {
+    const int M = 256;
+    for (int i = 0; i < 8 * M; ++i) {
+      const double th = ((i >> 3) + xg[i & 7]) * 2 * pi / M, w = wg[i & 7] * 2 * pi / M;
+      const double x[2] = {c[0] + R * std::cos(th), c[1] + R * std::sin(th)};
+      total += w * R * std::pow(host_spacing(p, 1.0, x), -(double)k);
+    }
+    return total;
+  }
+  const int MT = 32, MP = 64;
+  for (int i = 0; i < 8 * MT; ++i) {
+    const double th = ((i >> 3) + xg[i & 7]) * pi / MT, wt = wg[i & 7] * pi / MT;
+    double acc = 0.0;
+    for (int j = 0; j < 8 * MP; ++j) {
+      const double ph = ((j >> 3) + xg[j & 7]) * 2 * pi / MP, wp = wg[j & 7] * 2 * pi / MP;
+      const double x[3] = {c[0] + R * std::sin(th) * std::cos(ph), c[1] + R * std::sin(th) * std::sin(ph),
+                           c[2] + R * std::cos(th)};
+      acc += wp * std::pow(host_spacing(p, 1.0, x), -(double)k);
+    }
+    total += wt * R * R * std::sin(th) * acc;
+  }
+  return total;
+}
+
+// The features of a region and their integrals at s0 = 1 (§2.3, Eq. 6: a surface integral on the
+// feature surfaces and a line integral on the feature curves).
+FeatureList feature_integrals(const mpsph_params *p) {
+  FeatureList f;
+  const int d = p->dim;
+  if (p->geometry == MPSPH_PERIODIC) return f;
+  if (p->geometry == MPSPH_BALL) {
+    f.add(MPSPH_SURFACE, d - 1, round_integral(p, p->r_out, d - 1));
+    return f;
+  }
+  if (p->geometry == MPSPH_ANNULUS) {
+    f.add(MPSPH_SURFACE, 1, round_integral(p, p->r_in, 1));
+    f.add(MPSPH_SURFACE, 1, round_integral(p, p->r_out, 1));
+    return f;
+  }
+  const double *lo = p->lo, *hi = p->hi;
+  auto corner_of = [&](int bits, double *x) {
+    for (int a = 0; a < 3; ++a) x[a] = a < d ? ((bits >> a) & 1 ? hi[a] : lo[a]) : 0.0;
+  };
+  if (d == 2) {
+    for (int a = 0; a < 2; ++a)
+      for (int side = 0; side < 2; ++side) {
+        const int b = 1 - a;
+        double o[3] = {0, 0, 0}, e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+        o[a] = side ? hi[a] : lo[a];
+        o[b] = lo[b];
+        e1[b] = hi[b] - lo[b];
+        f.add(MPSPH_SURFACE, 1, flat_integral(p, o, e1, e2, 1, feature_panels(p, b, 256), 0));
+      }
+    for (int c = 0; c < 4; ++c) f.add(MPSPH_FIXED, 0, 1.0);
+    return f;
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int side = 0; side < 2; ++side) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      double o[3], e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+      corner_of(0, o);
+      o[a] = side ? hi[a] : lo[a];
+      e1[b] = hi[b] - lo[b];
+      e2[c] = hi[c] - lo[c];
+      f.add(MPSPH_SURFACE, 2, flat_integral(p, o, e1, e2, 2, feature_panels(p, b, 32), feature_panels(p, c, 32)));
+    }
+  for (int a = 0; a < 3; ++a) {
+    const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;  // the two other axes, lower first
+    for (int sc = 0; sc < 2; ++sc)
+      for (int sb = 0; sb < 2; ++sb) {
+        double o[3], e1[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+        corner_of(0, o);
+        o[b] = sb ? hi[b] : lo[b];
+        o[c] = sc ? hi[c] : lo[c];
+        e1[a] = hi[a] - lo[a];
+        f.add(MPSPH_CURVE, 1, flat_integral(p, o, e1, e2, 1, feature_panels(p, a, 256), 0));
+      }
+  }
+  for (int c = 0; c < 8; ++c) f.add(MPSPH_FIXED, 0, 1.0);
+  return f;
+}
+
 // Bounds of s over the bounding box, and a Lipschitz constant of s (domain units).
 bool spacing_bounds(const mpsph_params *p, double s0, double *smin, double *smax, double *lip) {
   if (p->field == MPSPH_GRID) {
@@ -2127,6 +2269,51 @@ int mpsph_field_scale(const mpsph_params *params, int64_t n, double *s0_out) {
   if (!(I > 0) || !std::isfinite(I)) return MPSPH_E_INVALID;
   *s0_out = std::pow(I / (double)n, 1.0 / params->dim);
   return MPSPH_OK;
+}
+
+int mpsph_feature_budget(const mpsph_params *params, int64_t n, mpsph_features_t *out) {
+  if (!valid_params(params) || n <= 0 || !out) return MPSPH_E_INVALID;
+  if (params->geometry == MPSPH_LEVELSET) return MPSPH_E_UNSUPPORTED;
+  const int d = params->dim;
+  const double Iv = field_integral_unit(params);
+  if (!(Iv > 0) || !std::isfinite(Iv)) return MPSPH_E_INVALID;
+  const FeatureList f = feature_integrals(params);
+  // n = sum_k c_k u^k with u = 1/s0: the volume term (k = dim) plus every feature's term
+  double coef[4] = {0, 0, 0, 0};
+  coef[d] = Iv;
+  for (int i = 0; i < f.n; ++i) {
+    if (!(f.I[i] > 0) || !std::isfinite(f.I[i])) return MPSPH_E_INVALID;
+    coef[f.power[i]] += f.I[i];
+  }
+  const double target = (double)n - coef[0];
+  if (!(target > 0)) return MPSPH_E_INVALID;
+  // Newton from the volume-only root, which lies at or above the root: the polynomial is convex
+  // and increasing for u > 0, so the iterates decrease monotonically onto it
+  double u = std::pow(target / Iv, 1.0 / d);
+  for (int it = 0; it < 200; ++it) {
+    double g = -target, dg = 0.0;
+    for (int k = 1; k <= d; ++k) {
+      g += coef[k] * std::pow(u, k);
+      dg += k * coef[k] * std::pow(u, k - 1);
+    }
+    const double du = g / dg;
+    u -= du;
+    if (std::fabs(du) <= 1e-15 * u) break;
+  }
+  if (!(u > 0) || !std::isfinite(u)) return MPSPH_E_INVALID;
+  *out = mpsph_features_t{};
+  out->s0 = 1.0 / u;
+  out->mass_volume = Iv * std::pow(u, d);
+  out->n_features = f.n;
+  int64_t used = 0;
+  for (int i = 0; i < f.n; ++i) {
+    out->type[i] = f.type[i];
+    out->mass[i] = f.I[i] * std::pow(u, f.power[i]);
+    out->count[i] = f.power[i] == 0 ? 1 : (int64_t)std::llround(out->mass[i]);
+    used += out->count[i];
+  }
+  out->n_volume = n - used;
+  return out->n_volume >= 0 ? MPSPH_OK : MPSPH_E_INVALID;
 }
 
 size_t mpsph_batch_workspace_bytes(int32_t ndom, const mpsph_params *params, const int64_t *n) {

@@ -55,6 +55,15 @@ class Metrics(C.Structure):
                [(k, C.c_int64) for k in ("interface_particles", "t0")]
 
 
+MAX_FEATURES = 26
+
+
+class Features(C.Structure):
+    _fields_ = [("s0", C.c_double), ("mass_volume", C.c_double), ("n_volume", C.c_int64),
+                ("n_features", C.c_int32), ("type", C.c_int32 * MAX_FEATURES),
+                ("mass", C.c_double * MAX_FEATURES), ("count", C.c_int64 * MAX_FEATURES)]
+
+
 _lib = None
 
 
@@ -69,6 +78,7 @@ def lib():
         P, V, I32, I64 = C.POINTER(Params), C.c_void_p, C.c_int32, C.c_int64
         sig = {
             "mpsph_field_scale": (C.c_int, [P, I64, C.POINTER(C.c_double)]),
+            "mpsph_feature_budget": (C.c_int, [P, I64, C.POINTER(Features)]),
             "mpsph_workspace_bytes": (C.c_size_t, [P, I64]),
             "mpsph_batch_workspace_bytes": (C.c_size_t, [I32, P, C.POINTER(I64)]),
             "mpsph_create": (C.c_int, [P, I64, V, C.c_size_t, V, C.POINTER(V)]),
@@ -169,6 +179,18 @@ def field_scale(spec: dict, n: int) -> float:
     out = C.c_double(0.0)
     _check(lib().mpsph_field_scale(C.byref(p), int(n), C.byref(out)), "mpsph_field_scale")
     return out.value
+
+
+def feature_budget(spec: dict, n: int) -> dict:
+    """Particle budget with the boundary features seeded explicitly (mpsph_feature_budget):
+    s0, the interior count and, per feature in the library's order, type, mass and count."""
+    p, keep = make_params(spec)
+    out = Features()
+    _check(lib().mpsph_feature_budget(C.byref(p), int(n), C.byref(out)), "mpsph_feature_budget")
+    k = out.n_features
+    return {"s0": out.s0, "mass_volume": out.mass_volume, "n_volume": int(out.n_volume),
+            "type": np.array(out.type[:k], dtype=np.int32), "mass": np.array(out.mass[:k]),
+            "count": np.array(out.count[:k], dtype=np.int64)}
 
 
 class Relaxer:

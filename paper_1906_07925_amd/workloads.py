@@ -203,6 +203,63 @@ def initial_state(spec: dict, seed: int, init: str, n_colours: int, per_axis: in
     return x, col.astype(np.int32), typ
 
 
+def _sphere_points(m: int, dim: int, rng: np.random.Generator) -> np.ndarray:
+    """m directions uniform on the unit sphere (circle)."""
+    v = rng.normal(size=(m, dim))
+    return v / np.linalg.norm(v, axis=1)[:, None]
+
+
+def feature_points(spec: dict, k: int, m: int, rng: np.random.Generator) -> np.ndarray:
+    """m points uniform (by measure) on boundary feature k of the region, features numbered as
+    the library's particle budget numbers them (box: faces or sides 2a + h, then in 3D edges
+    4a + hb + 2hc, then corners; ball: its sphere; annulus: inner, then outer circle)."""
+    d = spec["dim"]
+    g = spec["geometry"]
+    if g in ("ball", "annulus"):
+        c = np.asarray(spec["centre"], dtype=np.float64)
+        r = spec["r_in"] if (g == "annulus" and k == 0) else spec["r_out"]
+        return c + r * _sphere_points(m, d, rng)
+    lo = np.asarray(spec["lo"], dtype=np.float64)
+    hi = np.asarray(spec["hi"], dtype=np.float64)
+    n_faces = 2 * d
+    n_edges = 12 if d == 3 else 0
+    x = rng.uniform(lo, hi, size=(m, d))
+    if k < n_faces:
+        a, h = divmod(k, 2)
+        x[:, a] = hi[a] if h else lo[a]
+        return x
+    if k < n_faces + n_edges:
+        a, bits = divmod(k - n_faces, 4)
+        b, c = (1, 2) if a == 0 else ((0, 2) if a == 1 else (0, 1))
+        x[:, b] = hi[b] if bits & 1 else lo[b]
+        x[:, c] = hi[c] if bits & 2 else lo[c]
+        return x
+    bits = k - n_faces - n_edges
+    return np.tile(np.where([(bits >> a) & 1 for a in range(d)], hi, lo), (m, 1))
+
+
+def feature_seeded(spec: dict, budget: dict, seed: int, n_colours: int):
+    """Initial set with the boundary features seeded explicitly (§3.5): budget['count'][k]
+    particles of type budget['type'][k] uniform on feature k, and budget['n_volume'] normal
+    particles uniform in the interior; colours from the nearest of n_colours seeds.  The
+    budget comes from either side's particle-budget routine.  Returns (x, colour, type)."""
+    rng = _rng(seed)
+    xs, ts = [], []
+    for k, (cnt, typ) in enumerate(zip(budget["count"], budget["type"])):
+        if cnt > 0:
+            xs.append(feature_points(spec, k, int(cnt), rng))
+            ts.append(np.full(int(cnt), int(typ), dtype=np.int32))
+    nv = int(budget["n_volume"])
+    xs.append(_uniform_points(spec, nv, rng))
+    ts.append(np.zeros(nv, dtype=np.int32))
+    x = np.concatenate(xs)
+    typ = np.concatenate(ts)
+    perm = rng.permutation(x.shape[0])
+    x, typ = x[perm], typ[perm]
+    seeds = _uniform_points(spec, n_colours, rng)
+    return x, nearest_seed(x, seeds).astype(np.int32), typ
+
+
 # ---------------------------------------------------------------------------------------
 # The five configurations
 # ---------------------------------------------------------------------------------------
