@@ -121,6 +121,14 @@ typedef struct {
   const double *grid_phi;  /* host, prod(grid_n[0..dim)) level-set values (MPSPH_LEVELSET), domain
                               units, positive inside; node (i, j, k) at i + n0 (j + n1 k); copied */
   const double *grid_s;    /* host, node values g of the MPSPH_GRID field (> 0); copied */
+  int32_t seeded;          /* 0: a normal particle leaving the region is projected onto the
+                              boundary and becomes a feature particle (the feature mapping of
+                              Alg. 1); a surface particle reaching a box edge becomes a curve
+                              particle.  1: the features were seeded with the counts of
+                              mpsph_feature_budget: types never change; a normal particle leaving
+                              the region is reflected back into it (mirror image through the
+                              boundary) and a feature particle stays on its feature, reflected at
+                              the walls that bound it */
 } mpsph_params;
 
 typedef struct {
@@ -315,7 +323,7 @@ MPSPH_API int mpsph_set_field_coeff(mpsph_ctx *ctx, int32_t domain, const double
  * float32, load order, domain units).  Debug exports after the call refer to a recomputed
  * step, not to the last one.  Single-domain contexts with a box region and a uniform or RBF
  * field.  Synchronises.  Errors: MPSPH_E_INVALID (nsteps < 0, ckpt_every < 1), MPSPH_E_STATE,
- * MPSPH_E_UNSUPPORTED (batched context, other region or field), MPSPH_E_NOMEM. */
+ * MPSPH_E_UNSUPPORTED (batched context, other region or field, seeded features), MPSPH_E_NOMEM. */
 MPSPH_API int mpsph_grad(mpsph_ctx *ctx, int32_t nsteps, int32_t ckpt_every, double lambda, double *loss_out,
                          double *grad_coeff_out, float *d_grad_pos);
 

@@ -553,6 +553,44 @@ static void project_position(const orc_params *p, double *xi, int32_t *type) {
     }
     return;
   }
+  if (p->seeded) {
+    /* Features seeded explicitly with the counts of the boundary mass (Eq. 6): no particle
+     * changes type.  Reading: a normal particle that left the region is reflected back into it
+     * (mirror image through the boundary), a feature particle stays on its feature (Eq. 32)
+     * and is reflected at the walls that bound its feature. */
+    if (p->geometry == ORC_BOX) {
+      for (int a = 0; a < d; ++a) {
+        if (xi[a] < p->lo[a]) xi[a] = fmin(2.0 * p->lo[a] - xi[a], p->hi[a]);
+        if (xi[a] > p->hi[a]) xi[a] = fmax(2.0 * p->hi[a] - xi[a], p->lo[a]);
+      }
+      return;
+    }
+    if (p->geometry == ORC_LEVELSET) {
+      double g[3], gn = 0.0;
+      double phi = orc_grid_interp(p, p->grid_phi, xi, g);
+      if (*type == ORC_NORMAL && !(phi < 0.0)) return;
+      for (int a = 0; a < d; ++a) gn += g[a] * g[a];
+      gn = sqrt(gn);
+      double f = *type == ORC_NORMAL ? 2.0 : 1.0;
+      if (gn > 0.0)
+        for (int a = 0; a < d; ++a) xi[a] -= f * phi * g[a] / gn;
+      return;
+    }
+    double r = dist_to(xi, p->centre, d), phi = orc_level_set(p, xi), rt;
+    if (!(r > 0.0)) return;
+    if (*type == ORC_NORMAL) {
+      if (!(phi < 0.0)) return;
+      if (r > p->r_out)
+        rt = 2.0 * p->r_out - r;
+      else
+        rt = 2.0 * p->r_in - r;
+    } else {
+      rt = p->r_out;
+      if (p->geometry == ORC_ANNULUS && (r - p->r_in) < (p->r_out - r)) rt = p->r_in;
+    }
+    for (int a = 0; a < d; ++a) xi[a] = p->centre[a] + rt * (xi[a] - p->centre[a]) / r;
+    return;
+  }
   if (p->geometry == ORC_BOX) {
     int nf = 0;
     for (int a = 0; a < d; ++a) {
@@ -725,16 +763,27 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
         rc = ORC_E_NOMEM;
         continue;
       }
-      double ai[3] = {0, 0, 0}, A = 0.0, K = 0.0;
+      double ai[3] = {0, 0, 0}, A = 0.0, K = 0.0, Pr = 0.0;
       for (int64_t k = 0; k < cand.n; ++k) {
         int64_t j = cand.j[k];
         double e[3];
         double r = separation(p, x, i, j, e);
         double hij = 0.5 * (h[i] + h[j]);
         if (!(r < kap * hij) || !feels(type[i], type[j]) || r == 0.0) continue;
+        double inv2 = 1.0 / (rho_t[i] * rho_t[i]) + 1.0 / (rho_t[j] * rho_t[j]);
+        double gij = inv2 * orc_kernel_dw(r, hij, d) / r;
+        if (out->at_prop) {
+          /* conditioning diagnostic only; it does not enter the result */
+          double dvi = type[i] == ORC_FIXED ? 0.0 : 0.5 * dt1 * aabs[i];
+          double dvj = type[j] == ORC_FIXED ? 0.0 : 0.5 * dt1 * aabs[j];
+          double dH = 2.0 * (rho_t[i] * p->nu_coeff * kap * h[i] * dvi + rho_t[j] * p->nu_coeff * kap * h[j] * dvj);
+          double dv = 0.0;
+          for (int c = 0; c < d; ++c) dv += (vt[i * d + c] - vt[j * d + c]) * (vt[i * d + c] - vt[j * d + c]);
+          double H = eta[i] + eta[j] > 0.0 ? 2.0 * eta[i] * eta[j] / (eta[i] + eta[j]) : 0.0;
+          Pr += fabs(gij) * (dH * sqrt(dv) + H * (dvi + dvj));
+        }
         if (eta[i] + eta[j] == 0.0) continue;
         double etaij = 2.0 * eta[i] * eta[j] / (eta[i] + eta[j]);
-        double inv2 = 1.0 / (rho_t[i] * rho_t[i]) + 1.0 / (rho_t[j] * rho_t[j]);
         double s = etaij * inv2 * orc_kernel_dw(r, hij, d) / r;
         double mag = 0.0;
         for (int c = 0; c < d; ++c) {
@@ -748,6 +797,7 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
       for (int c = 0; c < d; ++c) at[i * d + c] = ai[c];
       atabs[i] = A;
       if (out->at_kabs) out->at_kabs[i] = K;
+      if (out->at_prop) out->at_prop[i] = Pr;
     }
     free(cand.j);
   }

@@ -42,7 +42,9 @@ typedef struct {
   int64_t t0, t1;       /* surface-tension ramp (step index); t0 < 0: sigma constant */
   double nu_coeff, c_acc, c_vel, c_visc;
   int32_t search;       /* 0: cell grid, 1: brute force over all pairs */
-  int32_t pad_;
+  int32_t seeded;       /* 1: the boundary features were seeded explicitly; particles keep
+                           their type and are reflected back into the region or onto their
+                           feature (see project_position) */
   /* Cartesian background mesh (§3.1-3.2): grid_n[a] nodes per axis spanning [lo, hi], node
    * (i, j, k) at index i + n0 (j + n1 k); values interpolated multilinearly. */
   int32_t grid_n[3];
@@ -57,6 +59,14 @@ typedef struct {
   /* conditioning diagnostics: sum over pair terms of |term| (1 + 3 q / (2 - q)), q = r/h_ij,
    * the relative sensitivity of a kernel-derivative term to a relative change of r */
   double *a_kabs, *at_kabs;
+  /* error of the viscous acceleration propagated from a relative error of one unit in every
+   * |a_j| term sum: v~ = a dt1 / 2 carries it into the velocity differences and through
+   * |v~| into the viscosities of Eq. 21-22; per particle
+   *   sum_j |g_ij| (dH_ij |v~_i - v~_j| + H_ij (dv_i + dv_j)),  dv_k = dt1 A_k / 2,
+   *   dH_ij = 2 (c_i dv_i + c_j dv_j),  c_k = rho_t,k nu_coeff kappa h_k,
+   * with A_k the sum of |pair terms| of a_k, H_ij the harmonic-mean viscosity and g_ij the
+   * rest of the pair coefficient */
+  double *at_prop;
   /* scalars of the step */
   double dt1, dt2, sigma, residual_l2, residual_linf, kinetic;
   double elr_mean, elr_std, elr_min, elr_max;

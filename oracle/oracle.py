@@ -46,7 +46,7 @@ class Params(C.Structure):
         ("tau", C.c_double), ("kappa", C.c_double), ("p0", C.c_double), ("sigma0", C.c_double),
         ("t0", C.c_int64), ("t1", C.c_int64),
         ("nu_coeff", C.c_double), ("c_acc", C.c_double), ("c_vel", C.c_double),
-        ("c_visc", C.c_double), ("search", C.c_int32), ("pad_", C.c_int32),
+        ("c_visc", C.c_double), ("search", C.c_int32), ("seeded", C.c_int32),
         ("grid_n", C.c_int32 * 3), ("pad2_", C.c_int32),
         ("grid_phi", C.POINTER(C.c_double)), ("grid_s", C.POINTER(C.c_double)),
     ]
@@ -57,7 +57,7 @@ _DP = C.POINTER(C.c_double)
 
 class Out(C.Structure):
     _fields_ = [(k, _DP) for k in ("rho", "rho_t", "h", "a", "a_abs", "vt", "at", "at_abs", "v",
-                                   "dr", "nn", "a_kabs", "at_kabs")] + [
+                                   "dr", "nn", "a_kabs", "at_kabs", "at_prop")] + [
         (k, C.c_double) for k in ("dt1", "dt2", "sigma", "residual_l2", "residual_linf", "kinetic",
                                   "elr_mean", "elr_std", "elr_min", "elr_max")] + [
         (k, C.c_int64) for k in ("pairs", "interface_pairs", "band_pairs", "n_normal", "n_elr",
@@ -137,6 +137,7 @@ class OracleParams:
         p.c_vel = spec.get("c_vel", 1.0 / 40.0)
         p.c_visc = spec.get("c_visc", 0.125)
         p.search = 1 if search == "brute" else 0
+        p.seeded = 1 if spec.get("seeded") else 0
         # background mesh: node values, x index fastest
         gn = spec.get("grid_n", (2, 2, 2))
         for a in range(3):
@@ -265,7 +266,7 @@ def level_set(op: OracleParams, x: np.ndarray) -> np.ndarray:
 
 def step(op: OracleParams, x: np.ndarray, colour: np.ndarray, ptype: np.ndarray, step_index: int,
          want: tuple = ("rho", "rho_t", "h", "a", "a_abs", "vt", "at", "at_abs", "v", "dr", "nn", "a_kabs",
-                        "at_kabs")):
+                        "at_kabs", "at_prop")):
     """Run one step.  Returns (new_x, new_type, result dict)."""
     x = np.array(x, dtype=np.float64, order="C", copy=True)
     n, d = x.shape
@@ -273,7 +274,7 @@ def step(op: OracleParams, x: np.ndarray, colour: np.ndarray, ptype: np.ndarray,
     typ = np.array(ptype, dtype=np.int32, order="C", copy=True)
     out = Out()
     arrays = {}
-    for k in ("rho", "rho_t", "h", "a_abs", "at_abs", "nn", "a_kabs", "at_kabs"):
+    for k in ("rho", "rho_t", "h", "a_abs", "at_abs", "nn", "a_kabs", "at_kabs", "at_prop"):
         if k in want:
             arrays[k] = np.zeros(n)
     for k in ("a", "vt", "at", "v", "dr"):
@@ -286,7 +287,7 @@ def step(op: OracleParams, x: np.ndarray, colour: np.ndarray, ptype: np.ndarray,
     if rc != 0:
         raise RuntimeError(f"orc_step failed with code {rc}")
     res = dict(arrays)
-    for k, _ in Out._fields_[13:]:
+    for k, _ in Out._fields_[14:]:
         res[k] = getattr(out, k)
     return x, typ, res
 

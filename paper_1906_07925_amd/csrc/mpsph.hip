@@ -304,6 +304,30 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
 
 
 // Box type from the number of faces a particle lies on.
+// Mirror image through the lower wall (X = c + o < 0  ->  -X), in (cell, offset) form.
+__device__ __forceinline__ void mirror_low(int &c, float &o) {
+  int cn = -c - 1;
+  float on = 1.f - o;
+  if (on >= 1.f) {
+    on = 0.f;
+    cn += 1;
+  }
+  c = cn;
+  o = on;
+}
+
+// Mirror image through the upper wall W = wc + wo (X = c + o > W  ->  2 W - X).
+__device__ __forceinline__ void mirror_high(int &c, float &o, int wc, float wo) {
+  const float x = wo - ((float)(c - wc) + (o - wo));
+  const float fl = floorf(x);
+  c = wc + (int)fl;
+  o = x - fl;
+  if (o >= 1.f) {
+    o = 0.f;
+    c += 1;
+  }
+}
+
 __device__ __forceinline__ int type_from_faces(int nf, int d) {
   return nf <= 0 ? 0 : (nf == 1 ? 1 : (nf == 2 ? (d == 3 ? 2 : 3) : 3));
 }
@@ -419,6 +443,25 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
           // periodic box: wrap into [0, P)
 #pragma unroll
           for (int a = 0; a < D; ++a) c[a] = ((c[a] % (g.gmax + 1)) + (g.gmax + 1)) % (g.gmax + 1);
+        } else if (g.geometry == 1 && g.seeded) {
+          // box with seeded features: a coordinate that left the box is mirrored at the wall it
+          // crossed; types never change
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (c[a] < 0) {
+              mirror_low(c[a], o[a]);
+              if (c[a] > g.whi_c[a] || (c[a] == g.whi_c[a] && o[a] > g.whi_o[a])) {
+                c[a] = g.whi_c[a];
+                o[a] = g.whi_o[a];
+              }
+            } else if (c[a] > g.whi_c[a] || (c[a] == g.whi_c[a] && o[a] > g.whi_o[a])) {
+              mirror_high(c[a], o[a], g.whi_c[a], g.whi_o[a]);
+              if (c[a] < 0) {
+                c[a] = 0;
+                o[a] = 0.f;
+              }
+            }
+          }
         } else if (g.geometry == 1) {
           // box: closest-point projection is a clamp to the walls; type from the faces touched
           int nf = 0;
@@ -443,7 +486,8 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
           if (ti != 0 || phi < 0.f) {
             const float gn2 = gr[0] * gr[0] + gr[1] * gr[1] + (D == 3 ? gr[2] * gr[2] : 0.f);
             if (gn2 > 0.f) {
-              const float sc = phi * fast_rsq(gn2);
+              // seeded features: a normal particle is mirrored through the zero level instead
+              const float sc = (g.seeded && ti == 0 ? 2.f : 1.f) * phi * fast_rsq(gn2);
 #pragma unroll
               for (int a = 0; a < D; ++a) {
                 const float x = o[a] - sc * gr[a];
@@ -456,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
                 }
               }
             }
-            ti = max(ti, 1);
+            if (!g.seeded) ti = max(ti, 1);
           }
         } else {
           // annulus / ball: radial projection onto the nearest boundary circle / sphere
@@ -468,9 +512,11 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
           }
           const float rr = sqrtf(r2);
           const float phi = g.geometry == 2 ? fminf(rr - g.r_in, g.r_out - rr) : g.r_out - rr;
-          if (ti != 0 || phi < 0.f) {
+          if ((ti != 0 || phi < 0.f) && rr > 0.f) {
             float rb = g.r_out;
             if (g.geometry == 2 && (rr - g.r_in) < (g.r_out - rr)) rb = g.r_in;
+            // seeded features: a normal particle is mirrored through the circle / sphere it crossed
+            if (g.seeded && ti == 0) rb = rr > g.r_out ? 2.f * g.r_out - rr : 2.f * g.r_in - rr;
             const float sc = rb / rr;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
@@ -484,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
                 c[a] += 1;
               }
             }
-            ti = max(ti, 1);
+            if (!g.seeded) ti = max(ti, 1);
           }
         }
       }
@@ -1573,6 +1619,7 @@ DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, con
   }
   g.r_in = (float)(p.r_in * ics);
   g.r_out = (float)(p.r_out * ics);
+  g.seeded = p.seeded ? 1 : 0;
   // background mesh: node spacing (hi - lo) / (n - 1) in cell units
   for (int a = 0; a < 3; ++a) {
     const int na = a < D ? std::max(p.grid_n[a], 2) : 2;
@@ -2664,7 +2711,7 @@ int mpsph_grad(mpsph_ctx *ctx, int32_t nsteps, int32_t ckpt_every, double lambda
   if (!ctx || nsteps < 0 || ckpt_every < 1 || !std::isfinite(lambda)) return MPSPH_E_INVALID;
   if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
   const Domain &dm = ctx->dom[0];
-  if (ctx->L.ndom != 1 || dm.p.geometry != MPSPH_BOX || dm.p.t0 == -2 ||
+  if (ctx->L.ndom != 1 || dm.p.geometry != MPSPH_BOX || dm.p.t0 == -2 || dm.p.seeded ||
       (dm.p.field != MPSPH_RBF_EXP && dm.p.field != MPSPH_UNIFORM))
     return MPSPH_E_UNSUPPORTED;
   return dm.p.dim == 2 ? grad_run<2>(ctx, nsteps, ckpt_every, lambda, loss_out, grad_coeff_out, d_grad_pos)

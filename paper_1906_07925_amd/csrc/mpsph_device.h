@@ -48,6 +48,7 @@ struct GridDev {
   const float *phi;  // MPSPH_LEVELSET: level set at the background-mesh nodes (cell units)
   int gn[3];         // background-mesh nodes per axis
   double ginv[3];    // 1 / node spacing in cell units
+  int seeded;        // features seeded explicitly: reflect instead of project-and-retag
 };
 
 // Target size field in cell units: s_cell(x) = s(x) / cs.

@@ -44,6 +44,7 @@ class Params(C.Structure):
         ("cell_log2", C.c_int32), ("debug", C.c_int32),
         ("t0_window", C.c_int32), ("t0_tol", C.c_double), ("theta", C.c_double),
         ("grid_n", C.c_int32 * 3), ("grid_phi", C.POINTER(C.c_double)), ("grid_s", C.POINTER(C.c_double)),
+        ("seeded", C.c_int32),
     ]
 
 
@@ -171,6 +172,7 @@ def make_params(spec: dict, s0: float | None = None, cell_log2: int = -1, debug:
     p.t0_window = int(spec.get("t0_window", 50))
     p.t0_tol = float(spec.get("t0_tol", 1e-3))
     p.theta = float(spec.get("theta", 0.2))
+    p.seeded = 1 if spec.get("seeded") else 0
     return p, keep
 
 

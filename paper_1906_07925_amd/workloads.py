@@ -203,34 +203,80 @@ def initial_state(spec: dict, seed: int, init: str, n_colours: int, per_axis: in
     return x, col.astype(np.int32), typ
 
 
-def _sphere_points(m: int, dim: int, rng: np.random.Generator) -> np.ndarray:
-    """m directions uniform on the unit sphere (circle)."""
-    v = rng.normal(size=(m, dim))
-    return v / np.linalg.norm(v, axis=1)[:, None]
+def _spread(m: int, rng: np.random.Generator, jitter: float) -> np.ndarray:
+    """m parameters in (0, 1), evenly spread between the ends (which other features occupy):
+    (i + 1 + U(-jitter, jitter)) / (m + 1), in random order."""
+    t = (np.arange(m) + 1.0 + rng.uniform(-jitter, jitter, size=m)) / (m + 1.0)
+    return rng.permutation(t)
 
 
-def feature_points(spec: dict, k: int, m: int, rng: np.random.Generator) -> np.ndarray:
-    """m points uniform (by measure) on boundary feature k of the region, features numbered as
-    the library's particle budget numbers them (box: faces or sides 2a + h, then in 3D edges
-    4a + hb + 2hc, then corners; ball: its sphere; annulus: inner, then outer circle)."""
+def _spread_2d(m: int, ea: float, eb: float, rng: np.random.Generator, jitter: float) -> np.ndarray:
+    """m points in the open rectangle (0, ea) x (0, eb): a jittered p x q lattice of spacing
+    about sqrt(ea eb / m) between the sides, with p q - m sites dropped at random."""
+    p = max(1, int(round(math.sqrt(m * ea / eb))))
+    q = max(1, int(math.ceil(m / p)))
+    while p * q < m:
+        p += 1
+    i, j = np.meshgrid(np.arange(p), np.arange(q), indexing="ij")
+    u = (i.reshape(-1) + 1.0 + rng.uniform(-jitter, jitter, size=p * q)) / (p + 1.0)
+    v = (j.reshape(-1) + 1.0 + rng.uniform(-jitter, jitter, size=p * q)) / (q + 1.0)
+    keep = rng.choice(p * q, size=m, replace=False)
+    return np.stack([u[keep] * ea, v[keep] * eb], axis=1)
+
+
+def _round_points(m: int, dim: int, rng: np.random.Generator, jitter: float) -> np.ndarray:
+    """m near-evenly spread unit vectors: equal angles on the circle, the Fibonacci (golden
+    angle) spiral on the sphere; jittered and randomly rotated."""
+    if dim == 2:
+        th = (np.arange(m) + 0.5 + rng.uniform(-jitter, jitter, size=m)) * (2.0 * math.pi / m)
+        th = th + rng.uniform(0.0, 2.0 * math.pi)
+        return rng.permutation(np.stack([np.cos(th), np.sin(th)], axis=1))
+    k = np.arange(m) + 0.5
+    z = 1.0 - 2.0 * k / m
+    ph = k * math.pi * (3.0 - math.sqrt(5.0)) + rng.uniform(-jitter, jitter, size=m) * (2.0 * math.pi / math.sqrt(m))
+    r = np.sqrt(np.maximum(1.0 - z * z, 0.0))
+    v = np.stack([r * np.cos(ph), r * np.sin(ph), z], axis=1)
+    # random rotation (QR of a Gaussian matrix, sign-fixed)
+    qm, rm = np.linalg.qr(rng.normal(size=(3, 3)))
+    qm = qm * np.sign(np.diag(rm))
+    return rng.permutation(v @ qm.T)
+
+
+def feature_points(spec: dict, k: int, m: int, rng: np.random.Generator, jitter: float = 0.1) -> np.ndarray:
+    """m points spread evenly over boundary feature k of the region (jittered 1D / 2D lattices,
+    equal angles, the Fibonacci sphere), features numbered as the library's particle budget
+    numbers them (box: faces or sides 2a + h, then in 3D edges 4a + hb + 2hc, then corners;
+    ball: its sphere; annulus: inner, then outer circle).  Even spreading keeps the initial
+    gaps near the target spacing: on a 1D or 2D feature the kernel's repulsion weakens for
+    pairs closer than half a smoothing length, so uniformly random points would stay bunched."""
     d = spec["dim"]
     g = spec["geometry"]
     if g in ("ball", "annulus"):
         c = np.asarray(spec["centre"], dtype=np.float64)
         r = spec["r_in"] if (g == "annulus" and k == 0) else spec["r_out"]
-        return c + r * _sphere_points(m, d, rng)
+        return c + r * _round_points(m, d, rng, jitter)
     lo = np.asarray(spec["lo"], dtype=np.float64)
     hi = np.asarray(spec["hi"], dtype=np.float64)
     n_faces = 2 * d
     n_edges = 12 if d == 3 else 0
-    x = rng.uniform(lo, hi, size=(m, d))
+    x = np.tile(lo, (m, 1))
     if k < n_faces:
         a, h = divmod(k, 2)
         x[:, a] = hi[a] if h else lo[a]
+        others = [b for b in range(d) if b != a]
+        if d == 2:
+            b = others[0]
+            x[:, b] = lo[b] + _spread(m, rng, jitter) * (hi[b] - lo[b])
+        else:
+            b, c = others
+            uv = _spread_2d(m, hi[b] - lo[b], hi[c] - lo[c], rng, jitter)
+            x[:, b] = lo[b] + uv[:, 0]
+            x[:, c] = lo[c] + uv[:, 1]
         return x
     if k < n_faces + n_edges:
         a, bits = divmod(k - n_faces, 4)
         b, c = (1, 2) if a == 0 else ((0, 2) if a == 1 else (0, 1))
+        x[:, a] = lo[a] + _spread(m, rng, jitter) * (hi[a] - lo[a])
         x[:, b] = hi[b] if bits & 1 else lo[b]
         x[:, c] = hi[c] if bits & 2 else lo[c]
         return x

@@ -77,9 +77,13 @@ def check_single_step(spec, s0, x32, col, typ, tol=1e-5, cell_log2=-1, report=No
     errs["dt1"] = abs(m["dt1"] - r["dt1"]) / r["dt1"] if r["dt1"] > 0 else abs(m["dt1"])
     errs["dt2"] = abs(m["dt2"] - r["dt2"]) / r["dt2"] if r["dt2"] > 0 else abs(m["dt2"])
     errs["vt_norm"] = rel(g["vt"], r["vt"])
+    # the viscous acceleration also inherits the error of a: v~ = a dt1 / 2 enters the velocity
+    # differences and, through |v~|, the viscosities; a near-balanced particle (|a_j| << A_j)
+    # has a v~ of large relative error.  The oracle's at_prop is that propagated error per unit
+    # relative error of the |pair term| sums of a.
     AT = r["at_abs"][:, None]
     dat = np.abs(g["at"] - r["at"])
-    bound_at = tol * AT + dlt * r["at_kabs"][:, None]
+    bound_at = tol * AT + dlt * r["at_kabs"][:, None] + tol * r["at_prop"][:, None]
     errs["at_cond"] = np.max(np.where(bound_at > 0, dat / np.maximum(bound_at, 1e-300) * tol, dat))
     errs["at_norm"] = rel(g["at"], r["at"])
     errs["v_norm"] = rel(g["v"], r["v"])
@@ -101,9 +105,13 @@ def check_single_step(spec, s0, x32, col, typ, tol=1e-5, cell_log2=-1, report=No
     assert abs(m["pairs"] - r["pairs"]) <= band, counts
     assert abs(m["interface_pairs"] - r["interface_pairs"]) <= band, counts
     assert m["n_normal"] == r["n_normal"] and m["nonfinite"] == 0
-    # positions after the step: displacement error plus float32 rounding of the position
+    # positions after the step: displacement error plus float32 rounding of the position; a
+    # projection onto a circle or sphere is computed relative to the centre in FP32 cell units,
+    # so it rounds at a few ulp of the radius whatever the size of the coordinate
     dx = np.abs(g["x1"] - x1)
     ulp = np.spacing(np.abs(x1).astype(np.float32)).astype(np.float64)
+    if spec["geometry"] in ("ball", "annulus"):
+        ulp = ulp + 2.0 ** -24 * spec["r_out"]
     drn = np.linalg.norm(r["dr"], axis=1)[:, None]
     assert np.all(dx <= 4 * ulp + 10 * tol * drn + 1e-12), np.max(dx / (4 * ulp + 10 * tol * drn))
     assert np.array_equal(g["t1"], t1)
