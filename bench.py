@@ -210,6 +210,40 @@ def mesh_run(torch, M, W, steps: int = 50, warmup: int = 20):
             "n_feature": m["n_feature"], "nonfinite": m["nonfinite"]}
 
 
+def features_run(torch, M, W, k: int, lanes: int, steps: int = 100, warmup: int = 20):
+    """The graded cube of the headline workload with its boundary features seeded explicitly:
+    the particle budget of Eq. 5-6 from the library (host), 6 faces, 12 edges and 8 corners
+    seeded evenly, the interior uniform at random, 64 colours; the headline's cell size and
+    lanes.  Step time and pair interactions/s (HIP events on the library stream)."""
+    n = 1 << 21
+    spec = W.cube_with_inclusion(n, seeded=True)
+    t0 = time.perf_counter()
+    bd = M.feature_budget(spec, n)
+    t_budget = time.perf_counter() - t0
+    x, col, typ = W.feature_seeded(spec, bd, W.BASE_SEED + 70, 64)
+    print(f"[bench] features: budget {t_budget:.2f} s, state generated", file=sys.stderr, flush=True)
+    R = M.Relaxer(spec, n=n, s0=bd["s0"])
+    R.configure(k, lanes)
+    R.load(torch.from_numpy(x.astype(np.float32)).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    R.step(warmup)
+    m0 = R.metrics()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    m = R.metrics()
+    xs, ts = R.store()
+    kept = bool(np.array_equal(ts.cpu().numpy(), typ))
+    R.close()
+    pairs = m["pairs_total"] - m0["pairs_total"]
+    print(f"[bench] features: {1e3 * dt / steps:.2f} ms/step, budget {t_budget:.2f} s", file=sys.stderr, flush=True)
+    return {"workload": "cube_inclusion_2m_seeded_features", "particles": n, "steps": steps,
+            "n_surface": int(np.sum(typ == 1)), "n_curve": int(np.sum(typ == 2)), "n_corner": int(np.sum(typ == 3)),
+            "budget_host_s": t_budget, "ms_per_step": 1e3 * dt / steps, "pairs_per_s": pairs / dt,
+            "types_kept": kept, "residual_l2": m["residual_l2"], "nonfinite": m["nonfinite"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +256,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-mesh", action="store_true", help="skip the background-mesh workload")
+    ap.add_argument("--no-features", action="store_true", help="skip the seeded-feature workload")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -323,6 +358,8 @@ def main():
         out["batched"] = batched_run(torch, M, W, args.batched_steps, 10)
     if not args.no_mesh:
         out["mesh"] = mesh_run(torch, M, W)
+    if not args.no_features:
+        out["features"] = features_run(torch, M, W, out["config"]["cell_log2"], out["config"]["lanes"])
     if not args.no_adjoint:
         out["adjoint"] = adjoint_run(torch, M, W)
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
