@@ -280,8 +280,11 @@ MPSPH_API int mpsph_store(mpsph_ctx *ctx, float *d_pos, int32_t *d_type);
 MPSPH_API int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out);
 
 /* Cell structure of the last step: d_key (n uint32, the cell key of each particle in
- * original order: cellbase + cx + 2^k cy + 4^k cz, where cellbase is 0 for a single domain and
- * in a batch the first cell of the domain's range of the global cell table), d_cell_start
+ * original order: cellbase + cx + 2^k row, where cellbase is 0 for a single domain and in a
+ * batch the first cell of the domain's range of the global cell table; row = cy in 2D, and in
+ * 3D the rows are numbered in tiles of 2^ly x 2^lz rows, ly = min(5, k), lz = min(4, k):
+ * row = (cy mod 2^ly) + 2^ly (cz mod 2^lz) + 2^(ly+lz) floor(cy / 2^ly) + 2^(k+lz) floor(cz / 2^lz)),
+ * d_cell_start
  * (ncells + 1 uint32: index of the first sorted particle of each cell, last entry n) -- either
  * may be NULL -- and the host values ncells (all domains) and cell_log2 (of domain 0).  The
  * two host values are available from creation on; the arrays need a completed step.

@@ -13,7 +13,8 @@
 //          (cx | type << 12 | colour << 14), id u32
 //   per step: acc float4 (a, e = rho_t nu_coeff r_c |a|), cell table u32[ncells+1]; rho, sum|term|,
 //             a~, v, dr, nearest distance only in debug mode
-// Positions are an integer cell coordinate per axis (packed in the key, row-major, x fastest)
+// Positions are an integer cell coordinate per axis (packed in the key, x fastest, 3D rows in
+// tiles: row_index)
 // plus a float offset in [0, 1) in cell units, so pair separations are formed from exact
 // integer differences plus differences of numbers below one.  Lengths inside the kernels are
 // in cell units; accelerations and velocities are the domain values divided by the cell size
@@ -88,11 +89,23 @@ __global__ __launch_bounds__(kBlock) void load_kernel(const DomDev *__restrict__
   const int t = type ? type[u] : 0;
   if (col < 0 || col >= (1 << 18) || t < 0 || t > 3) ok = false;
   if (!ok) atomicOr(bad, 1);
-  key[i] = dd.cellbase + pack_key<D>(c, dd.g.k);
+  key[i] = dd.cellbase + pack_key<D>(c, dd.g);
   off[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
   ct[i] = (uint32_t)(t & 3) | ((uint32_t)col << 2);
   id[i] = (uint32_t)u;
 }
+
+// Waves per SIMD the pair kernels are compiled for (their register budget: 64 VGPRs and 96 SGPRs
+// at 8 waves); 0 leaves it to the compiler, which otherwise settles at 7 waves.  Measured on the
+// 2M-particle graded cube: 8 waves make both pair passes 12-13 % faster.
+#ifndef MPSPH_PAIR_WAVES
+#define MPSPH_PAIR_WAVES 8
+#endif
+#if MPSPH_PAIR_WAVES > 0
+#define MPSPH_PAIR_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MPSPH_PAIR_WAVES, MPSPH_PAIR_WAVES)))
+#else
+#define MPSPH_PAIR_OCCUPANCY
+#endif
 
 // Empty-cell runs of at least this length are filled by fill_gaps instead of one thread.
 constexpr uint32_t kShortGap = 64;
@@ -153,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
   const float4 o4 = soff[s];
   const uint32_t ct = sct[s];
   int c[3];
-  unpack_key<D>(key - dd.cellbase, dd.g.k, dd.g.xmask, c);
+  unpack_key<D>(key - dd.cellbase, dd.g, c);
   const float o[3] = {o4.x, o4.y, o4.z};
   const float spc = field_spacing<D>(dd.f, c, o);
   wkey[i] = key;
@@ -170,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
 // the viscosity of Eq. 21-22 per unit of dt1/2, and the first time-step candidate (Eq. 29).
 // L lanes per particle (group); lane 0 of the group writes the particle's results.
 template <int D, int L, bool PER>
-__global__ __launch_bounds__(kBlock) void pass_density_force(
+__global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_force(
     const DomDev *__restrict__ doms, int ndom, int b0, const int64_t *__restrict__ stepctr, const uint32_t *__restrict__ wkey,
     const float4 *__restrict__ wpos, const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ cstart,
     float4 *__restrict__ acc, float *__restrict__ rho_out, float *__restrict__ nn_out, float *__restrict__ aabs_out,
@@ -195,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void pass_density_force(
   float dtc = INFINITY;
   if (active) {
     int ci[3];
-    unpack_key<D>(wkey[i] - cellbase, g.k, g.xmask, ci);
+    unpack_key<D>(wkey[i] - cellbase, g, ci);
     const float4 pi = wpos[i];
     const float oi[3] = {pi.x, pi.y, pi.z};
     const uint32_t ai = wjaux[i];
@@ -341,7 +354,7 @@ __device__ __forceinline__ int type_from_faces(int nf, int d) {
 // With v~ = a dt1/2 the three criteria of Eq. 29 are increasing functions of r_c/|a| and give
 // dt2 = dt1 min(1, 2 min(c_vel, c_visc / nu_coeff) / c_acc^2) (sp.dt2_factor).
 template <int D, int L, bool PER>
-__global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
+__global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_integrate(
     const DomDev *__restrict__ doms, int ndom, int b0, const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos,
     const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ wid, const uint32_t *__restrict__ cstart,
     const float4 *__restrict__ acc, const uint32_t *__restrict__ dtslots, uint32_t *__restrict__ skey,
@@ -362,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
   const float dt2 = dt1 * sp.dt2_factor;
   if (li < doms[d].n) {
     int ci[3];
-    unpack_key<D>(wkey[i] - cellbase, g.k, g.xmask, ci);
+    unpack_key<D>(wkey[i] - cellbase, g, ci);
     const float4 pi = wpos[i];
     const float oi[3] = {pi.x, pi.y, pi.z};
     const uint32_t ai = wjaux[i];
@@ -547,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void pass_viscous_integrate(
           o[a] = 0.f;
         }
       }
-      skey[i] = cellbase + pack_key<D>(c, g.k);
+      skey[i] = cellbase + pack_key<D>(c, g);
       soff[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
       sct[i] = (uint32_t)ti | ((ai >> 14) << 2);
       sid[i] = wid[i];
@@ -580,7 +593,7 @@ __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ 
   const GridDev &g = dd.g;
   const StepDev &sp = dd.sp;
   int ci[3];
-  unpack_key<D>(wkey[i] - dd.cellbase, g.k, g.xmask, ci);
+  unpack_key<D>(wkey[i] - dd.cellbase, g, ci);
   const float4 pi = wpos[i];
   const float oi[3] = {pi.x, pi.y, pi.z};
   const float hi = pi.w;
@@ -698,7 +711,7 @@ __global__ __launch_bounds__(kBlock) void store_kernel(const DomDev *__restrict_
   if (i >= i1) return;
   const DomDev &dd = doms[domain_of(doms, ndom, i)];
   int c[3];
-  unpack_key<D>(skey[i] - dd.cellbase, dd.g.k, dd.g.xmask, c);
+  unpack_key<D>(skey[i] - dd.cellbase, dd.g, c);
   const float4 o = soff[i];
   const float oo[3] = {o.x, o.y, o.z};
   const uint32_t id = sid[i];
@@ -744,7 +757,7 @@ __global__ __launch_bounds__(kBlock) void dump_kernel(const DomDev *__restrict__
       break;
     case MPSPH_F_X0: {
       int c[3];
-      unpack_key<D>(wkey[i] - dd.cellbase, dd.g.k, dd.g.xmask, c);
+      unpack_key<D>(wkey[i] - dd.cellbase, dd.g, c);
       const float oo[3] = {p.x, p.y, p.z};
       for (int a = 0; a < D; ++a) ov[a] = (float)(dd.lo[a] + ((double)c[a] + (double)oo[a]) * csd);
       break;
@@ -1620,6 +1633,9 @@ DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, con
   g.r_in = (float)(p.r_in * ics);
   g.r_out = (float)(p.r_out * ics);
   g.seeded = p.seeded ? 1 : 0;
+  // 3D row tiles of 32 x 16 rows (fewer when the grid is smaller)
+  g.ly = D == 3 ? (uint32_t)std::min(MPSPH_TILE_LY, g.k) : 0u;
+  g.lz = D == 3 ? (uint32_t)std::min(MPSPH_TILE_LZ, g.k) : 0u;
   // background mesh: node spacing (hi - lo) / (n - 1) in cell units
   for (int a = 0; a < 3; ++a) {
     const int na = a < D ? std::max(p.grid_n[a], 2) : 2;

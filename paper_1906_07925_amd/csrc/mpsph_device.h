@@ -34,6 +34,14 @@ enum : int {
 
 // Geometry of the cell grid and of the meshing region, in cell units.  Positions are held as
 // an integer cell coordinate per axis plus a float offset in [0, 1).
+// Row tiles of the 3D cell key (log2 of the tile's rows along y and z).
+#ifndef MPSPH_TILE_LY
+#define MPSPH_TILE_LY 5
+#endif
+#ifndef MPSPH_TILE_LZ
+#define MPSPH_TILE_LZ 4
+#endif
+
 struct GridDev {
   int k;             // cells per axis = 2^k
   int n;             // particles of the context (bound of every sorted index)
@@ -49,6 +57,7 @@ struct GridDev {
   int gn[3];         // background-mesh nodes per axis
   double ginv[3];    // 1 / node spacing in cell units
   int seeded;        // features seeded explicitly: reflect instead of project-and-retag
+  uint32_t ly, lz;   // 3D row tiles of 2^ly x 2^lz rows in the cell key (see row_index)
 };
 
 // Target size field in cell units: s_cell(x) = s(x) / cs.
@@ -237,18 +246,35 @@ __device__ __forceinline__ float field_spacing(const FieldDev &f, const int *c, 
   return f.s0 * __expf(e);
 }
 
-template <int D>
-__device__ __forceinline__ void unpack_key(uint32_t key, int k, uint32_t mask, int *c) {
-  c[0] = (int)(key & mask);
-  c[1] = (int)((key >> k) & mask);
-  if constexpr (D == 3) c[2] = (int)(key >> (2 * k));
+// Cell key = cx + 2^k row(cy, cz).  In 3D the rows (fixed cy, cz) are numbered tile by tile:
+// tiles of 2^ly x 2^lz rows, cy fastest inside a tile, then cz; tiles cy-major, then cz.  The
+// cells of a row stay consecutive (the candidate scan reads each row as one range), and a run
+// of consecutive particles in key order covers a compact block of rows, so the neighbour data a
+// launch window touches is small (ly = lz = 0 gives the plain row-major order).
+__device__ __forceinline__ uint32_t row_index(int cy, int cz, const GridDev &g) {
+  const uint32_t y = (uint32_t)cy, z = (uint32_t)cz;
+  return (y & ((1u << g.ly) - 1u)) | ((z & ((1u << g.lz) - 1u)) << g.ly) | ((y >> g.ly) << (g.ly + g.lz)) |
+         ((z >> g.lz) << (g.k + g.lz));
 }
 
 template <int D>
-__device__ __forceinline__ uint32_t pack_key(const int *c, int k) {
-  uint32_t key = (uint32_t)c[0] | ((uint32_t)c[1] << k);
-  if constexpr (D == 3) key |= (uint32_t)c[2] << (2 * k);
-  return key;
+__device__ __forceinline__ void unpack_key(uint32_t key, const GridDev &g, int *c) {
+  c[0] = (int)(key & g.xmask);
+  if constexpr (D == 2) {
+    c[1] = (int)(key >> g.k);
+  } else {
+    const uint32_t r = key >> g.k;
+    const uint32_t yl = r & ((1u << g.ly) - 1u), zl = (r >> g.ly) & ((1u << g.lz) - 1u);
+    const uint32_t yh = (r >> (g.ly + g.lz)) & ((1u << (g.k - g.ly)) - 1u), zh = r >> (g.k + g.lz);
+    c[1] = (int)((yh << g.ly) | yl);
+    c[2] = (int)((zh << g.lz) | zl);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t pack_key(const int *c, const GridDev &g) {
+  if constexpr (D == 2) return (uint32_t)c[0] | ((uint32_t)c[1] << g.k);
+  return (uint32_t)c[0] | (row_index(c[1], c[2], g) << g.k);
 }
 
 // Remove the components of v along the active constraint normals of a feature particle

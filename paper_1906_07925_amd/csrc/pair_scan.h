@@ -11,7 +11,7 @@ namespace mpsph {
 // Neighbour candidates
 //
 // Particle i's candidates are the particles of every x-run of cells (fixed y, z) that meets the
-// ball of radius rs around it; in the row-major cell order each run is one contiguous range of
+// ball of radius rs around it; in the cell order (x fastest) each run is one contiguous range of
 // the sorted arrays.  A group of L lanes works on one particle: the L lanes take L rows at a
 // time (each reads its row's range from the cell table), form the prefix sum of the run lengths,
 // and then visit the flattened candidates of those rows L at a time, lane l taking every L-th
@@ -102,8 +102,11 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
     x0 = max(0, x0);
     x1 = min(g.gmax, x1);
     const int cyw = per ? (cy + P) & g.gmax : cy;   // |cy - ci| < P: one wrap at most
-    uint32_t kb = (uint32_t)x0 | ((uint32_t)cyw << g.k);
-    if constexpr (D == 3) kb |= (uint32_t)(per ? (cz + P) & g.gmax : cz) << (2 * g.k);
+    uint32_t kb;
+    if constexpr (D == 3)
+      kb = (uint32_t)x0 | (row_index(cyw, per ? (cz + P) & g.gmax : cz, g) << g.k);
+    else
+      kb = (uint32_t)x0 | ((uint32_t)cyw << g.k);
     kb += cellbase;
     uint32_t a = 0u, b = 0u;
     if (hit) {

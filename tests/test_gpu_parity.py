@@ -56,8 +56,8 @@ def test_single_step_parity(torch_cuda, name, scale, k):
 
 def test_keys_and_cell_table_bit_exact(torch_cuda):
     """Cell keys of identical inputs are exact by construction: floor((x - lo) (2^k - 1)/L) per
-    axis in FP64, packed row-major; the cell table is the lower bound of each cell in the sorted
-    keys."""
+    axis in FP64, packed x fastest (3D rows in tiles of 32 x 16, as the header documents); the
+    cell table is the lower bound of each cell in the sorted keys."""
     torch = torch_cuda
     from paper_1906_07925_amd import mpsph as M
     for name, scale in (("square_4k", 1.0), ("annulus_262k", 0.01), ("cube_inclusion_2m", 0.004)):
@@ -76,9 +76,14 @@ def test_keys_and_cell_table_bit_exact(torch_cuda):
         c = np.floor(X).astype(np.int64)
         frac = (X - c).astype(np.float32)
         c[frac >= 1.0] += 1
-        expect = np.zeros(x32.shape[0], dtype=np.int64)
-        for a in range(d):
-            expect |= c[:, a] << (a * k)
+        if d == 2:
+            expect = c[:, 0] | (c[:, 1] << k)
+        else:
+            ly, lz = min(5, k), min(4, k)
+            y, z = c[:, 1], c[:, 2]
+            row = (y & ((1 << ly) - 1)) | ((z & ((1 << lz) - 1)) << ly) | ((y >> ly) << (ly + lz)) | \
+                ((z >> lz) << (k + lz))
+            expect = c[:, 0] | (row << k)
         assert np.array_equal(keys.astype(np.int64), expect)
         sk = np.sort(expect)
         ref = np.searchsorted(sk, np.arange(2 ** (d * k) + 1), side="left")
