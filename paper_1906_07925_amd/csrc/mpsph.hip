@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void load_kernel(const DomDev *__restrict__
   const int t = type ? type[u] : 0;
   if (col < 0 || col >= (1 << 18) || t < 0 || t > 3) ok = false;
   if (!ok) atomicOr(bad, 1);
-  key[i] = dd.cellbase + pack_key<D>(c, dd.g);
+  key[i] = dd.cellbase + pack_key<D>(c, o, dd.g);
   off[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
   ct[i] = (uint32_t)(t & 3) | ((uint32_t)col << 2);
   id[i] = (uint32_t)u;
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
 // Writes acc = (a after the force mapping of Eq. 30-31, e_i) with e_i = rho_t nu_coeff r_c |a_i|,
 // the viscosity of Eq. 21-22 per unit of dt1/2, and the first time-step candidate (Eq. 29).
 // L lanes per particle (group); lane 0 of the group writes the particle's results.
-template <int D, int L, bool PER>
+template <int D, int L, bool PER, bool DBG>
 __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_force(
     const DomDev *__restrict__ doms, int ndom, int b0, const int64_t *__restrict__ stepctr, const uint32_t *__restrict__ wkey,
     const float4 *__restrict__ wpos, const uint32_t *__restrict__ wjaux, const uint32_t *__restrict__ cstart,
@@ -225,15 +225,17 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
     const float opb = 1.f + sigma;
     float wsum = 0.f, ax = 0.f, ay = 0.f, az = 0.f, A = 0.f, nn2 = INFINITY;
     uint32_t npair = 0, nifc = 0;
-    uint32_t ncand = scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](int j, uint32_t drw, bool v) {
-      const float4 pj = wpos[j];
-      const uint32_t aj = wjaux[j];
+    const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
+    const uint32_t ncand = scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart,
+                                                 [&](uint32_t j, float dy0, float dz0, bool v) {
+      const float4 pj = buf_f4(rpos, j);
+      const uint32_t aj = buf_u32(raux, j);
       const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
-      const float dy = row_dy(drw) + (oi[1] - pj.y);
+      const float dy = dy0 + (oi[1] - pj.y);
       float r2 = dx * dx + dy * dy;
       float dz = 0.f;
       if constexpr (D == 3) {
-        dz = row_dz(drw) + (oi[2] - pj.z);
+        dz = dz0 + (oi[2] - pj.z);
         r2 += dz * dz;
       }
       const float hij = kh * (hi + pj.w);           // kappa h_ij
@@ -243,7 +245,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
       // coincident particles (two particles clamped into one corner): r = 0, no direction
       const bool apart = r2 > 1e-30f;
       const float rinv = fast_rsq(apart ? r2 : 1.f);
-      const float r = apart ? r2 * rinv : 0.f;
+      const float r = r2 * rinv;                    // (numerically) 0 when not apart
       const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
       wsum += dens ? u2 * u2 * fmaf(2.f, q, 1.f) : 0.f;
       const uint32_t colj = aj >> 14;
@@ -251,30 +253,29 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
       const bool feel = inter && (int)((aj >> 12) & 3) >= ti;
       nifc += (inter && diff) ? 1u : 0u;
       npair += feel ? 1u : 0u;
-      nn2 = inter ? fminf(nn2, r2) : nn2;
+      if (inter && r2 < nn2) nn2 = r2;
       if (!(feel && apart)) return;
       const float ih = sp.kappa * fast_rcp(hij);    // 1 / h_ij
-      const float q2 = r * ih, uu = fmaf(-0.5f, q2, 1.f);
+      const float uu = fmaf(-0.5f * r, ih, 1.f);    // 1 - q/2, q = r / h_ij
       const float ih2 = ih * ih;
-      const float ihp = D == 3 ? ih2 * ih2 : ih2 * ih;  // h_ij^-(d+1)
+      const float ihp = D == 3 ? ih2 * ih2 * ih : ih2 * ih2;  // h_ij^-(d+2) = h_ij^-(d+1) q / r
       const float sj = pj.w * sp.inv_tau;
       const float Pj = sp.p0c * powd<D>(sj * sj);
-      // -dW/dr = alpha h^-(d+1) 5 q (1 - q/2)^3 >= 0
-      const float s = (diff ? opb : 1.f) * (Pi + Pj) * (alpha5 * ihp * q2 * uu * uu * uu * rinv);
+      // -dW/dr / r = alpha h^-(d+1) 5 (q / r) (1 - q/2)^3 >= 0
+      const float s = (diff ? opb : 1.f) * (Pi + Pj) * (alpha5 * ihp * uu * uu * uu);
       ax = fmaf(s, dx, ax);
       ay = fmaf(s, dy, ay);
       az = fmaf(s, dz, az);
-      A = fmaf(s, r, A);
+      if constexpr (DBG) A = fmaf(s, r, A);        // sum of |pair terms| (debug export only)
     });
     wsum = group_sum<L>(wsum);
     ax = group_sum<L>(ax);
     ay = group_sum<L>(ay);
     if constexpr (D == 3) az = group_sum<L>(az);
-    if (aabs_out) A = group_sum<L>(A);
+    if constexpr (DBG) A = group_sum<L>(A);
     nn2 = group_min<L>(nn2);
     npair = group_sum_u<L>(npair);
     nifc = group_sum_u<L>(nifc);
-    ncand = group_sum_u<L>(ncand);
     if (sub == 0) {
       const float ihd = D == 3 ? ihi * ihi * ihi : ihi * ihi;
       const float rho = sp.alpha * ihd * (1.f + wsum);
@@ -391,32 +392,33 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
     float bx = 0.f, by = 0.f, bz = 0.f;
     // with eta_i = 0 every harmonic-mean viscosity of particle i vanishes: nothing to sum
     if (ei > 0.f) {
-      scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](int j, uint32_t drw, bool v) {
-        const float4 pj = wpos[j];
-        const uint32_t aj = wjaux[j];
+      const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
+      const BufRes racc = buf_res(acc, 16, (uint32_t)g.n);
+      scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](uint32_t j, float dy0, float dz0, bool v) {
+        const float4 pj = buf_f4(rpos, j);
+        const uint32_t aj = buf_u32(raux, j);
         const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
-        const float dy = row_dy(drw) + (oi[1] - pj.y);
+        const float dy = dy0 + (oi[1] - pj.y);
         float r2 = dx * dx + dy * dy;
         if constexpr (D == 3) {
-          const float dz = row_dz(drw) + (oi[2] - pj.z);
+          const float dz = dz0 + (oi[2] - pj.z);
           r2 += dz * dz;
         }
         const float hij = kh * (hi + pj.w);
         if (!(v && r2 > 1e-30f && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti)) return;
-        const float4 accj = acc[j];
-        const float rinv = fast_rsq(r2);
-        const float r = r2 * rinv;
+        const float4 accj = buf_f4(racc, j);
+        const float r = r2 * fast_rsq(r2);
         const float ej = hdt * accj.w;
         const float esum = ei + ej;
         const float etaij = 2.f * ei * ej * fast_rcp(esum > 0.f ? esum : 1.f);
         const float ih = sp.kappa * fast_rcp(hij);
-        const float q = r * ih, uu = fmaf(-0.5f, q, 1.f);
+        const float uu = fmaf(-0.5f * r, ih, 1.f);  // 1 - q/2, q = r / h_ij
         const float ih2 = ih * ih;
-        const float ihp = D == 3 ? ih2 * ih2 : ih2 * ih;
+        const float ihp = D == 3 ? ih2 * ih2 * ih : ih2 * ih2;  // h_ij^-(d+2) = h_ij^-(d+1) q / r
         const float sj = pj.w * sp.inv_tau;
         const float inv2 = invi + powd<D>(sj * sj);
-        // dW/dr / r = -5 alpha h^-(d+1) q (1 - q/2)^3 / r
-        const float s = -etaij * inv2 * (alpha5 * ihp * q * uu * uu * uu * rinv);
+        // dW/dr / r = -5 alpha h^-(d+1) (q / r) (1 - q/2)^3
+        const float s = -etaij * inv2 * (alpha5 * ihp * uu * uu * uu);
         const float dxv = hdt * accj.x, dyv = hdt * accj.y, dzv = hdt * accj.z;
         bx = fmaf(s, vix - dxv, bx);
         by = fmaf(s, viy - dyv, by);
@@ -560,7 +562,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
           o[a] = 0.f;
         }
       }
-      skey[i] = cellbase + pack_key<D>(c, g);
+      skey[i] = cellbase + pack_key<D>(c, o, g);
       soff[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
       sct[i] = (uint32_t)ti | ((ai >> 14) << 2);
       sid[i] = wid[i];
@@ -600,14 +602,15 @@ __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ 
   const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
   const float kh = 0.5f * sp.kappa;
   const uint32_t idi = wid[i];
-  scan_group<D, 1, PER>(i, 0, ci, oi, rs, g, dd.cellbase, cstart, [&](int j, uint32_t drw, bool v) {
+  scan_group<D, 1, PER>(i, 0, ci, oi, rs, g, dd.cellbase, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
+    const int j = v ? (int)jr : i;  // slots past the end carry an index outside the arrays
     const float4 pj = wpos[j];
     const uint32_t aj = wjaux[j];
     const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
-    const float dy = row_dy(drw) + (oi[1] - pj.y);
+    const float dy = dy0 + (oi[1] - pj.y);
     float r2 = dx * dx + dy * dy;
     if constexpr (D == 3) {
-      const float dz = row_dz(drw) + (oi[2] - pj.z);
+      const float dz = dz0 + (oi[2] - pj.z);
       r2 += dz * dz;
     }
     const float hij = kh * (hi + pj.w);
@@ -779,6 +782,7 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Derived {
   int dim, k, gmax;
+  int xe;                  // x sub-cells per cell in the cell key: 2^xe
   double L, cs, inv_cs, lo[3], xhi[3];
   double smin, smax, lip;  // spacing bounds (domain units), Lipschitz constant of s
   double search_fac;
@@ -1245,6 +1249,13 @@ int derive(const mpsph_params *p, int64_t n, double s0, Derived *d) {
     k = std::min(std::max(k, 1), kmax);
   }
   if (p->dim * k > 24) return MPSPH_E_UNSUPPORTED;
+  // x sub-cells: up to 2^MPSPH_XSUB per cell while the cell table stays within 4 entries per
+  // particle (its fill is part of every step) and the key within 26 bits
+  int xe = 0;
+  while (xe < MPSPH_XSUB && p->dim * k + xe < 26 &&
+         std::pow(2.0, p->dim * k + xe + 1) <= 4.0 * (double)std::max<int64_t>(n, 1))
+    ++xe;
+  d->xe = xe;
   d->k = k;
   d->gmax = (1 << k) - 1;
   // walls at cells 0 and 2^k - 1 (offset 0); a periodic box wraps after 2^k cells
@@ -1462,7 +1473,7 @@ int make_domain(const mpsph_params *params, int64_t n, Domain *dm) {
   dm->s0 = s0;
   int rc = derive(&dm->p, n, s0, &dm->d);
   if (rc) return rc;
-  dm->ncells = (uint32_t)1u << (params->dim * dm->d.k);
+  dm->ncells = (uint32_t)1u << (params->dim * dm->d.k + dm->d.xe);
   return MPSPH_OK;
 }
 
@@ -1634,6 +1645,7 @@ DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, con
   g.r_out = (float)(p.r_out * ics);
   g.seeded = p.seeded ? 1 : 0;
   // 3D row tiles of 32 x 16 rows (fewer when the grid is smaller)
+  g.xe = (uint32_t)dm.d.xe;
   g.ly = D == 3 ? (uint32_t)std::min(MPSPH_TILE_LY, g.k) : 0u;
   g.lz = D == 3 ? (uint32_t)std::min(MPSPH_TILE_LZ, g.k) : 0u;
   // background mesh: node spacing (hi - lo) / (n - 1) in cell units
@@ -1762,7 +1774,8 @@ template <int D, int L_, bool PER>
 void launch_pass1_l(mpsph_ctx *ctx, const Group &gr, hipStream_t st) {
   const Layout &L = ctx->L;
   const bool dbg = ctx->dom[0].p.debug != 0;
-  pass_density_force<D, L_, PER><<<gr.nb, kBlock, 0, st>>>(
+  auto kern = dbg ? pass_density_force<D, L_, PER, true> : pass_density_force<D, L_, PER, false>;
+  kern<<<gr.nb, kBlock, 0, st>>>(
       ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.b0, ctx->at<int64_t>(L.stepctr), ctx->at<uint32_t>(L.w_key),
       ctx->at<float4>(L.w_pos), ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart), ctx->at<float4>(L.acc),
       dbg ? ctx->at<float>(L.rho) : nullptr, dbg ? ctx->at<float>(L.nn) : nullptr,
@@ -1933,7 +1946,7 @@ int replan(std::vector<Domain> &doms, int kdelta, int lanes, Layout *L, int kabs
     }
     int rc = derive(&q, dm.n, dm.s0, &dm.d);
     if (rc) return rc;
-    dm.ncells = (uint32_t)1u << (q.dim * dm.d.k);
+    dm.ncells = (uint32_t)1u << (q.dim * dm.d.k + dm.d.xe);
   }
   return plan(doms, lanes, L);
 }

@@ -17,8 +17,10 @@ namespace mpsph {
 // and then visit the flattened candidates of those rows L at a time, lane l taking every L-th
 // one (its row is found by a binary search over the prefix sums with cross-lane reads).  All
 // lanes of a wave thus run the same loop trip counts whatever the run lengths are.
-// body(j, drow, valid) is called for every slot; drow packs the row offsets (ci[1] - cy) in the
-// low and (ci[2] - cz) in the high 16 bits; invalid slots carry j = i.
+// body(j, dy0, dz0, valid) is called for every slot with the row offsets dy0 = ci[1] - cy and
+// dz0 = ci[2] - cz (cell units); an invalid slot (past the round's end, or the particle itself)
+// may carry an index outside the arrays.  The return value is the group's candidate count
+// (the particle itself excluded), the same in every lane of the group.
 // ------------------------------------------------------------------------------------------
 // Lanes per particle in the pair kernels (measured on the 2M-particle graded cube: 4 is the
 // fastest of 1, 2, 4, 8, 16, 32).
@@ -38,9 +40,6 @@ __device__ __forceinline__ float sep_x(const GridDev &g, int cxi, int cxj, float
   }
   return dx;
 }
-
-__device__ __forceinline__ float row_dy(uint32_t dr) { return (float)(int)(int16_t)(dr & 0xffffu); }
-__device__ __forceinline__ float row_dz(uint32_t dr) { return (float)((int)dr >> 16); }
 
 template <int D, int L, bool PER = false, typename BodyF>
 __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, const float *oi, float rs,
@@ -78,7 +77,7 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
   const int nrows = ny * (z1 - z0 + 1);
   const float inv_ny = 1.f / (float)ny;
   const uint32_t nmax = (uint32_t)g.n;
-  uint32_t ncand = 0;
+  uint32_t total = 0;   // candidates of the group, the particle itself included
   for (int q0 = 0; q0 < nrows; q0 += L) {
     const int q = q0 + sub;
     const int qz = (int)(((float)q + 0.5f) * inv_ny);   // q / ny (q, ny < 2^12)
@@ -92,21 +91,25 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
     const float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
     const float d2 = ey * ey + ez * ez;
     const bool hit = q < nrows && d2 < rs2;
+    // x-run of the row in sub-cells (2^xe per cell; the power-of-two scaling is exact)
     const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
-    int x0 = ci[0] + (int)floorf(oi[0] - wx);
-    int x1 = ci[0] + (int)floorf(oi[0] + wx);
-    if (per && (x0 < 0 || x1 > g.gmax)) {  // a run across the period: the whole row, once
+    const float fx = (float)(1u << g.xe);
+    const int xlast = ((g.gmax + 1) << g.xe) - 1;
+    int x0 = (ci[0] << g.xe) + (int)floorf((oi[0] - wx) * fx);
+    int x1 = (ci[0] << g.xe) + (int)floorf((oi[0] + wx) * fx);
+    if (per && (x0 < 0 || x1 > xlast)) {  // a run across the period: the whole row, once
       x0 = 0;
-      x1 = g.gmax;
+      x1 = xlast;
     }
     x0 = max(0, x0);
-    x1 = min(g.gmax, x1);
+    x1 = min(xlast, x1);
     const int cyw = per ? (cy + P) & g.gmax : cy;   // |cy - ci| < P: one wrap at most
+    const uint32_t kx = g.k + g.xe;
     uint32_t kb;
     if constexpr (D == 3)
-      kb = (uint32_t)x0 | (row_index(cyw, per ? (cz + P) & g.gmax : cz, g) << g.k);
+      kb = (uint32_t)x0 | (row_index(cyw, per ? (cz + P) & g.gmax : cz, g) << kx);
     else
-      kb = (uint32_t)x0 | ((uint32_t)cyw << g.k);
+      kb = (uint32_t)x0 | ((uint32_t)cyw << kx);
     kb += cellbase;
     uint32_t a = 0u, b = 0u;
     if (hit) {
@@ -114,7 +117,9 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
       b = min(cstart[kb + (uint32_t)(x1 - x0) + 1u], nmax);
     }
     const uint32_t len = b > a ? b - a : 0u;
-    const uint32_t drow = ((uint32_t)(ci[1] - cy) & 0xffffu) | ((uint32_t)(D == 3 ? ci[2] - cz : 0) << 16);
+    // row offsets of the separation (unwrapped, so the minimum image in a periodic box)
+    const float dyr = (float)(ci[1] - cy);
+    const float dzr = D == 3 ? (float)(ci[2] - cz) : 0.f;
     uint32_t incl = len;
 #pragma unroll
     for (int o = 1; o < L; o <<= 1) {
@@ -122,7 +127,9 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
       if (sub >= o) incl += v;
     }
     const uint32_t T = __shfl(incl, L - 1, L);
-    const uint32_t excl = incl - len;
+    // candidate slot t of this round lies in the row r with excl_r <= t < incl_r: j = a_r + t - excl_r
+    const uint32_t base = a - (incl - len);
+    total += T;
     for (uint32_t t0 = 0; t0 < T; t0 += L) {
       const uint32_t t = t0 + (uint32_t)sub;
       int r = 0;
@@ -131,14 +138,14 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
         const uint32_t v = __shfl(incl, r + step - 1, L);
         if (v <= t) r += step;
       }
-      const uint32_t ar = __shfl(a, r, L), er = __shfl(excl, r, L), dr = __shfl(drow, r, L);
-      const uint32_t j = ar + (t - er);
-      const bool valid = t < T && (int)j != i;
-      ncand += valid ? 1u : 0u;
-      body(valid ? (int)j : i, dr, valid);
+      const uint32_t j = __shfl(base, r, L) + t;
+      const float dy0 = __shfl(dyr, r, L), dz0 = D == 3 ? __shfl(dzr, r, L) : 0.f;
+      // slots past the end carry an index that may lie outside the arrays: bodies must load
+      // through bounds-checked buffer loads or clamp it with the valid flag
+      body(j, dy0, dz0, t < T && j != (uint32_t)i);
     }
   }
-  return ncand;
+  return total > 0u ? total - 1u : 0u;
 }
 
 // Sum / minimum across the L lanes of a group (fixed butterfly order).

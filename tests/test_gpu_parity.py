@@ -56,8 +56,9 @@ def test_single_step_parity(torch_cuda, name, scale, k):
 
 def test_keys_and_cell_table_bit_exact(torch_cuda):
     """Cell keys of identical inputs are exact by construction: floor((x - lo) (2^k - 1)/L) per
-    axis in FP64, packed x fastest (3D rows in tiles of 32 x 16, as the header documents); the
-    cell table is the lower bound of each cell in the sorted keys."""
+    axis in FP64 and the float32 offset's x sub-cell, packed x fastest (2^xe sub-cells along x,
+    3D rows in tiles of 32 x 16, as the header documents); the cell table is the lower bound of
+    each cell in the sorted keys."""
     torch = torch_cuda
     from paper_1906_07925_amd import mpsph as M
     for name, scale in (("square_4k", 1.0), ("annulus_262k", 0.01), ("cube_inclusion_2m", 0.004)):
@@ -75,18 +76,28 @@ def test_keys_and_cell_table_bit_exact(torch_cuda):
         X = (x32.astype(np.float64) - np.asarray(spec["lo"][:d])) * ((2 ** k - 1) / L)
         c = np.floor(X).astype(np.int64)
         frac = (X - c).astype(np.float32)
-        c[frac >= 1.0] += 1
+        carry = frac >= 1.0
+        c[carry] += 1
+        frac[carry] = 0.0
+        ncells = cstart.size - 1
+        xe = int(np.log2(ncells)) - d * k
+        n = x32.shape[0]
+        expect_xe = 0
+        while expect_xe < 3 and d * k + expect_xe < 26 and 2 ** (d * k + expect_xe + 1) <= 4 * n:
+            expect_xe += 1
+        assert ncells == 2 ** (d * k + xe) and xe == expect_xe
+        xf = (c[:, 0] << xe) | np.floor(frac[:, 0] * np.float32(2 ** xe)).astype(np.int64)
         if d == 2:
-            expect = c[:, 0] | (c[:, 1] << k)
+            row = c[:, 1]
         else:
             ly, lz = min(5, k), min(4, k)
             y, z = c[:, 1], c[:, 2]
             row = (y & ((1 << ly) - 1)) | ((z & ((1 << lz) - 1)) << ly) | ((y >> ly) << (ly + lz)) | \
                 ((z >> lz) << (k + lz))
-            expect = c[:, 0] | (row << k)
+        expect = xf | (row << (k + xe))
         assert np.array_equal(keys.astype(np.int64), expect)
         sk = np.sort(expect)
-        ref = np.searchsorted(sk, np.arange(2 ** (d * k) + 1), side="left")
+        ref = np.searchsorted(sk, np.arange(ncells + 1), side="left")
         assert np.array_equal(cstart, ref)
         R.close()
 
