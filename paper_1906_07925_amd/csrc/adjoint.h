@@ -205,10 +205,11 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
     const float kh = 0.5f * sp.kappa, a5 = 5.f * sp.alpha, a75 = 7.5f * sp.alpha;
     float vb[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, eb = 0.f, sb = 0.f;
     if (ei > 0.f) {
+      const BufRes rpos = buf_res(tp.wpos, 16, (uint32_t)g.n), raux = buf_res(tp.wjaux, 4, (uint32_t)g.n);
       scan_group<D, L>(i, sub, ci, oi, rs, g, 0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-    const int j = v ? (int)jr : i;  // slots past the end carry an index outside the arrays
-        const float4 pj = tp.wpos[j];
-        const uint32_t aj = tp.wjaux[j];
+        const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
+        const float4 pj = buf_f4(rpos, jr);
+        const uint32_t aj = buf_u32(raux, jr);
         const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
         const float dy = dy0 + (oi[1] - pj.y);
         float dz = 0.f;
@@ -373,10 +374,11 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
   const float kh = 0.5f * sp.kappa, a5 = 5.f * sp.alpha, a75 = 7.5f * sp.alpha;
   const float opb = 1.f + sigma_of(sp, tstep);   // surface tension of the step (Eq. 24-25)
   float xb[3] = {0.f, 0.f, 0.f}, sb = 0.f;
+  const BufRes rpos = buf_res(tp.wpos, 16, (uint32_t)g.n), raux = buf_res(tp.wjaux, 4, (uint32_t)g.n);
   scan_group<D, L>(i, sub, ci, oi, rs, g, 0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-    const int j = v ? (int)jr : i;  // slots past the end carry an index outside the arrays
-    const float4 pj = tp.wpos[j];
-    const uint32_t aj = tp.wjaux[j];
+    const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
+    const float4 pj = buf_f4(rpos, jr);
+    const uint32_t aj = buf_u32(raux, jr);
     const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
     const float dy = dy0 + (oi[1] - pj.y);
     float dz = 0.f;
@@ -507,10 +509,11 @@ __global__ __launch_bounds__(kBlock) void loss_density(const DomDev *__restrict_
     const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
     const float kh = 0.5f * sp.kappa;
     float ws = 0.f, wi = 0.f;
+    const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
     scan_group<D, L>(i, sub, ci, oi, rs, g, 0u, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-    const int j = v ? (int)jr : i;  // slots past the end carry an index outside the arrays
-      const float4 pj = wpos[j];
-      const uint32_t aj = wjaux[j];
+      const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
+      const float4 pj = buf_f4(rpos, jr);
+      const uint32_t aj = buf_u32(raux, jr);
       const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
       const float dy = dy0 + (oi[1] - pj.y);
       float r2 = dx * dx + dy * dy;
@@ -571,10 +574,11 @@ __global__ __launch_bounds__(kBlock) void loss_grad(const DomDev *__restrict__ d
   const float rs = fminf(reach_fac * hi, sp.kappa * sp.hmax) * 1.0001f;
   const float kh = 0.5f * sp.kappa;
   float xb[3] = {0.f, 0.f, 0.f}, sb = 0.f;
+  const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
   scan_group<D, L>(i, sub, ci, oi, rs, g, 0u, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-    const int j = v ? (int)jr : i;  // slots past the end carry an index outside the arrays
-    const float4 pj = wpos[j];
-    const uint32_t aj = wjaux[j];
+    const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
+    const float4 pj = buf_f4(rpos, jr);
+    const uint32_t aj = buf_u32(raux, jr);
     const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
     const float dy = dy0 + (oi[1] - pj.y);
     float dz = 0.f;
