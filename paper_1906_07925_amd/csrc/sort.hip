@@ -43,8 +43,11 @@ __global__ __launch_bounds__(1024) void radix_scan(uint32_t *__restrict__ hist, 
   const int per = (ntiles + nparts - 1) / nparts;
   const int b0 = p * per, b1 = min(ntiles, b0 + per);
   uint32_t s = 0;
-  if (p < nparts)
+  if (p < nparts) {
+    // independent loads in flight (the tile sums are order-free integers)
+#pragma unroll 8
     for (int b = b0; b < b1; ++b) s += hist[(size_t)b * radix + d];
+  }
   part[threadIdx.x] = s;
   __syncthreads();
   if (threadIdx.x < radix) {
@@ -57,17 +60,35 @@ __global__ __launch_bounds__(1024) void radix_scan(uint32_t *__restrict__ hist, 
     dig_off[threadIdx.x] = run;  // digit total for now
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int t = 0; t < radix; ++t) {
-      uint32_t x = dig_off[t];
-      dig_off[t] = run;
-      run += x;
+  if (threadIdx.x < 64) {
+    // exclusive scan of the (at most 256) digit totals by one wave: 4 per lane, then the lanes
+    const int l = threadIdx.x;
+    uint32_t v[4], tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = 4 * l + q;
+      v[q] = t < radix ? dig_off[t] : 0u;
+      tot += v[q];
+    }
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t u = __shfl_up(incl, o, 64);
+      if (l >= o) incl += u;
+    }
+    uint32_t run = incl - tot;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = 4 * l + q;
+      if (t < radix) dig_off[t] = run;
+      run += v[q];
     }
   }
   __syncthreads();
   if (p < nparts) {
     uint32_t run = dig_off[d] + part[threadIdx.x];
+    // the loads do not depend on the running offset: the compiler can issue them ahead
+#pragma unroll 8
     for (int b = b0; b < b1; ++b) {
       uint32_t t = hist[(size_t)b * radix + d];
       hist[(size_t)b * radix + d] = run;
