@@ -359,6 +359,13 @@ class Relaxer:
         _check(lib().mpsph_debug_cells(self._ctx, None, None, C.byref(nc), C.byref(k)), "mpsph_debug_cells")
         return k.value
 
+    def ncells(self) -> int:
+        """Cells of the cell table (all domains, x sub-cells included)."""
+        nc = C.c_int64(0)
+        k = C.c_int32(0)
+        _check(lib().mpsph_debug_cells(self._ctx, None, None, C.byref(nc), C.byref(k)), "mpsph_debug_cells")
+        return nc.value
+
     def set_field_coeff(self, coeff, domain: int = 0):
         """New RBF coefficients of one domain's size field (s0 and the cell grid are kept)."""
         c = np.ascontiguousarray(np.asarray(coeff, dtype=np.float64).reshape(-1))
