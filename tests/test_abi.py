@@ -23,7 +23,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(M.LIB_PATH):
-        pytest.fail("libmpsph.so is not built (run __graft_entry__.build())")
+        pytest.fail("libmpsph.so is not built (run paper_1906_07925_amd/build.py)")
     return M.lib()
 
 
