@@ -130,13 +130,28 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
     // candidate slot t of this round lies in the row r with excl_r <= t < incl_r: j = a_r + t - excl_r
     const uint32_t base = a - (incl - len);
     total += T;
+    // the group's prefix sums in every lane (quad broadcasts for L <= 4), for the row search
+    uint32_t inc0 = 0, inc1 = 0, inc2 = 0;
+    if constexpr (L == 2) {
+      inc0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)incl, 0xA0, 0xF, 0xF, false);   // quad_perm 0,0,2,2
+    } else if constexpr (L == 4) {
+      inc0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)incl, 0x00, 0xF, 0xF, false);   // quad_perm 0,0,0,0
+      inc1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)incl, 0x55, 0xF, 0xF, false);   // quad_perm 1,1,1,1
+      inc2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)incl, 0xAA, 0xF, 0xF, false);   // quad_perm 2,2,2,2
+    }
     for (uint32_t t0 = 0; t0 < T; t0 += L) {
       const uint32_t t = t0 + (uint32_t)sub;
       int r = 0;
+      if constexpr (L == 2) {
+        r = t >= inc0 ? 1 : 0;
+      } else if constexpr (L == 4) {
+        r = (t >= inc0 ? 1 : 0) + (t >= inc1 ? 1 : 0) + (t >= inc2 ? 1 : 0);
+      } else {
 #pragma unroll
-      for (int step = L / 2; step > 0; step >>= 1) {
-        const uint32_t v = __shfl(incl, r + step - 1, L);
-        if (v <= t) r += step;
+        for (int step = L / 2; step > 0; step >>= 1) {
+          const uint32_t v = __shfl(incl, r + step - 1, L);
+          if (v <= t) r += step;
+        }
       }
       const uint32_t j = __shfl(base, r, L) + t;
       const float dy0 = __shfl(dyr, r, L), dz0 = D == 3 ? __shfl(dzr, r, L) : 0.f;
