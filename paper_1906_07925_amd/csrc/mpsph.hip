@@ -397,6 +397,8 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
       scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](uint32_t j, float dy0, float dz0, bool v) {
         const float4 pj = buf_f4(rpos, j);
         const uint32_t aj = buf_u32(raux, j);
+        // issued with the position load so that its latency overlaps the range test
+        const float4 accj = buf_f4(racc, j);
         const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
         const float dy = dy0 + (oi[1] - pj.y);
         float r2 = dx * dx + dy * dy;
@@ -406,7 +408,6 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
         }
         const float hij = kh * (hi + pj.w);
         if (!(v && r2 > 1e-30f && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti)) return;
-        const float4 accj = buf_f4(racc, j);
         const float r = r2 * fast_rsq(r2);
         const float ej = hdt * accj.w;
         const float esum = ei + ej;
