@@ -11,12 +11,14 @@ namespace mpsph {
 // Neighbour candidates
 //
 // Particle i's candidates are the particles of every x-run of cells (fixed y, z) that meets the
-// ball of radius rs around it; in the cell order (x fastest) each run is one contiguous range of
-// the sorted arrays.  A group of L lanes works on one particle: the L lanes take L rows at a
-// time (each reads its row's range from the cell table), form the prefix sum of the run lengths,
-// and then visit the flattened candidates of those rows L at a time, lane l taking every L-th
-// one (its row is found by a binary search over the prefix sums with cross-lane reads).  All
-// lanes of a wave thus run the same loop trip counts whatever the run lengths are.
+// ball of radius rs around it, the run taken at x sub-cell resolution; in the cell order (x
+// fastest) each run is one contiguous range of the sorted arrays.  A group of L lanes works on
+// one particle: the L lanes take L rows at a time (each reads its row's range from the cell
+// table), form the prefix sum of the run lengths, and then visit the flattened candidates of
+// those rows L at a time, lane l taking every L-th one.  A slot's row comes from comparing it
+// with the group's prefix sums (held in every lane through quad broadcasts for L <= 4; a
+// binary search with cross-lane reads for L = 8).  All lanes of a group run the same loop trip
+// counts whatever the run lengths are.
 // body(j, dy0, dz0, valid) is called for every slot with the row offsets dy0 = ci[1] - cy and
 // dz0 = ci[2] - cz (cell units); an invalid slot (past the round's end, or the particle itself)
 // may carry an index outside the arrays.  The return value is the group's candidate count
