@@ -511,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void loss_density(const DomDev *__restrict_
     float ws = 0.f, wi = 0.f;
     const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
     scan_group<D, L>(i, sub, ci, oi, rs, g, 0u, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-      const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
+      // jr lies past the arrays for invalid slots: bounds-checked loads first
       const float4 pj = buf_f4(rpos, jr);
       const uint32_t aj = buf_u32(raux, jr);
       const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);

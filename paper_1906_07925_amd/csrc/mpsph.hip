@@ -375,61 +375,76 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
   const float hdt = 0.5f * dt1;
   const float dt2 = dt1 * sp.dt2_factor;
   if (li < doms[d].n) {
-    int ci[3];
-    unpack_key<D>(wkey[i] - cellbase, g, ci);
-    const float4 pi = wpos[i];
-    const float oi[3] = {pi.x, pi.y, pi.z};
-    const uint32_t ai = wjaux[i];
-    int ti = (ai >> 12) & 3;
-    const float hi = pi.w;
-    const float si = hi * sp.inv_tau;
-    const float invi = powd<D>(si * si);              // 1 / rho_t,i^2
-    const float4 acci = acc[i];
-    const float vix = hdt * acci.x, viy = hdt * acci.y, viz = hdt * acci.z, ei = hdt * acci.w;
-    const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
-    const float kh = 0.5f * sp.kappa;
-    const float alpha5 = 5.f * sp.alpha;
     float bx = 0.f, by = 0.f, bz = 0.f;
-    // with eta_i = 0 every harmonic-mean viscosity of particle i vanishes: nothing to sum
-    if (ei > 0.f) {
-      const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
-      const BufRes racc = buf_res(acc, 16, (uint32_t)g.n);
-      scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart, [&](uint32_t j, float dy0, float dz0, bool v) {
-        const float4 pj = buf_f4(rpos, j);
-        const uint32_t aj = buf_u32(raux, j);
-        // issued with the position load so that its latency overlaps the range test
-        const float4 accj = buf_f4(racc, j);
-        const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
-        const float dy = dy0 + (oi[1] - pj.y);
-        float r2 = dx * dx + dy * dy;
-        if constexpr (D == 3) {
-          const float dz = dz0 + (oi[2] - pj.z);
-          r2 += dz * dz;
-        }
-        const float hij = kh * (hi + pj.w);
-        if (!(v && r2 > 1e-30f && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti)) return;
-        const float r = r2 * fast_rsq(r2);
-        const float ej = hdt * accj.w;
-        const float esum = ei + ej;
-        const float etaij = 2.f * ei * ej * fast_rcp(esum > 0.f ? esum : 1.f);
-        const float ih = sp.kappa * fast_rcp(hij);
-        const float uu = fmaf(-0.5f * r, ih, 1.f);  // 1 - q/2, q = r / h_ij
-        const float ih2 = ih * ih;
-        const float ihp = D == 3 ? ih2 * ih2 * ih : ih2 * ih2;  // h_ij^-(d+2) = h_ij^-(d+1) q / r
-        const float sj = pj.w * sp.inv_tau;
-        const float inv2 = invi + powd<D>(sj * sj);
-        // dW/dr / r = -5 alpha h^-(d+1) (q / r) (1 - q/2)^3
-        const float s = -etaij * inv2 * (alpha5 * ihp * uu * uu * uu);
-        const float dxv = hdt * accj.x, dyv = hdt * accj.y, dzv = hdt * accj.z;
-        bx = fmaf(s, vix - dxv, bx);
-        by = fmaf(s, viy - dyv, by);
-        if constexpr (D == 3) bz = fmaf(s, viz - dzv, bz);
-      });
+    {
+      // the pair sum; the particle's own data is scoped to it (the epilogue reads it again)
+      int ci[3];
+      unpack_key<D>(wkey[i] - cellbase, g, ci);
+      const float4 pi = wpos[i];
+      const float oi[3] = {pi.x, pi.y, pi.z};
+      const int ti = (wjaux[i] >> 12) & 3;
+      const float hi = pi.w;
+      const float si = hi * sp.inv_tau;
+      const float invi = powd<D>(si * si);              // 1 / rho_t,i^2
+      const float4 acci = acc[i];
+      const float vix = hdt * acci.x, viy = hdt * acci.y, viz = hdt * acci.z, ei = hdt * acci.w;
+      const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
+      const float kh = 0.5f * sp.kappa;
+      const float alpha5 = 5.f * sp.alpha;
+      // with eta_i = 0 every harmonic-mean viscosity of particle i vanishes: nothing to sum
+      if (ei > 0.f) {
+        const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
+        const BufRes racc = buf_res(acc, 16, (uint32_t)g.n);
+        const auto body = [&](uint32_t j, float dy0, float dz0, bool v) {
+          const float4 pj = buf_f4(rpos, j);
+          const uint32_t aj = buf_u32(raux, j);
+          // issued with the position load so that its latency overlaps the range test
+          const float4 accj = buf_f4(racc, j);
+          const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
+          const float dy = dy0 + (oi[1] - pj.y);
+          float r2 = dx * dx + dy * dy;
+          if constexpr (D == 3) {
+            const float dz = dz0 + (oi[2] - pj.z);
+            r2 += dz * dz;
+          }
+          const float hij = kh * (hi + pj.w);
+          if (!(v && r2 > 1e-30f && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti)) return;
+          const float r = r2 * fast_rsq(r2);
+          const float ej = hdt * accj.w;
+          const float esum = ei + ej;
+          const float etaij = 2.f * ei * ej * fast_rcp(esum > 0.f ? esum : 1.f);
+          const float ih = sp.kappa * fast_rcp(hij);
+          const float uu = fmaf(-0.5f * r, ih, 1.f);  // 1 - q/2, q = r / h_ij
+          const float ih2 = ih * ih;
+          const float ihp = D == 3 ? ih2 * ih2 * ih : ih2 * ih2;  // h_ij^-(d+2) = h_ij^-(d+1) q / r
+          const float sj = pj.w * sp.inv_tau;
+          const float inv2 = invi + powd<D>(sj * sj);
+          // dW/dr / r = -5 alpha h^-(d+1) (q / r) (1 - q/2)^3
+          const float s = -etaij * inv2 * (alpha5 * ihp * uu * uu * uu);
+          const float dxv = hdt * accj.x, dyv = hdt * accj.y, dzv = hdt * accj.z;
+          bx = fmaf(s, vix - dxv, bx);
+          by = fmaf(s, viy - dyv, by);
+          if constexpr (D == 3) bz = fmaf(s, viz - dzv, bz);
+        };
+        scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart, body);
+      }
     }
     bx = group_sum<L>(bx);
     by = group_sum<L>(by);
     if constexpr (D == 3) bz = group_sum<L>(bz);
     if (sub == 0) {
+      // the particle's own data is read again rather than kept in registers across the pair
+      // loop, through an index the compiler cannot tie to i, so that neither values nor
+      // addresses stay live across it (this keeps the pass free of register spills)
+      const int io = __shfl(i, (int)(threadIdx.x & (kWave - 1)));
+      int ci[3];
+      unpack_key<D>(wkey[io] - cellbase, g, ci);
+      const float4 pe = wpos[io];
+      const float oi[3] = {pe.x, pe.y, pe.z};
+      const uint32_t ai = wjaux[io];
+      int ti = (ai >> 12) & 3;
+      const float4 acce = acc[io];
+      const float vix = hdt * acce.x, viy = hdt * acce.y, viz = hdt * acce.z;
       float b[3] = {bx, by, bz};
       project_feature<D>(g, ti, ci, oi, b);
       float v[3] = {vix + 0.5f * b[0] * dt2, viy + 0.5f * b[1] * dt2, viz + 0.5f * b[2] * dt2};
@@ -563,13 +578,13 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
           o[a] = 0.f;
         }
       }
-      skey[i] = cellbase + pack_key<D>(c, o, g);
-      soff[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
-      sct[i] = (uint32_t)ti | ((ai >> 14) << 2);
-      sid[i] = wid[i];
-      if (at_out) at_out[i] = make_float4(b[0], b[1], b[2], 0.f);
-      if (v_out) v_out[i] = make_float4(v[0], v[1], v[2], 0.f);
-      if (dr_out) dr_out[i] = make_float4(dr[0], dr[1], dr[2], 0.f);
+      skey[io] = cellbase + pack_key<D>(c, o, g);
+      soff[io] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
+      sct[io] = (uint32_t)ti | ((ai >> 14) << 2);
+      sid[io] = wid[io];
+      if (at_out) at_out[io] = make_float4(b[0], b[1], b[2], 0.f);
+      if (v_out) v_out[io] = make_float4(v[0], v[1], v[2], 0.f);
+      if (dr_out) dr_out[io] = make_float4(dr[0], dr[1], dr[2], 0.f);
       part[0] = (double)ke;
       part[1] = fin ? 0.0 : 1.0;
       part[2] = ti != 0 ? 1.0 : 0.0;

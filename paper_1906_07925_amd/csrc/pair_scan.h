@@ -203,7 +203,9 @@ __device__ __forceinline__ void block_min_to_slots(float v, int lb, uint32_t *sl
 __device__ __forceinline__ float read_dt1(const uint32_t *slots) {
   float v = __uint_as_float(slots[threadIdx.x & (kDtSlots - 1)]);
   for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
-  return v < INFINITY ? v : 0.f;
+  v = v < INFINITY ? v : 0.f;
+  // the same value in every lane: held as a wave-uniform (scalar) value
+  return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
 }
 
 }  // namespace mpsph
