@@ -244,8 +244,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
       if (!(dens || inter)) return;
       // coincident particles (two particles clamped into one corner): r = 0, no direction
       const bool apart = r2 > 1e-30f;
-      const float rinv = fast_rsq(apart ? r2 : 1.f);
-      const float r = r2 * rinv;                    // (numerically) 0 when not apart
+      const float r = fast_sqrt(r2);
       const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
       wsum += dens ? u2 * u2 * fmaf(2.f, q, 1.f) : 0.f;
       const uint32_t colj = aj >> 14;
@@ -409,7 +408,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
           }
           const float hij = kh * (hi + pj.w);
           if (!(v && r2 > 1e-30f && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti)) return;
-          const float r = r2 * fast_rsq(r2);
+          const float r = fast_sqrt(r2);
           const float ej = hdt * accj.w;
           const float esum = ei + ej;
           const float etaij = 2.f * ei * ej * fast_rcp(esum > 0.f ? esum : 1.f);

@@ -217,6 +217,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }  // x >= 0; sqrt(0) = 0
 
 template <int D>
 __device__ __forceinline__ float powd(float s) {  // s^D
