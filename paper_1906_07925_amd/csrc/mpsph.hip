@@ -13,10 +13,10 @@
 //          (cx | type << 12 | colour << 14), id u32
 //   per step: acc float4 (a, e = rho_t nu_coeff r_c |a|), cell table u32[ncells+1]; rho, sum|term|,
 //             a~, v, dr, nearest distance only in debug mode
-// Positions are an integer cell coordinate per axis (packed in the key, x fastest, 3D rows in
-// tiles: row_index)
-// plus a float offset in [0, 1) in cell units, so pair separations are formed from exact
-// integer differences plus differences of numbers below one.  Lengths inside the kernels are
+// Positions are an integer cell coordinate per axis (packed in the key: x fastest and at
+// sub-cell resolution, 3D rows numbered in tiles by row_index) plus a float offset in [0, 1) in
+// cell units, so pair separations are formed from exact integer differences plus differences of
+// numbers below one.  Lengths inside the kernels are
 // in cell units; accelerations and velocities are the domain values divided by the cell size
 // (time is unchanged; the EOS constant is scaled by cs^(d-2) to make this exact).
 //

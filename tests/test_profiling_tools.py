@@ -53,3 +53,16 @@ def test_step_table(tmp_path):
     assert cells[1] == "2"
     assert float(cells[2]) == pytest.approx(2 * 4000 * 1024 / 2 / 1e6, abs=0.05)
     assert float(cells[3]) == pytest.approx(1000 * 1024 / 2 / 1e6, abs=0.05)
+
+
+def test_kernel_source_digest_ignores_comments(tmp_path, monkeypatch):
+    """The digest that ties committed counters to the kernels follows the code only."""
+    import bench
+    src = tmp_path / "k.hip"
+    src.write_text("// header\nint f(int x) {  // trailing\n  return x + 1;\n}\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(src)])
+    d0 = bench.kernel_source_digest()
+    src.write_text("// another header\n\nint f(int x) {\n  // note\n  return x + 1;   \n}\n")
+    assert bench.kernel_source_digest() == d0
+    src.write_text("int f(int x) {\n  return x + 2;\n}\n")
+    assert bench.kernel_source_digest() != d0
