@@ -197,6 +197,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
   const int li = local / L, sub = local % L;
   const int i = doms[d].off + li;
   const bool active = li < doms[d].n;
+  __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
   const float sigma = sigma_of(sp, (float)*stepctr, metrics[(size_t)d * 32 + kAutoT0]);
   double part[12];
   double ifcp[1] = {0.0};
@@ -226,8 +227,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
     float wsum = 0.f, ax = 0.f, ay = 0.f, az = 0.f, A = 0.f, nn2 = INFINITY;
     uint32_t npair = 0, nifc = 0;
     const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
-    const uint32_t ncand = scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart,
-                                                 [&](uint32_t j, float dy0, float dz0, bool v) {
+    const auto body = [&](uint32_t j, float dy0, float dz0, bool v) {
       const float4 pj = buf_f4(rpos, j);
       const uint32_t aj = buf_u32(raux, j);
       const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
@@ -266,7 +266,9 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
       ay = fmaf(s, dy, ay);
       az = fmaf(s, dz, az);
       if constexpr (DBG) A = fmaf(s, r, A);        // sum of |pair terms| (debug export only)
-    });
+    };
+    const uint32_t ncand = scan_group_table<D, L, row_table_rows<L>(), PER>(
+        i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g, cellbase, cstart, body);
     wsum = group_sum<L>(wsum);
     ax = group_sum<L>(ax);
     ay = group_sum<L>(ay);
@@ -373,6 +375,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
   const float dt1 = read_dt1(dtslots + d * kDtSlots);
   const float hdt = 0.5f * dt1;
   const float dt2 = dt1 * sp.dt2_factor;
+  __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
   if (li < doms[d].n) {
     float bx = 0.f, by = 0.f, bz = 0.f;
     {
@@ -425,7 +428,8 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
           by = fmaf(s, viy - dyv, by);
           if constexpr (D == 3) bz = fmaf(s, viz - dzv, bz);
         };
-        scan_group<D, L, PER>(i, sub, ci, oi, rs, g, cellbase, cstart, body);
+        scan_group_table<D, L, row_table_rows<L>(), PER>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(),
+                                                          ci, oi, rs, g, cellbase, cstart, body);
       }
     }
     bx = group_sum<L>(bx);

@@ -1,5 +1,5 @@
-// Neighbour candidate scan and lane-group helpers shared by the forward pair passes and
-// their adjoints (gfx950, wave64).
+// Neighbour candidate scans and lane-group helpers of the pair passes, their adjoints and the
+// pair dump (gfx950, wave64).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -8,7 +8,8 @@
 
 namespace mpsph {
 
-// Neighbour candidates
+// Neighbour candidates (scan_group: the adjoints and the pair dump; the forward passes use
+// scan_group_table below, which visits the same candidates)
 //
 // Particle i's candidates are the particles of every x-run of cells (fixed y, z) that meets the
 // ball of radius rs around it, the run taken at x sub-cell resolution; in the cell order (x
@@ -160,6 +161,146 @@ __device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, co
       // slots past the end carry an index that may lie outside the arrays: bodies must load
       // through bounds-checked buffer loads or clamp it with the valid flag
       body(j, dy0, dz0, t < T && j != (uint32_t)i);
+    }
+  }
+  return total > 0u ? total - 1u : 0u;
+}
+
+// Rows per chunk of the LDS row table at 4 lanes per particle (scaled with the lanes, so that
+// the table of a 256-thread block stays near 16 KB and 8 blocks fit a CU's LDS).
+#ifndef MPSPH_ROW_TABLE
+#define MPSPH_ROW_TABLE 18
+#endif
+template <int L>
+constexpr int row_table_rows() {
+  return MPSPH_ROW_TABLE * L / 4 < L ? L : MPSPH_ROW_TABLE * L / 4;
+}
+// Entries between two rows of one group's column (one more than the groups of a block, so that
+// the columns of a wave's groups start in different banks).
+template <int L>
+constexpr int row_table_stride() {
+  return kBlock / L + 1;
+}
+
+// Candidate scan with a row table in LDS (the forward pair passes).
+//
+// The same candidates as scan_group, visited in one flattened loop per group: the group first
+// lays out its non-empty x-runs (rows) in a table in LDS (base index, end of the run in the
+// flattened slot order, row offsets), then visits the slots L at a time, each lane advancing
+// through the table as its slot index passes the end of a row.  Unlike scan_group, whose
+// groups advance row round by row round in step with the whole wave, a group's loop here
+// ends when its own candidates end.  A table holds at most C rows; a particle with more
+// non-empty rows is scanned in several chunks.
+// tab: the group's column of the table, entry e at tab[e * stride]; C >= L.
+// body and return value as in scan_group.
+template <int D, int L, int C, bool PER = false, typename BodyF>
+__device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab, int stride, const int *ci,
+                                                     const float *oi, float rs, const GridDev &g, uint32_t cellbase,
+                                                     const uint32_t *__restrict__ cstart, BodyF &&body) {
+  static_assert(C >= L, "a table chunk holds at least one round of rows");
+  rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
+  const float rs2 = rs * rs;
+  const bool per = PER && g.geometry == 0;
+  const int P = g.gmax + 1;
+  int z0 = D == 3 ? ci[2] + (int)floorf(oi[2] - rs) : 0;
+  int z1 = D == 3 ? ci[2] + (int)floorf(oi[2] + rs) : 0;
+  int y0 = ci[1] + (int)floorf(oi[1] - rs);
+  int y1 = ci[1] + (int)floorf(oi[1] + rs);
+  if (per) {
+    if (y1 - y0 + 1 > P) {
+      y0 = ci[1] - P / 2;
+      y1 = y0 + P - 1;
+    }
+    if (D == 3 && z1 - z0 + 1 > P) {
+      z0 = ci[2] - P / 2;
+      z1 = z0 + P - 1;
+    }
+  } else {
+    y0 = max(0, y0);
+    y1 = min(g.gmax, y1);
+    if (D == 3) {
+      z0 = max(0, z0);
+      z1 = min(g.gmax, z1);
+    }
+  }
+  const int ny = y1 - y0 + 1;
+  const int nrows = ny * (z1 - z0 + 1);
+  const float inv_ny = 1.f / (float)ny;
+  const uint32_t nmax = (uint32_t)g.n;
+  const float fx = (float)(1u << g.xe);
+  const int xlast = ((g.gmax + 1) << g.xe) - 1;
+  const uint32_t kx = g.k + g.xe;
+  uint32_t total = 0;   // candidates of the group, the particle itself included
+  int q0 = 0;
+  while (q0 < nrows) {
+    // table of the next chunk of rows: whole rounds of L rows while a round surely fits
+    uint32_t ne = 0, run = 0;
+    while (q0 < nrows && ne + L <= (uint32_t)C) {
+      const int q = q0 + sub;
+      const int qz = (int)(((float)q + 0.5f) * inv_ny);   // q / ny (q, ny < 2^12)
+      const int cz = z0 + qz, cy = y0 + (q - qz * ny);
+      float ez = 0.f;
+      if constexpr (D == 3) {
+        const float lo = (float)(cz - ci[2]) - oi[2], hi = lo + 1.f;
+        ez = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
+      }
+      const float lo = (float)(cy - ci[1]) - oi[1], hi = lo + 1.f;
+      const float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
+      const float d2 = ey * ey + ez * ez;
+      const bool hit = q < nrows && d2 < rs2;
+      const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
+      int x0 = (ci[0] << g.xe) + (int)floorf((oi[0] - wx) * fx);
+      int x1 = (ci[0] << g.xe) + (int)floorf((oi[0] + wx) * fx);
+      if (per && (x0 < 0 || x1 > xlast)) {
+        x0 = 0;
+        x1 = xlast;
+      }
+      x0 = max(0, x0);
+      x1 = min(xlast, x1);
+      const int cyw = per ? (cy + P) & g.gmax : cy;
+      uint32_t kb;
+      if constexpr (D == 3)
+        kb = (uint32_t)x0 | (row_index(cyw, per ? (cz + P) & g.gmax : cz, g) << kx);
+      else
+        kb = (uint32_t)x0 | ((uint32_t)cyw << kx);
+      kb += cellbase;
+      uint32_t a = 0u, b = 0u;
+      if (hit) {
+        a = cstart[kb];
+        b = min(cstart[kb + (uint32_t)(x1 - x0) + 1u], nmax);
+      }
+      const uint32_t len = b > a ? b - a : 0u;
+      // prefix sums over the group of the run lengths and of the non-empty flags
+      uint32_t incl = len, nz = len > 0u ? 1u : 0u;
+#pragma unroll
+      for (int o = 1; o < L; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, L), w = __shfl_up(nz, o, L);
+        if (sub >= o) {
+          incl += v;
+          nz += w;
+        }
+      }
+      if (len > 0u) {
+        const uint32_t end = run + incl;   // end of the row in the chunk's slot order
+        const float dyr = (float)(ci[1] - cy), dzr = D == 3 ? (float)(ci[2] - cz) : 0.f;
+        tab[(ne + nz - 1u) * (uint32_t)stride] =
+            make_uint4(a - (end - len), end, __float_as_uint(dyr), __float_as_uint(dzr));
+      }
+      run += __shfl(incl, L - 1, L);
+      ne += __shfl(nz, L - 1, L);
+      q0 += L;
+    }
+    total += run;
+    // the chunk's slots, L at a time; slot t of row e is candidate base_e + t
+    uint32_t e = 0;
+    uint4 cur = tab[0];
+    for (uint32_t t0 = 0; t0 < run; t0 += L) {
+      const uint32_t t = t0 + (uint32_t)sub;
+      while (t >= cur.y && e + 1u < ne) cur = tab[++e * (uint32_t)stride];
+      const uint32_t j = cur.x + t;
+      // slots past the end carry an index that may lie outside the arrays: bodies must load
+      // through bounds-checked buffer loads or clamp it with the valid flag
+      body(j, __uint_as_float(cur.z), __uint_as_float(cur.w), t < run && j != (uint32_t)i);
     }
   }
   return total > 0u ? total - 1u : 0u;
