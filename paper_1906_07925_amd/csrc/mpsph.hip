@@ -1183,6 +1183,58 @@ FeatureList feature_integrals(const mpsph_params *p) {
 }
 
 // Bounds of s over the bounding box, and a Lipschitz constant of s (domain units).
+// Bounds of the RBF field s = s0 exp(f), f(x) = sum_k c_k G_k(x), G_k = exp(-|x - x_k|^2 / (2 w^2)),
+// over the box: the extremes of f and of |grad f| sampled on a grid, widened by what the
+// derivative bounds allow between grid points (|grad G| <= 1 / (w sqrt(e)) and |hess G| <= 1 / w^2
+// everywhere, so |grad f| <= Lf = sum |c_k| / (w sqrt(e)) and |hess f| <= Hf = sum |c_k| / w^2; a
+// point of the box lies within rho, half the grid cell's diagonal, of a grid node).  Each bound
+// is also capped by its grid-free form.  The Lipschitz constant of s is smax * max |grad f|.
+void rbf_bounds(const mpsph_params *p, double s0, double *smin, double *smax, double *lip) {
+  const int d = p->dim, nr = p->n_rbf;
+  const double w = p->rbf_width;
+  double pos = 0, neg = 0, abs_sum = 0;
+  for (int k = 0; k < nr; ++k) {
+    pos += std::max(p->rbf_coeff[k], 0.0);
+    neg += std::min(p->rbf_coeff[k], 0.0);
+    abs_sum += std::fabs(p->rbf_coeff[k]);
+  }
+  const double Lf = abs_sum / (w * std::exp(0.5)), Hf = abs_sum / (w * w);
+  const int m = d == 3 ? 64 : 256;   // grid nodes per axis
+  double step[3] = {0, 0, 0}, rho2 = 0;
+  for (int a = 0; a < d; ++a) {
+    step[a] = (p->hi[a] - p->lo[a]) / (m - 1);
+    rho2 += 0.25 * step[a] * step[a];
+  }
+  const double rho = std::sqrt(rho2), inv2w2 = 1.0 / (2.0 * w * w);
+  double fmax = -INFINITY, fmin = INFINITY, gmax = 0;
+  const int mz = d == 3 ? m : 1;
+  for (int iz = 0; iz < mz; ++iz)
+    for (int iy = 0; iy < m; ++iy)
+      for (int ix = 0; ix < m; ++ix) {
+        const double x[3] = {p->lo[0] + ix * step[0], p->lo[1] + iy * step[1], d == 3 ? p->lo[2] + iz * step[2] : 0.0};
+        double f = 0, g[3] = {0, 0, 0};
+        for (int k = 0; k < nr; ++k) {
+          double dv[3] = {0, 0, 0}, r2 = 0;
+          for (int a = 0; a < d; ++a) {
+            dv[a] = x[a] - p->rbf_centre[k * d + a];
+            r2 += dv[a] * dv[a];
+          }
+          const double t = p->rbf_coeff[k] * std::exp(-r2 * inv2w2);
+          f += t;
+          for (int a = 0; a < d; ++a) g[a] -= t * dv[a] / (w * w);
+        }
+        fmax = std::max(fmax, f);
+        fmin = std::min(fmin, f);
+        gmax = std::max(gmax, std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]));
+      }
+  fmax = std::min(pos, fmax + Lf * rho);
+  fmin = std::max(neg, fmin - Lf * rho);
+  gmax = std::min(Lf, gmax + Hf * rho);
+  *smin = s0 * std::exp(fmin);
+  *smax = s0 * std::exp(fmax);
+  *lip = *smax * gmax;
+}
+
 bool spacing_bounds(const mpsph_params *p, double s0, double *smin, double *smax, double *lip) {
   if (p->field == MPSPH_GRID) {
     // the interpolant stays within the node extremes; its slope along an axis is bounded by the
@@ -1234,17 +1286,8 @@ bool spacing_bounds(const mpsph_params *p, double s0, double *smin, double *smax
       *lip = s0 * std::fabs(p->fa);
       break;
     }
-    default: {
-      double pos = 0, neg = 0, abs_sum = 0;
-      for (int k = 0; k < p->n_rbf; ++k) {
-        pos += std::max(p->rbf_coeff[k], 0.0);
-        neg += std::min(p->rbf_coeff[k], 0.0);
-        abs_sum += std::fabs(p->rbf_coeff[k]);
-      }
-      *smin = s0 * std::exp(neg);
-      *smax = s0 * std::exp(pos);
-      *lip = *smax * abs_sum / (p->rbf_width * std::exp(0.5));
-    }
+    default:
+      rbf_bounds(p, s0, smin, smax, lip);
   }
   return *smin > 0 && std::isfinite(*smax);
 }
