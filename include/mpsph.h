@@ -158,6 +158,16 @@ typedef struct {
  * quadrature; params->s0 is ignored.  Errors: MPSPH_E_INVALID for bad params or n <= 0. */
 MPSPH_API int mpsph_field_scale(const mpsph_params *params, int64_t n, double *s0_out);
 
+/* Bounds of the target size field over the region's box that the neighbour search relies on
+ * (§3.3: the cut-off r_c = kappa h, h = tau s, Eq. 16): out[0] = s0 (as mpsph_create normalises
+ * it for n particles, or params->s0 when that is positive), out[1] = s_min, out[2] = s_max and
+ * out[3] = a Lipschitz constant of s (domain units).  A pair can interact only within
+ * kappa (h_i + h_j) / 2 and h_j <= h_i + tau L r, so these bounds fix the search radius and the
+ * default cell size.  For the RBF field they come from the field sampled on a grid, widened by
+ * its derivative bounds between nodes.  Host-only; no device.  Errors: MPSPH_E_INVALID for bad
+ * params or n <= 0. */
+MPSPH_API int mpsph_field_bounds(const mpsph_params *params, int64_t n, double *out);
+
 /* Particle budget of a region whose boundary features carry their own particles (§2.3, Eq. 4-6,
  * with unit particle mass, Eq. 15, so that the particle count equals the total mass M_t).
  *

@@ -1184,11 +1184,12 @@ FeatureList feature_integrals(const mpsph_params *p) {
 
 // Bounds of s over the bounding box, and a Lipschitz constant of s (domain units).
 // Bounds of the RBF field s = s0 exp(f), f(x) = sum_k c_k G_k(x), G_k = exp(-|x - x_k|^2 / (2 w^2)),
-// over the box: the extremes of f and of |grad f| sampled on a grid, widened by what the
-// derivative bounds allow between grid points (|grad G| <= 1 / (w sqrt(e)) and |hess G| <= 1 / w^2
-// everywhere, so |grad f| <= Lf = sum |c_k| / (w sqrt(e)) and |hess f| <= Hf = sum |c_k| / w^2; a
-// point of the box lies within rho, half the grid cell's diagonal, of a grid node).  Each bound
-// is also capped by its grid-free form.  The Lipschitz constant of s is smax * max |grad f|.
+// over the box, from f and grad f on a grid: every point of the box lies within rho (half a grid
+// cell's diagonal) of a node n, and |hess G| <= 1 / w^2 everywhere, so with Hf = sum |c_k| / w^2
+//   f(x) <= f(n) + |grad f(n)| rho + Hf rho^2 / 2   (Taylor), likewise for the minimum, and
+//   |grad f(x)| <= |grad f(n)| + Hf rho.
+// Each bound is also capped by its grid-free form (sum of the positive / negative c_k, and
+// |grad f| <= sum |c_k| / (w sqrt(e))).  The Lipschitz constant of s is smax * max |grad f|.
 void rbf_bounds(const mpsph_params *p, double s0, double *smin, double *smax, double *lip) {
   const int d = p->dim, nr = p->n_rbf;
   const double w = p->rbf_width;
@@ -1223,12 +1224,14 @@ void rbf_bounds(const mpsph_params *p, double s0, double *smin, double *smax, do
           f += t;
           for (int a = 0; a < d; ++a) g[a] -= t * dv[a] / (w * w);
         }
-        fmax = std::max(fmax, f);
-        fmin = std::min(fmin, f);
-        gmax = std::max(gmax, std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]));
+        const double gn = std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        const double reach = gn * rho + 0.5 * Hf * rho * rho;
+        fmax = std::max(fmax, f + reach);
+        fmin = std::min(fmin, f - reach);
+        gmax = std::max(gmax, gn);
       }
-  fmax = std::min(pos, fmax + Lf * rho);
-  fmin = std::max(neg, fmin - Lf * rho);
+  fmax = std::min(pos, fmax);
+  fmin = std::max(neg, fmin);
   gmax = std::min(Lf, gmax + Hf * rho);
   *smin = s0 * std::exp(fmin);
   *smax = s0 * std::exp(fmax);
@@ -2406,6 +2409,23 @@ int mpsph_field_scale(const mpsph_params *params, int64_t n, double *s0_out) {
   double I = field_integral_unit(params);
   if (!(I > 0) || !std::isfinite(I)) return MPSPH_E_INVALID;
   *s0_out = std::pow(I / (double)n, 1.0 / params->dim);
+  return MPSPH_OK;
+}
+
+int mpsph_field_bounds(const mpsph_params *params, int64_t n, double *out) {
+  if (!valid_params(params) || n <= 0 || !out) return MPSPH_E_INVALID;
+  double s0 = params->s0;
+  if (!(s0 > 0)) {
+    const double I = field_integral_unit(params);
+    if (!(I > 0) || !std::isfinite(I)) return MPSPH_E_INVALID;
+    s0 = std::pow(I / (double)n, 1.0 / params->dim);
+  }
+  double smin, smax, lip;
+  if (!spacing_bounds(params, s0, &smin, &smax, &lip)) return MPSPH_E_INVALID;
+  out[0] = s0;
+  out[1] = smin;
+  out[2] = smax;
+  out[3] = lip;
   return MPSPH_OK;
 }
 

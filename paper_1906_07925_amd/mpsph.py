@@ -79,6 +79,7 @@ def lib():
         P, V, I32, I64 = C.POINTER(Params), C.c_void_p, C.c_int32, C.c_int64
         sig = {
             "mpsph_field_scale": (C.c_int, [P, I64, C.POINTER(C.c_double)]),
+            "mpsph_field_bounds": (C.c_int, [P, I64, C.POINTER(C.c_double)]),
             "mpsph_feature_budget": (C.c_int, [P, I64, C.POINTER(Features)]),
             "mpsph_workspace_bytes": (C.c_size_t, [P, I64]),
             "mpsph_batch_workspace_bytes": (C.c_size_t, [I32, P, C.POINTER(I64)]),
@@ -181,6 +182,15 @@ def field_scale(spec: dict, n: int) -> float:
     out = C.c_double(0.0)
     _check(lib().mpsph_field_scale(C.byref(p), int(n), C.byref(out)), "mpsph_field_scale")
     return out.value
+
+
+def field_bounds(spec: dict, n: int) -> dict:
+    """Bounds of the size field the neighbour search relies on (mpsph_field_bounds): s0, s_min,
+    s_max and a Lipschitz constant of s, domain units."""
+    p, keep = make_params(spec)
+    out = (C.c_double * 4)()
+    _check(lib().mpsph_field_bounds(C.byref(p), int(n), out), "mpsph_field_bounds")
+    return dict(s0=out[0], smin=out[1], smax=out[2], lip=out[3])
 
 
 def feature_budget(spec: dict, n: int) -> dict:
