@@ -98,6 +98,19 @@ __device__ __forceinline__ float field_grad(const FieldDev &f, const int *c, con
   return s;
 }
 
+// Minimum of non-negative floats over the block into *dst: one atomic per block.
+__device__ __forceinline__ void block_min_atomic(float v, uint32_t *dst) {
+  __shared__ float wmin[kBlock / kWave];
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) wmin[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = wmin[0];
+    for (int w = 1; w < kBlock / kWave; ++w) m = fminf(m, wmin[w]);
+    if (m < INFINITY) atomic_min_pos(dst, m);
+  }
+}
+
 // Resets the per-step scalars: minimum time-step bits, index attaining it.
 __global__ void adj_init(uint32_t *minbits, uint32_t *argmin) {
   *minbits = kInfBits;
@@ -121,6 +134,7 @@ __global__ __launch_bounds__(kBlock) void adj_drift(const DomDev *__restrict__ d
   const float dt2 = dt1 * sp.dt2_factor;
   double part[1] = {0.0};
   const int ops[1] = {0};
+  float c1 = INFINITY;   // the particle's candidate of T1
   if (i < dom->n) {
     int ci[3];
     unpack_key<D>(tp.wkey[i], g, ci);
@@ -161,11 +175,10 @@ __global__ __launch_bounds__(kBlock) void adj_drift(const DomDev *__restrict__ d
     // candidate of the first time step (as in the forward pass, from the stored a)
     const float4 a4 = tp.acc[i];
     const float am2 = a4.x * a4.x + a4.y * a4.y + (D == 3 ? a4.z * a4.z : 0.f);
-    float c1 = INFINITY;
     if (ti != 3 && am2 > 0.f) c1 = sp.c_acc * sqrtf(sp.kappa * pi.w * fast_rsq(am2));
     dtc[i] = c1;
-    if (c1 < INFINITY) atomic_min_pos(minbits, c1);
   }
+  block_min_atomic(c1, minbits);
   block_reduce_write<1>(part, ops, partials + (size_t)blockIdx.x * kNumPartials);
 }
 
@@ -185,6 +198,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
   const StepDev &sp = dom->sp;
   const int local = lb * kBlock + threadIdx.x;
   const int i = local / L, sub = local % L;
+  __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
   const float dt1 = read_dt1(tp.dts);
   const float hdt = 0.5f * dt1;
   double part[1] = {0.0};
@@ -206,7 +220,8 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
     float vb[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, eb = 0.f, sb = 0.f;
     if (ei > 0.f) {
       const BufRes rpos = buf_res(tp.wpos, 16, (uint32_t)g.n), raux = buf_res(tp.wjaux, 4, (uint32_t)g.n);
-      scan_group<D, L>(i, sub, ci, oi, rs, g, 0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
+      scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
+                                                 0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
         const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
         const float4 pj = buf_f4(rpos, jr);
         const uint32_t aj = buf_u32(raux, jr);
@@ -358,6 +373,7 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
   const StepDev &sp = dom->sp;
   const int local = lb * kBlock + threadIdx.x;
   const int i = local / L, sub = local % L;
+  __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
   if (i >= dom->n) return;
   int ci[3];
   unpack_key<D>(tp.wkey[i], g, ci);
@@ -375,7 +391,8 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
   const float opb = 1.f + sigma_of(sp, tstep);   // surface tension of the step (Eq. 24-25)
   float xb[3] = {0.f, 0.f, 0.f}, sb = 0.f;
   const BufRes rpos = buf_res(tp.wpos, 16, (uint32_t)g.n), raux = buf_res(tp.wjaux, 4, (uint32_t)g.n);
-  scan_group<D, L>(i, sub, ci, oi, rs, g, 0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
+  scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
+                                                 0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
     const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
     const float4 pj = buf_f4(rpos, jr);
     const uint32_t aj = buf_u32(raux, jr);
@@ -472,14 +489,23 @@ __global__ __launch_bounds__(kBlock) void adj_field(const DomDev *__restrict__ d
   }
 }
 
-// c-bar[m] += sum over blocks of cpart (fixed order, one block of 64 threads per 64 terms).
-__global__ __launch_bounds__(kMaxRbf) void adj_sum_coeff(const double *__restrict__ cpart, int nblocks, int n_rbf,
-                                                         double *__restrict__ cbar) {
-  const int m = threadIdx.x;
-  if (m >= n_rbf) return;
+// c-bar[m] += sum over blocks of cpart[b][m]: one block per coefficient, each thread summing
+// every 256th block partial in order, then a fixed tree over the threads (deterministic).
+constexpr int kCoeffSumThreads = 256;
+__global__ __launch_bounds__(kCoeffSumThreads) void adj_sum_coeff(const double *__restrict__ cpart, int nblocks,
+                                                                  int n_rbf, double *__restrict__ cbar) {
+  __shared__ double red[kCoeffSumThreads];
+  const int m = blockIdx.x;
+  if (m >= n_rbf) return;  // block-uniform
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += cpart[(size_t)b * kMaxRbf + m];
-  cbar[m] += s;
+  for (int b = threadIdx.x; b < nblocks; b += kCoeffSumThreads) s += cpart[(size_t)b * kMaxRbf + m];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kCoeffSumThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cbar[m] += red[0];
 }
 
 // Loss, first pass (L lanes per particle, sorted order of the final state):
@@ -496,6 +522,7 @@ __global__ __launch_bounds__(kBlock) void loss_density(const DomDev *__restrict_
   const StepDev &sp = dom->sp;
   const int local = lb * kBlock + threadIdx.x;
   const int i = local / L, sub = local % L;
+  __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
   double part[2] = {0.0, 0.0};
   const int ops[2] = {0, 0};
   if (i < dom->n) {
@@ -510,7 +537,8 @@ __global__ __launch_bounds__(kBlock) void loss_density(const DomDev *__restrict_
     const float kh = 0.5f * sp.kappa;
     float ws = 0.f, wi = 0.f;
     const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
-    scan_group<D, L>(i, sub, ci, oi, rs, g, 0u, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
+    scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
+                                                 0u, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
       // jr lies past the arrays for invalid slots: bounds-checked loads first
       const float4 pj = buf_f4(rpos, jr);
       const uint32_t aj = buf_u32(raux, jr);
@@ -562,6 +590,7 @@ __global__ __launch_bounds__(kBlock) void loss_grad(const DomDev *__restrict__ d
   const StepDev &sp = dom->sp;
   const int local = lb * kBlock + threadIdx.x;
   const int i = local / L, sub = local % L;
+  __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
   if (i >= dom->n) return;
   int ci[3];
   unpack_key<D>(wkey[i], g, ci);
@@ -575,7 +604,8 @@ __global__ __launch_bounds__(kBlock) void loss_grad(const DomDev *__restrict__ d
   const float kh = 0.5f * sp.kappa;
   float xb[3] = {0.f, 0.f, 0.f}, sb = 0.f;
   const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
-  scan_group<D, L>(i, sub, ci, oi, rs, g, 0u, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
+  scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
+                                                 0u, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
     const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
     const float4 pj = buf_f4(rpos, jr);
     const uint32_t aj = buf_u32(raux, jr);

@@ -2282,7 +2282,8 @@ int loss_backward(GradRun &R, double lam) {
   adj_field<D><<<R.nb1, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar),
                                            R.at<float4>(R.P.xbar), R.at<double>(R.P.cpart));
   if (dm.p.field == MPSPH_RBF_EXP && dm.p.n_rbf > 0)
-    adj_sum_coeff<<<1, kMaxRbf, 0, R.st>>>(R.at<double>(R.P.cpart), R.nb1, dm.p.n_rbf, R.at<double>(R.P.cbar));
+    adj_sum_coeff<<<std::max(dm.p.n_rbf, 1), kCoeffSumThreads, 0, R.st>>>(R.at<double>(R.P.cpart), R.nb1, dm.p.n_rbf,
+                                                                        R.at<double>(R.P.cbar));
   HIP_OK(hipGetLastError());
   return MPSPH_OK;
 }
@@ -2316,7 +2317,8 @@ int step_backward(GradRun &R, int m, int64_t t) {
   adj_field<D><<<R.nb1, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar),
                                            R.at<float4>(R.P.xbar), R.at<double>(R.P.cpart));
   if (dm.p.field == MPSPH_RBF_EXP && dm.p.n_rbf > 0)
-    adj_sum_coeff<<<1, kMaxRbf, 0, R.st>>>(R.at<double>(R.P.cpart), R.nb1, dm.p.n_rbf, R.at<double>(R.P.cbar));
+    adj_sum_coeff<<<std::max(dm.p.n_rbf, 1), kCoeffSumThreads, 0, R.st>>>(R.at<double>(R.P.cpart), R.nb1, dm.p.n_rbf,
+                                                                        R.at<double>(R.P.cbar));
   HIP_OK(hipGetLastError());
   return MPSPH_OK;
 }
