@@ -25,8 +25,9 @@ namespace mpsph {
 // may carry an index outside the arrays.  The return value is the group's candidate count
 // (the particle itself excluded), the same in every lane of the group.
 // ------------------------------------------------------------------------------------------
-// Lanes per particle in the pair kernels (measured on the 2M-particle graded cube: 4 is the
-// fastest of 1, 2, 4, 8, 16, 32).
+// Lanes per particle of the pair kernels of a context that is not tuned (mpsph_configure and
+// mpsph_autotune choose 2, 4 or 8) and of the adjoint kernels.  Measured: 8 lanes are the fastest
+// on the 2M-particle graded cube, 4 on the 64-domain batch and on the RBF cube's gradient.
 #ifndef MPSPH_LANES
 #define MPSPH_LANES 4
 #endif
