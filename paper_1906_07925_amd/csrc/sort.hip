@@ -2,16 +2,24 @@
 //
 // One pass over a digit of up to 8 bits is three kernels:
 //   radix_hist    per-tile digit histograms (LDS counters)            -> hist[tile][digit]
-//   radix_scan    exclusive offsets in (digit, tile) order, in place  (one workgroup)
-//   radix_scatter stable ranking inside the tile (wave ballots + per-wave counts in LDS) and
-//                 scatter to hist offsets.
+//   radix_scan    per digit (one workgroup each): exclusive offsets over the tiles, in place,
+//                 and the digit's total                               -> dsum[digit]
+//   radix_scatter digit bases from the totals, stable ranking inside the tile (wave ballots +
+//                 per-wave counts in LDS) and scatter to base + tile offset.
 // The order of equal keys is the input order, so the permutation is deterministic.
 #include "sort.h"
+
+#include <algorithm>
 
 namespace mpsph {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+// Keys per thread of a tile (measured on 2M keys: 16 beats 8 and 4, whose extra tiles cost the
+// scan and the scatter more than their shorter ranking loops save).
+#ifndef MPSPH_SORT_ITEMS
+#define MPSPH_SORT_ITEMS 16
+#endif
+constexpr int kSortItems = MPSPH_SORT_ITEMS;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
 __global__ __launch_bounds__(kSortThreads) void radix_hist(const uint32_t *__restrict__ keys, int n,
@@ -32,81 +40,70 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist(const uint32_t *__res
   for (int t = threadIdx.x; t < radix; t += kSortThreads) hist[(size_t)blockIdx.x * radix + t] = cnt[t];
 }
 
-// Exclusive scan of hist[tile][digit] in digit-major order: offset(d, b) = sum of all counts of
-// digits < d plus counts of digit d in tiles < b.  One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void radix_scan(uint32_t *__restrict__ hist, int ntiles, int bits) {
-  __shared__ uint32_t part[1024];
-  __shared__ uint32_t dig_off[256];
+// Exclusive scan over the tiles of one digit's column of hist (one workgroup per digit), in
+// place, and the digit's total into dsum[digit].  Thread t takes a contiguous run of tiles.
+__global__ __launch_bounds__(kSortThreads) void radix_scan(uint32_t *__restrict__ hist, int ntiles, int bits,
+                                                         uint32_t *__restrict__ dsum) {
+  __shared__ uint32_t wsum[kSortThreads / 64];
   const int radix = 1 << bits;
-  const int nparts = 1024 / radix;
-  const int d = threadIdx.x % radix, p = threadIdx.x / radix;
-  const int per = (ntiles + nparts - 1) / nparts;
-  const int b0 = p * per, b1 = min(ntiles, b0 + per);
+  const int d = blockIdx.x;
+  const int per = (ntiles + kSortThreads - 1) / kSortThreads;
+  const int b0 = min(ntiles, (int)threadIdx.x * per), b1 = min(ntiles, b0 + per);
   uint32_t s = 0;
-  if (p < nparts) {
-    // independent loads in flight (the tile sums are order-free integers)
-#pragma unroll 8
-    for (int b = b0; b < b1; ++b) s += hist[(size_t)b * radix + d];
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x < radix) {
-    uint32_t run = 0;
-    for (int q = 0; q < nparts; ++q) {
-      uint32_t t = part[q * radix + threadIdx.x];
-      part[q * radix + threadIdx.x] = run;
-      run += t;
-    }
-    dig_off[threadIdx.x] = run;  // digit total for now
-  }
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    // exclusive scan of the (at most 256) digit totals by one wave: 4 per lane, then the lanes
-    const int l = threadIdx.x;
-    uint32_t v[4], tot = 0;
+  for (int b = b0; b < b1; ++b) s += hist[(size_t)b * radix + d];
+  // exclusive prefix of the thread sums: within the wave, then over the waves
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t incl = s;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = 4 * l + q;
-      v[q] = t < radix ? dig_off[t] : 0u;
-      tot += v[q];
-    }
-    uint32_t incl = tot;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t u = __shfl_up(incl, o, 64);
-      if (l >= o) incl += u;
-    }
-    uint32_t run = incl - tot;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = 4 * l + q;
-      if (t < radix) dig_off[t] = run;
-      run += v[q];
-    }
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += u;
   }
+  if (lane == 63) wsum[w] = incl;
   __syncthreads();
-  if (p < nparts) {
-    uint32_t run = dig_off[d] + part[threadIdx.x];
-    // the loads do not depend on the running offset: the compiler can issue them ahead
-#pragma unroll 8
-    for (int b = b0; b < b1; ++b) {
-      uint32_t t = hist[(size_t)b * radix + d];
-      hist[(size_t)b * radix + d] = run;
-      run += t;
-    }
+  uint32_t run = incl - s;
+  for (int ww = 0; ww < w; ++ww) run += wsum[ww];
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t t = hist[(size_t)b * radix + d];
+    hist[(size_t)b * radix + d] = run;
+    run += t;
   }
+  if (threadIdx.x == kSortThreads - 1) dsum[d] = run;
 }
 
 __global__ __launch_bounds__(kSortThreads) void radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, int n, int shift, int bits, const uint32_t *__restrict__ offs) {
+    uint32_t *__restrict__ vout, int n, int shift, int bits, const uint32_t *__restrict__ offs,
+    const uint32_t *__restrict__ dsum) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[kSortThreads / 64][256];
   const int radix = 1 << bits;
   const uint32_t mask = (uint32_t)radix - 1u;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  for (int t = threadIdx.x; t < radix; t += kSortThreads) run[t] = offs[(size_t)blockIdx.x * radix + t];
+  if (threadIdx.x < 64) {
+    // digit bases: exclusive prefix of the (at most 256) digit totals, 4 per lane
+    uint32_t v[4], tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = 4 * lane + q;
+      v[q] = t < radix ? dsum[t] : 0u;
+      tot += v[q];
+    }
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t u = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += u;
+    }
+    uint32_t b = incl - tot;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = 4 * lane + q;
+      if (t < radix) run[t] = b + offs[(size_t)blockIdx.x * radix + t];
+      b += v[q];
+    }
+  }
   const int base = blockIdx.x * kSortTile;
   for (int it = 0; it < kSortItems; ++it) {
     for (int t = threadIdx.x; t < (kSortThreads / 64) * radix; t += kSortThreads) wcnt[t / radix][t % radix] = 0;
@@ -144,7 +141,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(
 
 size_t radix_hist_words(int n) {
   int tiles = (n + kSortTile - 1) / kSortTile;
-  return (size_t)(tiles > 0 ? tiles : 1) * 256;
+  return (size_t)(tiles > 0 ? tiles : 1) * 256 + 256;   // tile histograms, then the digit totals
 }
 
 int radix_passes(int key_bits) { return key_bits <= 0 ? 0 : (key_bits + 7) / 8; }
@@ -154,6 +151,7 @@ hipError_t radix_sort(const uint32_t *keys_in, uint32_t *k0, uint32_t *v0, uint3
                       const uint32_t **keys_out, const uint32_t **perm_out, LaunchHook *hook) {
   const int passes = radix_passes(key_bits);
   const int tiles = (n + kSortTile - 1) / kSortTile;
+  uint32_t *dsum = hist + (size_t)std::max(tiles, 1) * 256;
   const uint32_t *kin = keys_in, *vin = nullptr;
   uint32_t *ko[2] = {k0, k1}, *vo[2] = {v0, v1};
   int shift = 0;
@@ -164,10 +162,10 @@ hipError_t radix_sort(const uint32_t *keys_in, uint32_t *k0, uint32_t *v0, uint3
     radix_hist<<<tiles, kSortThreads, 0, stream>>>(kin, n, shift, bits, hist);
     if (hook) hook->end();
     if (hook) hook->begin("radix_scan");
-    radix_scan<<<1, 1024, 0, stream>>>(hist, tiles, bits);
+    radix_scan<<<1 << bits, kSortThreads, 0, stream>>>(hist, tiles, bits, dsum);
     if (hook) hook->end();
     if (hook) hook->begin("radix_scatter");
-    radix_scatter<<<tiles, kSortThreads, 0, stream>>>(kin, vin, ko[p & 1], vo[p & 1], n, shift, bits, hist);
+    radix_scatter<<<tiles, kSortThreads, 0, stream>>>(kin, vin, ko[p & 1], vo[p & 1], n, shift, bits, hist, dsum);
     if (hook) hook->end();
     kin = ko[p & 1];
     vin = vo[p & 1];
