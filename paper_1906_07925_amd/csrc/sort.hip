@@ -4,8 +4,9 @@
 //   radix_hist    per-tile digit histograms (LDS counters)            -> hist[tile][digit]
 //   radix_scan    per digit (one workgroup each): exclusive offsets over the tiles, in place,
 //                 and the digit's total                               -> dsum[digit]
-//   radix_scatter digit bases from the totals, stable ranking inside the tile (wave ballots +
-//                 per-wave counts in LDS) and scatter to base + tile offset.
+//   radix_scatter digit bases from the totals; every key of the tile ranked among the keys of its
+//                 wave and item with the same digit (wave ballots), the (item, wave) counts turned
+//                 into tile offsets per digit in LDS, and each key scattered to base + offset + rank.
 // The order of equal keys is the input order, so the permutation is deterministic.
 #include "sort.h"
 
@@ -75,8 +76,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     uint32_t *__restrict__ vout, int n, int shift, int bits, const uint32_t *__restrict__ offs,
     const uint32_t *__restrict__ dsum) {
+  constexpr int kW = kSortThreads / 64;
   __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[kSortThreads / 64][256];
+  // per (item, wave) row and digit: the count of the wave's keys with that digit in that item,
+  // then their offset in the tile (below 2^16: a tile holds kSortTile keys)
+  __shared__ uint16_t cnt[kSortItems * kW][256];
   const int radix = 1 << bits;
   const uint32_t mask = (uint32_t)radix - 1u;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -104,38 +108,53 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(
       b += v[q];
     }
   }
+  uint32_t *cnt32 = reinterpret_cast<uint32_t *>(&cnt[0][0]);
+  for (int t = threadIdx.x; t < kSortItems * kW * 128; t += kSortThreads) cnt32[t] = 0u;
   const int base = blockIdx.x * kSortTile;
+  uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+#pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
-    for (int t = threadIdx.x; t < (kSortThreads / 64) * radix; t += kSortThreads) wcnt[t / radix][t % radix] = 0;
-    __syncthreads();
     const int idx = base + it * kSortThreads + threadIdx.x;
     const bool valid = idx < n;
-    uint32_t key = valid ? kin[idx] : 0u;
-    uint32_t dig = (key >> shift) & mask;
+    key[it] = valid ? kin[idx] : 0u;
+    val[it] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
+  }
+  __syncthreads();
+  // rank every key among the keys of its wave and item with the same digit
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const bool valid = base + it * kSortThreads + (int)threadIdx.x < n;
+    const uint32_t dig = (key[it] >> shift) & mask;
     uint64_t same = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
-      bool bit = (dig >> b) & 1u;
-      uint64_t bal = __ballot(bit);
+      const bool bit = (dig >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
       same &= bit ? bal : ~bal;
     }
-    uint32_t rank = (uint32_t)__popcll(same & lt);
-    if (valid && rank == 0) wcnt[w][dig] = (uint32_t)__popcll(same);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[dig] + rank;
-      for (int ww = 0; ww < w; ++ww) pos += wcnt[ww][dig];
+    rank[it] = (uint32_t)__popcll(same & lt);
+    if (valid && rank[it] == 0u) cnt[it * kW + w][dig] = (uint16_t)__popcll(same);
+  }
+  __syncthreads();
+  // per digit, offsets of the (item, wave) groups in input order
+  for (int d = threadIdx.x; d < radix; d += kSortThreads) {
+    uint32_t s = 0;
+    for (int q = 0; q < kSortItems * kW; ++q) {
+      const uint32_t c = cnt[q][d];
+      cnt[q][d] = (uint16_t)s;
+      s += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    if (base + it * kSortThreads + (int)threadIdx.x < n) {
+      const uint32_t dig = (key[it] >> shift) & mask;
+      const uint32_t pos = run[dig] + cnt[it * kW + w][dig] + rank[it];
       if (pos < (uint32_t)n) {
-        kout[pos] = key;
-        vout[pos] = vin ? vin[idx] : (uint32_t)idx;
+        kout[pos] = key[it];
+        vout[pos] = val[it];
       }
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < radix; t += kSortThreads) {
-      uint32_t s = 0;
-      for (int ww = 0; ww < kSortThreads / 64; ++ww) s += wcnt[ww][t];
-      run[t] += s;
-    }
-    __syncthreads();
   }
 }
 
