@@ -364,6 +364,35 @@ def test_configured_lanes_keep_the_step(torch_cuda, lanes):
     assert abs(m["pairs"] - r["pairs"]) <= r["band_pairs"]
 
 
+@pytest.mark.parametrize("lanes", [2, 4, 8])
+def test_row_table_chunks_keep_the_step(torch_cuda, lanes):
+    """Cells four times finer than the size rule put ~100 non-empty rows around each particle,
+    more than one chunk of the pair passes' LDS row table holds at any lane count (at most 36
+    rows): the chunked scan must still visit every candidate once."""
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    cfg = W.config("cube_inclusion_2m", scale=0.008)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    R = M.Relaxer(spec, n=x32.shape[0], s0=s0, debug=True)
+    k = R.cell_log2() + 2
+    R.configure(k, lanes)
+    op, _, _, r = PU.oracle_step(spec, s0, x32, col, typ)
+    _, h = O.field(op, x32.astype(np.float64))
+    radius_cells = op.p.kappa * h * (2 ** k - 1)          # unit cube: cell side 1 / (2^k - 1)
+    assert np.median(np.pi * (radius_cells + 0.5) ** 2) > 2 * 36
+    R.load(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    R.step(1)
+    a = R.field("a").cpu().numpy().astype(np.float64)
+    rho = R.field("rho").cpu().numpy().astype(np.float64)
+    m = R.metrics()
+    R.close()
+    assert np.max(np.abs(rho - r["rho"]) / r["rho"]) <= 1e-5
+    assert PU.rel(a, r["a"]) <= 1e-5
+    assert abs(m["pairs"] - r["pairs"]) <= r["band_pairs"]
+
+
 def test_automatic_t0(torch_cuda):
     """Automatic t0 (t0 = -2): the device detects the first step at which the interface-pair
     count and the number of interface particles have stayed within t0_tol of a reference for
