@@ -25,7 +25,9 @@
 //   reorder_field   gather the state in key order, evaluate the target field (Eq. 1-2, 16), fill
 //                   the cell table
 //   pass_density_force  density (Eq. 17), pressure + surface tension (Eq. 18-19, 23-25),
-//                   projection (Eq. 30-31), first time step (Eq. 29, block minima)
+//                   projection (Eq. 30-31), first time step (Eq. 29, block minima); like the
+//                   viscous pass, a lane group per particle walks its candidates through a row
+//                   table in LDS (scan_group_table in pair_scan.h)
 //   pass_viscous_integrate  mid-point velocity (Eq. 26), viscosity (Eq. 21-22), viscous
 //                   acceleration (Eq. 20), second time step (Eq. 29), velocity (Eq. 27), drift
 //                   (Eq. 28), feature projection and re-tagging (Eq. 32)
