@@ -26,9 +26,9 @@
 #include "mpsph_device.h"
 #include "pair_scan.h"
 
-// Waves per SIMD the viscous adjoint is compiled for; 0 leaves it to the compiler (5 waves at 93
-// VGPRs in 3D).  7 waves spill 40 bytes per lane yet make the reverse sweep 3 % faster on the
-// 2^20-particle RBF cube.
+// Waves per SIMD the viscous adjoint is compiled for; 0 leaves it to the compiler (5 waves in 3D).
+// 7 waves spill 68 bytes per lane yet make the reverse sweep of the 2^20-particle RBF cube about
+// 1 % faster than 6 waves or the compiler's choice (118.8 / 119.3 / 120.0 ms).
 #ifndef MPSPH_ADJ_WAVES
 #define MPSPH_ADJ_WAVES 7
 #endif

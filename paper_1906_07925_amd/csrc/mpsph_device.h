@@ -35,7 +35,8 @@ enum : int {
 // Geometry of the cell grid and of the meshing region, in cell units.  Positions are held as
 // an integer cell coordinate per axis plus a float offset in [0, 1).
 // Most sub-cells per cell along x in the cell key (log2).  Measured on the 2M-particle graded
-// cube at 2^6 cells: 0 / 1 / 2 / 3 / 4 bits give 4.49 / 4.03 / 3.84 / 3.76 / 3.79 ms per step.
+// cube at 2^6 cells: 0 / 1 / 2 / 3 / 4 bits give 4.49 / 4.03 / 3.84 / 3.76 / 3.79 ms per step
+// (4 lanes, before the row-table scan; with it and 8 lanes 4 bits gain only 0.3 % over 3).
 #ifndef MPSPH_XSUB
 #define MPSPH_XSUB 3
 #endif
