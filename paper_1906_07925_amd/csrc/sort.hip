@@ -6,7 +6,8 @@
 //                 and the digit's total                               -> dsum[digit]
 //   radix_scatter digit bases from the totals; every key of the tile ranked among the keys of its
 //                 wave and item with the same digit (wave ballots), the (item, wave) counts turned
-//                 into tile offsets per digit in LDS, and each key scattered to base + offset + rank.
+//                 into tile offsets per digit in LDS, the tile staged in LDS in sorted order and
+//                 written out run by run (base + position in the digit's run).
 // The order of equal keys is the input order, so the permutation is deterministic.
 #include "sort.h"
 
@@ -78,9 +79,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(
     const uint32_t *__restrict__ dsum) {
   constexpr int kW = kSortThreads / 64;
   __shared__ uint32_t run[256];
+  __shared__ uint32_t tstart[256];
   // per (item, wave) row and digit: the count of the wave's keys with that digit in that item,
-  // then their offset in the tile (below 2^16: a tile holds kSortTile keys)
+  // then their offset in the tile (below 2^16: a tile holds kSortTile keys); afterwards the
+  // staging area of the tile's keys and values (2 x kSortTile words, the same 32 KB)
   __shared__ uint16_t cnt[kSortItems * kW][256];
+  static_assert(sizeof(cnt) >= 2 * kSortTile * sizeof(uint32_t), "staging area");
   const int radix = 1 << bits;
   const uint32_t mask = (uint32_t)radix - 1u;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(
     if (valid && rank[it] == 0u) cnt[it * kW + w][dig] = (uint16_t)__popcll(same);
   }
   __syncthreads();
-  // per digit, offsets of the (item, wave) groups in input order
+  // per digit, offsets of the (item, wave) groups in input order, and the digit's count in the tile
   for (int d = threadIdx.x; d < radix; d += kSortThreads) {
     uint32_t s = 0;
     for (int q = 0; q < kSortItems * kW; ++q) {
@@ -143,17 +147,59 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter(
       cnt[q][d] = (uint16_t)s;
       s += c;
     }
+    tstart[d] = s;
   }
   __syncthreads();
+  if (threadIdx.x < 64) {
+    // where each digit's keys start in the tile's sorted order: exclusive prefix of the counts
+    uint32_t v[4], tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = 4 * lane + q;
+      v[q] = t < radix ? tstart[t] : 0u;
+      tot += v[q];
+    }
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t u = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += u;
+    }
+    uint32_t b = incl - tot;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = 4 * lane + q;
+      if (t < radix) tstart[t] = b;
+      b += v[q];
+    }
+  }
+  __syncthreads();
+  // each key's place in the tile's sorted order (the counts are read for the last time here)
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const uint32_t dig = (key[it] >> shift) & mask;
+    rank[it] += tstart[dig] + cnt[it * kW + w][dig];
+  }
+  __syncthreads();
+  // stage the tile in sorted order in the counts' memory, then write it out in that order, so
+  // that consecutive threads store consecutive positions of a digit's run
+  uint32_t *sk = cnt32, *sv = cnt32 + kSortTile;
 #pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
     if (base + it * kSortThreads + (int)threadIdx.x < n) {
-      const uint32_t dig = (key[it] >> shift) & mask;
-      const uint32_t pos = run[dig] + cnt[it * kW + w][dig] + rank[it];
-      if (pos < (uint32_t)n) {
-        kout[pos] = key[it];
-        vout[pos] = val[it];
-      }
+      sk[rank[it]] = key[it];
+      sv[rank[it]] = val[it];
+    }
+  }
+  __syncthreads();
+  const int tile_n = min(kSortTile, n - base);
+  for (int l = threadIdx.x; l < tile_n; l += kSortThreads) {
+    const uint32_t k = sk[l];
+    const uint32_t dig = (k >> shift) & mask;
+    const uint32_t pos = run[dig] + ((uint32_t)l - tstart[dig]);
+    if (pos < (uint32_t)n) {
+      kout[pos] = k;
+      vout[pos] = sv[l];
     }
   }
 }
