@@ -623,7 +623,9 @@ __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ 
   const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
   const float kh = 0.5f * sp.kappa;
   const uint32_t idi = wid[i];
-  scan_group<D, 1, PER>(i, 0, ci, oi, rs, g, dd.cellbase, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
+  __shared__ uint4 rowtab[row_table_rows<1>() * row_table_stride<1>()];
+  scan_group_table<D, 1, row_table_rows<1>(), PER>(i, 0, rowtab + threadIdx.x, row_table_stride<1>(), ci, oi, rs, g,
+                                                   dd.cellbase, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
     const int j = v ? (int)jr : i;  // slots past the end carry an index outside the arrays
     const float4 pj = wpos[j];
     const uint32_t aj = wjaux[j];

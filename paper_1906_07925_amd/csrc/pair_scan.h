@@ -8,22 +8,12 @@
 
 namespace mpsph {
 
-// Neighbour candidates (scan_group: the adjoints and the pair dump; the forward passes use
-// scan_group_table below, which visits the same candidates)
+// Neighbour candidates
 //
 // Particle i's candidates are the particles of every x-run of cells (fixed y, z) that meets the
 // ball of radius rs around it, the run taken at x sub-cell resolution; in the cell order (x
 // fastest) each run is one contiguous range of the sorted arrays.  A group of L lanes works on
-// one particle: the L lanes take L rows at a time (each reads its row's range from the cell
-// table), form the prefix sum of the run lengths, and then visit the flattened candidates of
-// those rows L at a time, lane l taking every L-th one.  A slot's row comes from comparing it
-// with the group's prefix sums (held in every lane through quad broadcasts for L <= 4; a
-// binary search with cross-lane reads for L = 8).  All lanes of a group run the same loop trip
-// counts whatever the run lengths are.
-// body(j, dy0, dz0, valid) is called for every slot with the row offsets dy0 = ci[1] - cy and
-// dz0 = ci[2] - cz (cell units); an invalid slot (past the round's end, or the particle itself)
-// may carry an index outside the arrays.  The return value is the group's candidate count
-// (the particle itself excluded), the same in every lane of the group.
+// one particle (scan_group_table below).
 // ------------------------------------------------------------------------------------------
 // Lanes per particle of the pair kernels of a context that is not tuned (mpsph_configure and
 // mpsph_autotune choose 2, 4 or 8) and of the adjoint kernels.  Measured: 8 lanes are the fastest
@@ -45,130 +35,8 @@ __device__ __forceinline__ float sep_x(const GridDev &g, int cxi, int cxj, float
   return dx;
 }
 
-template <int D, int L, bool PER = false, typename BodyF>
-__device__ __forceinline__ uint32_t scan_group(int i, int sub, const int *ci, const float *oi, float rs,
-                                               const GridDev &g, uint32_t cellbase, const uint32_t *__restrict__ cstart,
-                                               BodyF &&body) {
-  // a finite, non-negative radius keeps every cell range inside [0, gmax] (NaN -> 0)
-  rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
-  const float rs2 = rs * rs;
-  // periodic box (period P = 2^k cells): rows are taken unwrapped around the particle, at most
-  // P of them, so that each row is visited once and its unwrapped offset is the minimum image
-  const bool per = PER && g.geometry == 0;
-  const int P = g.gmax + 1;
-  int z0 = D == 3 ? ci[2] + (int)floorf(oi[2] - rs) : 0;
-  int z1 = D == 3 ? ci[2] + (int)floorf(oi[2] + rs) : 0;
-  int y0 = ci[1] + (int)floorf(oi[1] - rs);
-  int y1 = ci[1] + (int)floorf(oi[1] + rs);
-  if (per) {
-    if (y1 - y0 + 1 > P) {
-      y0 = ci[1] - P / 2;
-      y1 = y0 + P - 1;
-    }
-    if (D == 3 && z1 - z0 + 1 > P) {
-      z0 = ci[2] - P / 2;
-      z1 = z0 + P - 1;
-    }
-  } else {
-    y0 = max(0, y0);
-    y1 = min(g.gmax, y1);
-    if (D == 3) {
-      z0 = max(0, z0);
-      z1 = min(g.gmax, z1);
-    }
-  }
-  const int ny = y1 - y0 + 1;
-  const int nrows = ny * (z1 - z0 + 1);
-  const float inv_ny = 1.f / (float)ny;
-  const uint32_t nmax = (uint32_t)g.n;
-  uint32_t total = 0;   // candidates of the group, the particle itself included
-  for (int q0 = 0; q0 < nrows; q0 += L) {
-    const int q = q0 + sub;
-    const int qz = (int)(((float)q + 0.5f) * inv_ny);   // q / ny (q, ny < 2^12)
-    const int cz = z0 + qz, cy = y0 + (q - qz * ny);
-    float ez = 0.f;
-    if constexpr (D == 3) {
-      const float lo = (float)(cz - ci[2]) - oi[2], hi = lo + 1.f;
-      ez = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
-    }
-    const float lo = (float)(cy - ci[1]) - oi[1], hi = lo + 1.f;
-    const float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
-    const float d2 = ey * ey + ez * ez;
-    const bool hit = q < nrows && d2 < rs2;
-    // x-run of the row in sub-cells (2^xe per cell; the power-of-two scaling is exact)
-    const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
-    const float fx = (float)(1u << g.xe);
-    const int xlast = ((g.gmax + 1) << g.xe) - 1;
-    int x0 = (ci[0] << g.xe) + (int)floorf((oi[0] - wx) * fx);
-    int x1 = (ci[0] << g.xe) + (int)floorf((oi[0] + wx) * fx);
-    if (per && (x0 < 0 || x1 > xlast)) {  // a run across the period: the whole row, once
-      x0 = 0;
-      x1 = xlast;
-    }
-    x0 = max(0, x0);
-    x1 = min(xlast, x1);
-    const int cyw = per ? (cy + P) & g.gmax : cy;   // |cy - ci| < P: one wrap at most
-    const uint32_t kx = g.k + g.xe;
-    uint32_t kb;
-    if constexpr (D == 3)
-      kb = (uint32_t)x0 | (row_index(cyw, per ? (cz + P) & g.gmax : cz, g) << kx);
-    else
-      kb = (uint32_t)x0 | ((uint32_t)cyw << kx);
-    kb += cellbase;
-    uint32_t a = 0u, b = 0u;
-    if (hit) {
-      a = cstart[kb];
-      b = min(cstart[kb + (uint32_t)(x1 - x0) + 1u], nmax);
-    }
-    const uint32_t len = b > a ? b - a : 0u;
-    // row offsets of the separation (unwrapped, so the minimum image in a periodic box)
-    const float dyr = (float)(ci[1] - cy);
-    const float dzr = D == 3 ? (float)(ci[2] - cz) : 0.f;
-    uint32_t incl = len;
-#pragma unroll
-    for (int o = 1; o < L; o <<= 1) {
-      const uint32_t v = __shfl_up(incl, o, L);
-      if (sub >= o) incl += v;
-    }
-    const uint32_t T = __shfl(incl, L - 1, L);
-    // candidate slot t of this round lies in the row r with excl_r <= t < incl_r: j = a_r + t - excl_r
-    const uint32_t base = a - (incl - len);
-    total += T;
-    // the group's prefix sums in every lane (quad broadcasts for L <= 4), for the row search
-    uint32_t inc0 = 0, inc1 = 0, inc2 = 0;
-    if constexpr (L == 2) {
-      inc0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)incl, 0xA0, 0xF, 0xF, false);   // quad_perm 0,0,2,2
-    } else if constexpr (L == 4) {
-      inc0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)incl, 0x00, 0xF, 0xF, false);   // quad_perm 0,0,0,0
-      inc1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)incl, 0x55, 0xF, 0xF, false);   // quad_perm 1,1,1,1
-      inc2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)incl, 0xAA, 0xF, 0xF, false);   // quad_perm 2,2,2,2
-    }
-    for (uint32_t t0 = 0; t0 < T; t0 += L) {
-      const uint32_t t = t0 + (uint32_t)sub;
-      int r = 0;
-      if constexpr (L == 2) {
-        r = t >= inc0 ? 1 : 0;
-      } else if constexpr (L == 4) {
-        r = (t >= inc0 ? 1 : 0) + (t >= inc1 ? 1 : 0) + (t >= inc2 ? 1 : 0);
-      } else {
-#pragma unroll
-        for (int step = L / 2; step > 0; step >>= 1) {
-          const uint32_t v = __shfl(incl, r + step - 1, L);
-          if (v <= t) r += step;
-        }
-      }
-      const uint32_t j = __shfl(base, r, L) + t;
-      const float dy0 = __shfl(dyr, r, L), dz0 = D == 3 ? __shfl(dzr, r, L) : 0.f;
-      // slots past the end carry an index that may lie outside the arrays: bodies must load
-      // through bounds-checked buffer loads or clamp it with the valid flag
-      body(j, dy0, dz0, t < T && j != (uint32_t)i);
-    }
-  }
-  return total > 0u ? total - 1u : 0u;
-}
-
 // Rows per chunk of the LDS row table at 4 lanes per particle (scaled with the lanes, so that
-// the table of a 256-thread block stays near 16 KB and 8 blocks fit a CU's LDS).
+// the table of a 256-thread block stays below 19 KB and 8 blocks fit a CU's LDS).
 #ifndef MPSPH_ROW_TABLE
 #define MPSPH_ROW_TABLE 18
 #endif
@@ -183,17 +51,20 @@ constexpr int row_table_stride() {
   return kBlock / L + 1;
 }
 
-// Candidate scan with a row table in LDS (the forward pair passes).
+// Candidate scan with a row table in LDS (the pair passes, their adjoints and the pair dump).
 //
-// The same candidates as scan_group, visited in one flattened loop per group: the group first
-// lays out its non-empty x-runs (rows) in a table in LDS (base index, end of the run in the
-// flattened slot order, row offsets), then visits the slots L at a time, each lane advancing
-// through the table as its slot index passes the end of a row.  Unlike scan_group, whose
-// groups advance row round by row round in step with the whole wave, a group's loop here
-// ends when its own candidates end.  A table holds at most C rows; a particle with more
-// non-empty rows is scanned in several chunks.
+// The group's L lanes take L rows at a time (each reads its row's range from the cell table)
+// and lay out the non-empty ones in a table in LDS: base index, end of the run in the flattened
+// slot order of the particle's candidates, row offsets.  Then the group visits the slots L at a
+// time, lane l taking every L-th one and advancing through the table as its slot index passes
+// the end of a row.  A group's loop ends when its own candidates end (no wave-wide rounds of
+// rows).  A table holds at most C rows; a particle with more non-empty rows is scanned in
+// several chunks.
 // tab: the group's column of the table, entry e at tab[e * stride]; C >= L.
-// body and return value as in scan_group.
+// body(j, dy0, dz0, valid) is called for every slot with the row offsets dy0 = ci[1] - cy and
+// dz0 = ci[2] - cz (cell units); an invalid slot (past the chunk's end, or the particle itself)
+// may carry an index outside the arrays.  The return value is the group's candidate count
+// (the particle itself excluded), the same in every lane of the group.
 template <int D, int L, int C, bool PER = false, typename BodyF>
 __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab, int stride, const int *ci,
                                                      const float *oi, float rs, const GridDev &g, uint32_t cellbase,
