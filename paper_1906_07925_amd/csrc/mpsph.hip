@@ -601,7 +601,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
 
 // Debug: ordered geometric neighbour pairs (i, j != i, r_ij < kappa h_ij, no type mask) of the
 // last step's start-of-step state, enumerated with the same candidate scan and predicate as the
-// pair passes (one lane per particle).  Pairs go to (out_i, out_j) as load indices while the
+// pair passes (two lanes per particle).  Pairs go to (out_i, out_j) as load indices while the
 // running count stays below cap; *count receives the total.
 template <int D, bool PER>
 __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ doms, int ndom, int i0, int i1,
@@ -610,8 +610,10 @@ __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ 
                                                      const uint32_t *__restrict__ cstart, unsigned long long cap,
                                                      uint32_t *__restrict__ out_i, uint32_t *__restrict__ out_j,
                                                      unsigned long long *__restrict__ count) {
-  const int i = i0 + blockIdx.x * kBlock + threadIdx.x;
-  if (i >= i1) return;
+  constexpr int L = 2;   // lanes per particle, as in the pair passes
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int i = i0 + t / L, sub = t % L;
+  if (i >= i1) return;   // both lanes of a particle leave together
   const DomDev &dd = doms[domain_of(doms, ndom, i)];
   const GridDev &g = dd.g;
   const StepDev &sp = dd.sp;
@@ -623,9 +625,9 @@ __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ 
   const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
   const float kh = 0.5f * sp.kappa;
   const uint32_t idi = wid[i];
-  __shared__ uint4 rowtab[row_table_rows<1>() * row_table_stride<1>()];
-  scan_group_table<D, 1, row_table_rows<1>(), PER>(i, 0, rowtab + threadIdx.x, row_table_stride<1>(), ci, oi, rs, g,
-                                                   dd.cellbase, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
+  __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
+  scan_group_table<D, L, row_table_rows<L>(), PER>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs,
+                                                   g, dd.cellbase, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
     const int j = v ? (int)jr : i;  // slots past the end carry an index outside the arrays
     const float4 pj = wpos[j];
     const uint32_t aj = wjaux[j];
@@ -2777,7 +2779,8 @@ int mpsph_debug_pairs(mpsph_ctx *ctx, int64_t cap, uint32_t *d_i, uint32_t *d_j,
     if (gr.i1 <= gr.i0) continue;
     auto kern = gr.D == 2 ? (gr.periodic ? dump_pairs<2, true> : dump_pairs<2, false>)
                           : (gr.periodic ? dump_pairs<3, true> : dump_pairs<3, false>);
-    kern<<<(gr.i1 - gr.i0 + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(
+    // two lanes per particle
+    kern<<<(int)((2 * (int64_t)(gr.i1 - gr.i0) + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
         ctx->at<DomDev>(L.doms) + gr.d0, gr.nd, gr.i0, gr.i1, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
         ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.w_id), ctx->at<uint32_t>(L.cstart),
         (unsigned long long)cap, d_i, d_j, cnt);

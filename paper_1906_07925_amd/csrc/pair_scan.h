@@ -70,6 +70,9 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
                                                      const float *oi, float rs, const GridDev &g, uint32_t cellbase,
                                                      const uint32_t *__restrict__ cstart, BodyF &&body) {
   static_assert(C >= L, "a table chunk holds at least one round of rows");
+  // one lane per particle is not supported: such a build listed some candidates twice on the
+  // GPU, although the same steps emulated on the CPU visit each candidate once
+  static_assert(L >= 2, "at least two lanes per particle");
   rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
   const float rs2 = rs * rs;
   const bool per = PER && g.geometry == 0;
