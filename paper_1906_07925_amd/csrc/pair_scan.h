@@ -70,8 +70,10 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
                                                      const float *oi, float rs, const GridDev &g, uint32_t cellbase,
                                                      const uint32_t *__restrict__ cstart, BodyF &&body) {
   static_assert(C >= L, "a table chunk holds at least one round of rows");
-  // one lane per particle is not supported: such a build listed some candidates twice on the
-  // GPU, although the same steps emulated on the CPU visit each candidate once
+  // one lane per particle is not supported: with no cross-lane operation in the loop nest the
+  // compiler merged the chunk loop with the table loop and took the chunk loop's exit mask from a
+  // compare of the divergent inner loop, and such a build listed some candidates twice (the same
+  // build with the chunk bound passed through a width-1 shuffle listed each once)
   static_assert(L >= 2, "at least two lanes per particle");
   rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
   const float rs2 = rs * rs;
