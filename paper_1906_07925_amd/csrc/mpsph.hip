@@ -219,12 +219,15 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
     const uint32_t coli = ai >> 14;
     const float hi = pi.w;
     const float si = hi * sp.inv_tau;                 // target spacing, rho_t = s^-d
-    const float Pi = sp.p0c * powd<D>(si * si);       // p0 / rho_t^2 = p0 s^(2d)
+    // P = p0 / rho_t^2 = p0 tau^-2d h^2d and -dW/dr / r = 5 alpha 2^(d+2) (h_i + h_j)^-(d+2) (1 - q/2)^3
+    // for the pair's h_ij: the pair sum takes h^2d and (h_i + h_j)^-(d+2), and the factors
+    // common to every pair are applied once to the group's total
+    const float Phi = powd<D>(hi * hi);
+    const float fscale = sp.p0c * powd<D>(sp.inv_tau * sp.inv_tau) * (5.f * sp.alpha) * (D == 3 ? 32.f : 16.f);
     const float ihi = fast_rcp(hi);
     const float rci = sp.kappa * hi, rci2 = rci * rci;
     const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
     const float kh = 0.5f * sp.kappa;
-    const float alpha5 = 5.f * sp.alpha;
     const float opb = 1.f + sigma;
     float wsum = 0.f, ax = 0.f, ay = 0.f, az = 0.f, A = 0.f, nn2 = INFINITY;
     uint32_t npair = 0, nifc = 0;
@@ -240,7 +243,8 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
         dz = dz0 + (oi[2] - pj.z);
         r2 += dz * dz;
       }
-      const float hij = kh * (hi + pj.w);           // kappa h_ij
+      const float hs = hi + pj.w;                   // 2 h_ij
+      const float hij = kh * hs;                    // kappa h_ij
       const bool dens = v && r2 < rci2;
       const bool inter = v && r2 < hij * hij;
       if (!(dens || inter)) return;
@@ -256,14 +260,13 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
       npair += feel ? 1u : 0u;
       if (inter && r2 < nn2) nn2 = r2;
       if (!(feel && apart)) return;
-      const float ih = sp.kappa * fast_rcp(hij);    // 1 / h_ij
-      const float uu = fmaf(-0.5f * r, ih, 1.f);    // 1 - q/2, q = r / h_ij
-      const float ih2 = ih * ih;
-      const float ihp = D == 3 ? ih2 * ih2 * ih : ih2 * ih2;  // h_ij^-(d+2) = h_ij^-(d+1) q / r
-      const float sj = pj.w * sp.inv_tau;
-      const float Pj = sp.p0c * powd<D>(sj * sj);
-      // -dW/dr / r = alpha h^-(d+1) 5 (q / r) (1 - q/2)^3 >= 0
-      const float s = (diff ? opb : 1.f) * (Pi + Pj) * (alpha5 * ihp * uu * uu * uu);
+      const float rh = fast_rcp(hs);                // 1 / (2 h_ij)
+      const float uu = fmaf(-r, rh, 1.f);           // 1 - q/2, q = r / h_ij
+      const float rh2 = rh * rh;
+      const float rhp = D == 3 ? rh2 * rh2 * rh : rh2 * rh2;  // (2 h_ij)^-(d+2)
+      const float hj2 = pj.w * pj.w;
+      // (P_i + P_j) (-dW/dr / r) over the common factor fscale (>= 0)
+      const float s = (diff ? opb : 1.f) * (Phi + powd<D>(hj2)) * (rhp * uu * uu * uu);
       ax = fmaf(s, dx, ax);
       ay = fmaf(s, dy, ay);
       az = fmaf(s, dz, az);
@@ -272,10 +275,10 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
     const uint32_t ncand = scan_group_table<D, L, row_table_rows<L>(), PER>(
         i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g, cellbase, cstart, body);
     wsum = group_sum<L>(wsum);
-    ax = group_sum<L>(ax);
-    ay = group_sum<L>(ay);
-    if constexpr (D == 3) az = group_sum<L>(az);
-    if constexpr (DBG) A = group_sum<L>(A);
+    ax = fscale * group_sum<L>(ax);
+    ay = fscale * group_sum<L>(ay);
+    if constexpr (D == 3) az = fscale * group_sum<L>(az);
+    if constexpr (DBG) A = fscale * group_sum<L>(A);
     nn2 = group_min<L>(nn2);
     npair = group_sum_u<L>(npair);
     nifc = group_sum_u<L>(nifc);
@@ -374,9 +377,12 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
   const int i = doms[d].off + li;
   double part[3] = {0.0, 0.0, 0.0};
   const int ops[3] = {0, 0, 0};
+  // dt1 is published in LDS and read again after the pair sum, so that no copy of it stays live
+  // across the pair loop
+  __shared__ float sdt1;
   const float dt1 = read_dt1(dtslots + d * kDtSlots);
-  const float hdt = 0.5f * dt1;
-  const float dt2 = dt1 * sp.dt2_factor;
+  if (threadIdx.x == 0) sdt1 = dt1;
+  __syncthreads();
   __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
   if (li < doms[d].n) {
     float bx = 0.f, by = 0.f, bz = 0.f;
@@ -388,13 +394,15 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
       const float oi[3] = {pi.x, pi.y, pi.z};
       const int ti = (wjaux[i] >> 12) & 3;
       const float hi = pi.w;
-      const float si = hi * sp.inv_tau;
-      const float invi = powd<D>(si * si);              // 1 / rho_t,i^2
+      // 1 / rho_t^2 = tau^-2d h^2d, v = (dt1/2) a, eta = (dt1/2) e and dW/dr / r =
+      // -5 alpha 2^(d+2) (h_i + h_j)^-(d+2) (1 - q/2)^3 for the pair's h_ij: the pair sum takes h^2d,
+      // a, e and (h_i + h_j)^-(d+2), and the factors common to every pair are applied once to the
+      // group's total
+      const float invi = powd<D>(hi * hi);
       const float4 acci = acc[i];
-      const float vix = hdt * acci.x, viy = hdt * acci.y, viz = hdt * acci.z, ei = hdt * acci.w;
+      const float ei = (0.5f * dt1) * acci.w;
       const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
       const float kh = 0.5f * sp.kappa;
-      const float alpha5 = 5.f * sp.alpha;
       // with eta_i = 0 every harmonic-mean viscosity of particle i vanishes: nothing to sum
       if (ei > 0.f) {
         const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
@@ -411,32 +419,35 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
             const float dz = dz0 + (oi[2] - pj.z);
             r2 += dz * dz;
           }
-          const float hij = kh * (hi + pj.w);
+          const float hs = hi + pj.w;   // 2 h_ij
+          const float hij = kh * hs;
           if (!(v && r2 > 1e-30f && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti)) return;
           const float r = fast_sqrt(r2);
-          const float ej = hdt * accj.w;
-          const float esum = ei + ej;
-          const float etaij = 2.f * ei * ej * fast_rcp(esum > 0.f ? esum : 1.f);
-          const float ih = sp.kappa * fast_rcp(hij);
-          const float uu = fmaf(-0.5f * r, ih, 1.f);  // 1 - q/2, q = r / h_ij
-          const float ih2 = ih * ih;
-          const float ihp = D == 3 ? ih2 * ih2 * ih : ih2 * ih2;  // h_ij^-(d+2) = h_ij^-(d+1) q / r
-          const float sj = pj.w * sp.inv_tau;
-          const float inv2 = invi + powd<D>(sj * sj);
-          // dW/dr / r = -5 alpha h^-(d+1) (q / r) (1 - q/2)^3
-          const float s = -etaij * inv2 * (alpha5 * ihp * uu * uu * uu);
-          const float dxv = hdt * accj.x, dyv = hdt * accj.y, dzv = hdt * accj.z;
-          bx = fmaf(s, vix - dxv, bx);
-          by = fmaf(s, viy - dyv, by);
-          if constexpr (D == 3) bz = fmaf(s, viz - dzv, bz);
+          // e_i e_j / (e_i + e_j), half the harmonic mean; e_i > 0 here and e_j >= 0, so the sum
+          // is positive
+          const float eh = acci.w * accj.w * fast_rcp(acci.w + accj.w);
+          const float rh = fast_rcp(hs);
+          const float uu = fmaf(-r, rh, 1.f);  // 1 - q/2, q = r / h_ij
+          const float rh2 = rh * rh;
+          const float rhp = D == 3 ? rh2 * rh2 * rh : rh2 * rh2;  // (2 h_ij)^-(d+2)
+          const float hj2 = pj.w * pj.w;
+          const float s = eh * (invi + powd<D>(hj2)) * (rhp * uu * uu * uu);
+          bx = fmaf(s, acci.x - accj.x, bx);
+          by = fmaf(s, acci.y - accj.y, by);
+          if constexpr (D == 3) bz = fmaf(s, acci.z - accj.z, bz);
         };
         scan_group_table<D, L, row_table_rows<L>(), PER>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(),
                                                           ci, oi, rs, g, cellbase, cstart, body);
       }
     }
-    bx = group_sum<L>(bx);
-    by = group_sum<L>(by);
-    if constexpr (D == 3) bz = group_sum<L>(bz);
+    const float hdt = 0.5f * sdt1;
+    const float dt2 = sdt1 * sp.dt2_factor;
+    // the factors left out of the pair sum: 2 of the harmonic mean, -5 alpha 2^(d+2), tau^-2d and
+    // (dt1/2)^2
+    const float vscale = (-2.f * 5.f * sp.alpha * (D == 3 ? 32.f : 16.f)) * powd<D>(sp.inv_tau * sp.inv_tau) * hdt * hdt;
+    bx = vscale * group_sum<L>(bx);
+    by = vscale * group_sum<L>(by);
+    if constexpr (D == 3) bz = vscale * group_sum<L>(bz);
     if (sub == 0) {
       // the particle's own data is read again rather than kept in registers across the pair
       // loop, through an index the compiler cannot tie to i, so that neither values nor
