@@ -265,6 +265,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-mesh", action="store_true", help="skip the background-mesh workload")
     ap.add_argument("--no-features", action="store_true", help="skip the seeded-feature workload")
+    ap.add_argument("--leg", choices=("batched", "mesh", "adjoint"), default="",
+                    help="run only this secondary workload and print its record (for a kernel trace of it)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -275,6 +277,13 @@ def main():
     import torch
     from paper_1906_07925_amd import mpsph as M
     from paper_1906_07925_amd import workloads as W
+
+    if args.leg:
+        legs = {"batched": lambda: batched_run(torch, M, W, args.batched_steps, 10),
+                "mesh": lambda: mesh_run(torch, M, W),
+                "adjoint": lambda: adjoint_run(torch, M, W)}
+        print(json.dumps({"leg": args.leg, **legs[args.leg]()}))
+        return
 
     cfg = W.config(WORKLOAD)
     spec = cfg["spec"]

@@ -66,3 +66,19 @@ def test_kernel_source_digest_ignores_comments(tmp_path, monkeypatch):
     assert bench.kernel_source_digest() == d0
     src.write_text("int f(int x) {\n  return x + 2;\n}\n")
     assert bench.kernel_source_digest() != d0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: --gpus above 1 ends at once with exit status 2 and a JSON
+    message, before anything is loaded."""
+    import json
+    import subprocess
+    import sys
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__file__))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+    r = subprocess.run([sys.executable, "bench.py", "--leg", "sort"], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "invalid choice" in r.stderr
