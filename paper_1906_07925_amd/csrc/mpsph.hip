@@ -1726,7 +1726,7 @@ DomDev domain_device(const Domain &dm, const int *rbf_c, const float *rbf_o, con
   g.r_in = (float)(p.r_in * ics);
   g.r_out = (float)(p.r_out * ics);
   g.seeded = p.seeded ? 1 : 0;
-  // 3D row tiles of 32 x 16 rows (fewer when the grid is smaller)
+  // 3D row tiles of 16 x 16 rows (fewer when the grid is smaller)
   g.xe = (uint32_t)dm.d.xe;
   g.ly = D == 3 ? (uint32_t)std::min(MPSPH_TILE_LY, g.k) : 0u;
   g.lz = D == 3 ? (uint32_t)std::min(MPSPH_TILE_LZ, g.k) : 0u;

@@ -57,7 +57,7 @@ def test_single_step_parity(torch_cuda, name, scale, k):
 def test_keys_and_cell_table_bit_exact(torch_cuda):
     """Cell keys of identical inputs are exact by construction: floor((x - lo) (2^k - 1)/L) per
     axis in FP64 and the float32 offset's x sub-cell, packed x fastest (2^xe sub-cells along x,
-    3D rows in tiles of 32 x 16, as the header documents); the cell table is the lower bound of
+    3D rows in tiles of 16 x 16, as the header documents); the cell table is the lower bound of
     each cell in the sorted keys."""
     torch = torch_cuda
     from paper_1906_07925_amd import mpsph as M
@@ -90,7 +90,7 @@ def test_keys_and_cell_table_bit_exact(torch_cuda):
         if d == 2:
             row = c[:, 1]
         else:
-            ly, lz = min(5, k), min(4, k)
+            ly, lz = min(4, k), min(4, k)
             y, z = c[:, 1], c[:, 2]
             row = (y & ((1 << ly) - 1)) | ((z & ((1 << lz) - 1)) << ly) | ((y >> ly) << (ly + lz)) | \
                 ((z >> lz) << (k + lz))
