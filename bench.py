@@ -9,7 +9,9 @@ tension, both time steps, viscous pass, integrator, FP64 metrics) on that partic
 Prints one JSON line: pair interactions per second over the timed steps (ordered pairs
 i != j inside the cut-off that pass the type mask, counted on the device each step), the step
 rate, per-kernel times measured with HIP events on the library's stream, the roofline entry of
-the dominant kernel, the CPU oracle timed on the host on a bounded sample, and (object
+the dominant kernel (and per kernel: HBM fraction on algorithmic bytes, FP32 fraction of the pair
+passes on algorithmic FLOPs; the whole step against HBM), the early and late 100-step windows of
+1000-step runs (median of 5), the CPU oracle timed on the host on a bounded sample, and (object
 "batched") 64 independent mixed 2D/3D domains relaxed in one batched context against the same
 domains solved one after the other, and (object "adjoint", field "adjoint_forward_ratio") the
 reverse sweep of the gradient of the relaxation loss over 50 steps of the 2^20-particle RBF cube
@@ -32,17 +34,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pair interactions/s + relax steps/s at 2M-particle 3D; adjoint/forward ratio"
 WORKLOAD = "cube_inclusion_2m"
-PEAK_FP32_TFLOPS = 157.3      # published MI355X FP32 vector peak
+# MI355X published figures: 256 CUs at 2.4 GHz; FP32 vector 157.3 TFLOP/s counts packed FP32
+# (two lanes' worth per instruction).  Packed FP32 instructions are kept out of this build, so
+# the attainable peak is 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+PEAK_FP32_TFLOPS = 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-# Algorithmic FP32 operations per ordered interacting pair (each arithmetic operation of the
-# formula once, a fused multiply-add as two, rsqrt / rcp as one):
-#  density / force pass: separation 6, r^2 5, 1/r and r 2, density term with h_i 9, h_ij and
-#    1/h_ij 3, q and 1 - q/2 3, h_ij^-(d+1) 3, P_j from s_j 4, P_i + P_j 1, (1 + beta) 1,
-#    coefficient 6, accumulation of a 6                                               = 49
-#  viscous pass: separation 6, r^2 5, 1/r and r 2, h_ij and 1/h_ij 3, q and 1 - q/2 3,
-#    h_ij^-(d+1) 3, 1/rho_t,j^2 and the sum 5, eta_j 1, harmonic mean 4, coefficient 6,
-#    v~_j and v~_ij 6, accumulation 6                                                  = 50
-FLOPS_PER_PAIR = {"pass_density_force": 49, "pass_viscous_integrate": 50}
+# Algorithmic FP32 operations per ordered interacting pair: each arithmetic operation the
+# formula itself needs (per-particle quantities such as P_j, 1/rho_t,j^2, v~_j and eta_j count
+# once per particle, not per pair), a fused multiply-add as two; square roots and reciprocals
+# are counted separately, not as FLOPs.
+#  density / force pass (Eq. 17, 18, 23-24): r_ij 3, r^2 5, W(r, h_i) 9 (q, 1 - q/2, its 4th
+#    power, 1 + 2q, product, sum), h_ij and q_ij 3, dW/dr(r, h_ij) 8 ((1 - q/2)^3, q, h_ij^-4,
+#    constant), P_i + P_j and 1 + beta 2, coefficient 2, a_i += s r_ij 6         = 38 (+3: sqrt, 2 rcp)
+#  viscous pass (Eq. 20-22): r_ij 3, r^2 5, h_ij and q_ij 3, dW/dr 8, 1/rho_t,i^2 + 1/rho_t,j^2 1,
+#    harmonic mean 3, coefficient 2, v~_i - v~_j 3, accumulation 6              = 34 (+4: sqrt, 3 rcp)
+FLOPS_PER_PAIR = {"pass_density_force": 38, "pass_viscous_integrate": 34}
+# Algorithmic HBM bytes per launch of each kernel of a step: (per particle, per cell-table entry).
+# Neighbour data re-read by the pair passes is reuse through the caches, not algorithmic traffic.
+#  radix_hist: the key; radix_scatter: key and value read and written; reorder_field: the
+#  permutation, key, offsets, flags and id read (32 B), key, position + h, flags and id written
+#  (28 B), the cell table written; pair passes: the particle's own key, position and flags (24 B)
+#  and the cell table read, a written (16 B); the viscous pass also reads a and the id (20 B)
+#  and writes the new state (28 B).
+KERNEL_BYTES = {"radix_hist": (4, 0), "radix_scatter": (16, 0), "reorder_field": (60, 4),
+                "pass_density_force": (40, 4), "pass_viscous_integrate": (72, 4)}
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1906_07925_amd", "csrc", f)
                   for f in ("mpsph.hip", "mpsph_device.h", "pair_scan.h", "adjoint.h", "sort.hip", "sort.h")]
@@ -75,15 +91,101 @@ def load_traffic(kernel: str, cell_log2: int, lanes: int):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, x, col, typ):
-    """The FP64 oracle as it stands, one step of the same 2M-particle input on the host."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(runs: int = 3, steps: int = 10):
+    """The FP64 oracle as it stands, on a bounded sample of the workload: the same recipe at
+    262,144 particles (64^3 jittered lattice, size field normalised to that count, 64 colours),
+    1 warm-up step then `steps` timed steps, median of `runs` runs.  Pair interactions/s is per
+    pair, so the sample's rate stands for the full-size one."""
     from oracle import oracle as O
+    from paper_1906_07925_amd import workloads as W
+    cfg = W.config(WORKLOAD, scale=0.125)
+    x, col, typ = W.make_state(cfg)
+    x = x.astype(np.float32).astype(np.float64)
     op = O.OracleParams(cfg["spec"])
-    t0 = time.perf_counter()
-    _, _, r = O.step(op, x.astype(np.float32).astype(np.float64), col, typ, 0, want=())
-    dt = time.perf_counter() - t0
-    return {"value": r["pairs"] / dt, "unit": "pair interactions/s", "cores": O.threads(), "kind": "oracle",
-            "sample": f"1 step (step 0) of the full {x.shape[0]}-particle input, {r['pairs']} pairs, {dt:.1f} s"}
+    rates, sps, pairs_step = [], [], []
+    for _ in range(runs):
+        xr, tr = x, typ
+        xr, tr, _ = O.step(op, xr, col, tr, 0, want=())
+        t0 = time.perf_counter()
+        pairs = 0
+        for k in range(1, steps + 1):
+            xr, tr, r = O.step(op, xr, col, tr, k, want=())
+            pairs += r["pairs"]
+        dt = time.perf_counter() - t0
+        rates.append(pairs / dt)
+        sps.append(steps / dt)
+        pairs_step.append(pairs / steps)
+        print(f"[bench] cpu baseline run: {dt:.1f} s for {steps} steps", file=sys.stderr, flush=True)
+    return {"value": float(np.median(rates)), "unit": "pair interactions/s", "cores": O.threads(), "kind": "oracle",
+            "steps_per_s": float(np.median(sps)), "pairs_per_step": float(np.median(pairs_step)),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "sample": f"the workload's recipe at {x.shape[0]} particles (64^3 lattice), steps 1-{steps} after 1 "
+                      f"warm-up step, median of {runs} runs, FP64 oracle with {O.threads()} OpenMP threads"}
+
+
+def windows(torch, R, dev_x, dev_c, runs: int, early: int = 100, warm: int = 10, total: int = 1000):
+    """Early and late windows of full-length runs: `runs` times the state is loaded, `warm`
+    steps run untimed, steps warm..warm+early are timed (early window), the run continues
+    untimed to step total-100 and the last 100 steps are timed (late window).  CUDA events on
+    the stream the library launches on; pairs from the device counters.  Medians over runs."""
+    stream = torch.cuda.current_stream()
+    out = {"early": [], "late": []}
+    for _ in range(runs):
+        R.load(dev_x, dev_c)
+        R.step(warm)
+        for name, nsteps, before in (("early", early, 0), ("late", 100, total - 100 - warm - early)):
+            if before > 0:
+                R.step(before)
+            m0 = R.metrics()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            R.step(nsteps)
+            e1.record(stream)
+            e1.synchronize()
+            m1 = R.metrics()
+            ms = e0.elapsed_time(e1)
+            out[name].append((ms / nsteps, (m1["pairs_total"] - m0["pairs_total"]) / nsteps,
+                              (m1["candidates_total"] - m0["candidates_total"]) / nsteps))
+    res = {}
+    for name, vals in out.items():
+        a = np.array(vals)
+        med = np.median(a, axis=0)
+        res[name] = {"steps": f"{warm}-{warm + early}" if name == "early" else f"{total - 100}-{total}",
+                     "ms_per_step": float(med[0]), "ms_per_step_runs": [float(v) for v in a[:, 0]],
+                     "pairs_per_step": float(med[1]), "pairs_per_s": float(med[1] / med[0] * 1e3),
+                     "candidates_per_pair": float(med[2] / med[1])}
+    res["runs"] = runs
+    print(f"[bench] windows: early {res['early']['ms_per_step']:.3f} ms/step, late {res['late']['ms_per_step']:.3f} "
+          f"ms/step (median of {runs} runs of {total} steps)", file=sys.stderr, flush=True)
+    return res
+
+
+def kernel_rooflines(kern: dict, steps: int, n: int, ncells: int, pairs: int) -> dict:
+    """Per-kernel figures over the timed region: HBM fraction on algorithmic bytes for the
+    memory-bound kernels, FP32 fraction on algorithmic FLOPs for the pair passes."""
+    out = {}
+    for name, (launches, ms) in kern.items():
+        avg_s = ms / launches / 1e3
+        e = {"launches_per_step": launches / steps, "avg_launch_ms": ms / launches}
+        if name in KERNEL_BYTES:
+            bp, bc = KERNEL_BYTES[name]
+            b = bp * n + bc * ncells
+            e.update(bytes_per_launch=b, hbm_GBs=b / avg_s / 1e9, hbm_frac=b / avg_s / 1e9 / PEAK_HBM_GBS)
+        if name in FLOPS_PER_PAIR:
+            t = FLOPS_PER_PAIR[name] * pairs / launches / avg_s / 1e12
+            e.update(flops_per_pair=FLOPS_PER_PAIR[name], tflops=t, fp32_frac=t / PEAK_FP32_TFLOPS)
+        out[name] = e
+    return out
 
 
 def batched_run(torch, M, W, steps: int, warmup: int, graph_steps: int = 10):
@@ -264,6 +366,8 @@ def main():
     ap.add_argument("--config", type=str, default="",
                     help="K,L: cells per axis 2^K and L lanes per particle instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--window-runs", type=int, default=5,
+                    help="runs of 1000 steps for the early / late windows (0 skips them)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-domain batched comparison")
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
@@ -339,17 +443,34 @@ def main():
     kname = max(kern, key=lambda k: kern[k][1])
     launches, ms = kern[kname]
     avg_s = ms / launches / 1e3
+    ncells = R.ncells()
+    per_kernel = kernel_rooflines(kern, args.steps, n, ncells, pairs)
     roof = {"kernel": kname}
     if kname in FLOPS_PER_PAIR:
         flops = FLOPS_PER_PAIR[kname] * pairs / launches
         achieved = flops / avg_s / 1e12
         roof.update(bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                     frac=achieved / PEAK_FP32_TFLOPS, flops_per_pair=FLOPS_PER_PAIR[kname],
-                    pairs_per_launch=pairs / launches)
+                    pairs_per_launch=pairs / launches, peak_packed_fp32=PEAK_FP32_PACKED_TFLOPS,
+                    frac_of_packed_peak=achieved / PEAK_FP32_PACKED_TFLOPS)
     else:
-        roof.update(bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s", frac=None)
+        b = per_kernel[kname].get("bytes_per_launch")
+        roof.update(bound="hbm", achieved=b / avg_s / 1e9 if b else None, peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=b / avg_s / 1e9 / PEAK_HBM_GBS if b else None)
     roof["traffic"] = load_traffic(kname, R.cell_log2(), R.lanes)
     roof["avg_launch_ms"] = ms / launches
+    # both pair passes against the FP32 peak, and the whole step against HBM
+    pp = [k for k in FLOPS_PER_PAIR if k in kern]
+    pp_ms = sum(kern[k][1] for k in pp) / args.steps
+    pp_tf = sum(FLOPS_PER_PAIR[k] for k in pp) * pairs / args.steps / (pp_ms / 1e3) / 1e12
+    pair_passes = {"kernels": pp, "flops_per_pair": sum(FLOPS_PER_PAIR[k] for k in pp), "ms_per_step": pp_ms,
+                   "tflops": pp_tf, "frac": pp_tf / PEAK_FP32_TFLOPS, "peak": PEAK_FP32_TFLOPS}
+    step_bytes = sum(e["bytes_per_launch"] * e["launches_per_step"] for e in per_kernel.values() if "bytes_per_launch" in e)
+    step_s = elapsed / args.steps
+    hbm_step = {"algorithmic_bytes_per_step": step_bytes, "bytes_per_particle": step_bytes / n,
+                "achieved_GBs": step_bytes / step_s / 1e9, "frac": step_bytes / step_s / 1e9 / PEAK_HBM_GBS,
+                "peak": PEAK_HBM_GBS}
+    win = windows(torch, R, dev_x, dev_c, args.window_runs) if args.window_runs > 0 else None
 
     out = {
         "metric": METRIC,
@@ -373,6 +494,10 @@ def main():
         "adjoint_forward_ratio": None,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])},
         "roofline": roof,
+        "pair_passes": pair_passes,
+        "hbm_whole_step": hbm_step,
+        "kernels": per_kernel,
+        "windows": win,
     }
     R.close()
     if not args.no_batched:
@@ -385,7 +510,7 @@ def main():
         out["adjoint"] = adjoint_run(torch, M, W)
         out["adjoint_forward_ratio"] = out["adjoint"]["ratio"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, x, col, typ)
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
 
 

@@ -646,12 +646,13 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
   double *eta = calloc(nv, sizeof(double)), *nn = malloc(nv * sizeof(double));
   int64_t *npair = calloc(nv, sizeof(int64_t)), *nifc = calloc(nv, sizeof(int64_t));
   int64_t *nband = calloc(nv, sizeof(int64_t));
+  double *kabs = calloc(nv, sizeof(double));
   int32_t *type0 = malloc(nv * sizeof(int32_t));
   grid_t g;
   memset(&g, 0, sizeof(g));
   int rc = ORC_OK;
   if (!rho_t || !h || !P || !rho || !a || !aabs || !vt || !at || !atabs || !v || !eta || !nn ||
-      !npair || !nifc || !nband || !type0) {
+      !npair || !nifc || !nband || !kabs || !type0) {
     rc = ORC_E_NOMEM;
     goto done;
   }
@@ -714,6 +715,7 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
       rho[i] = rs;
       for (int c = 0; c < d; ++c) a[i * d + c] = ai[c];
       aabs[i] = A;
+      kabs[i] = K;
       if (out->a_kabs) out->a_kabs[i] = K;
       nn[i] = nearest;
       npair[i] = np;
@@ -763,7 +765,7 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
         rc = ORC_E_NOMEM;
         continue;
       }
-      double ai[3] = {0, 0, 0}, A = 0.0, K = 0.0, Pr = 0.0;
+      double ai[3] = {0, 0, 0}, A = 0.0, K = 0.0, Pr[3] = {0.0, 0.0, 0.0};
       for (int64_t k = 0; k < cand.n; ++k) {
         int64_t j = cand.j[k];
         double e[3];
@@ -772,15 +774,20 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
         if (!(r < kap * hij) || !feels(type[i], type[j]) || r == 0.0) continue;
         double inv2 = 1.0 / (rho_t[i] * rho_t[i]) + 1.0 / (rho_t[j] * rho_t[j]);
         double gij = inv2 * orc_kernel_dw(r, hij, d) / r;
-        if (out->at_prop) {
-          /* conditioning diagnostic only; it does not enter the result */
-          double dvi = type[i] == ORC_FIXED ? 0.0 : 0.5 * dt1 * aabs[i];
-          double dvj = type[j] == ORC_FIXED ? 0.0 : 0.5 * dt1 * aabs[j];
-          double dH = 2.0 * (rho_t[i] * p->nu_coeff * kap * h[i] * dvi + rho_t[j] * p->nu_coeff * kap * h[j] * dvj);
+        if (out->at_prop || out->at_prop_k || out->at_prop_kn) {
+          /* conditioning diagnostic only; it does not enter the result.  Weights of particle
+           * k: A_k, K_k, K_k / nn_k. */
           double dv = 0.0;
           for (int c = 0; c < d; ++c) dv += (vt[i * d + c] - vt[j * d + c]) * (vt[i * d + c] - vt[j * d + c]);
           double H = eta[i] + eta[j] > 0.0 ? 2.0 * eta[i] * eta[j] / (eta[i] + eta[j]) : 0.0;
-          Pr += fabs(gij) * (dH * sqrt(dv) + H * (dvi + dvj));
+          for (int w = 0; w < 3; ++w) {
+            double wi = w == 0 ? aabs[i] : (w == 1 ? kabs[i] : (nn[i] > 0.0 && nn[i] < INFINITY ? kabs[i] / nn[i] : 0.0));
+            double wj = w == 0 ? aabs[j] : (w == 1 ? kabs[j] : (nn[j] > 0.0 && nn[j] < INFINITY ? kabs[j] / nn[j] : 0.0));
+            double dvi = type[i] == ORC_FIXED ? 0.0 : 0.5 * dt1 * wi;
+            double dvj = type[j] == ORC_FIXED ? 0.0 : 0.5 * dt1 * wj;
+            double dH = 2.0 * (rho_t[i] * p->nu_coeff * kap * h[i] * dvi + rho_t[j] * p->nu_coeff * kap * h[j] * dvj);
+            Pr[w] += fabs(gij) * (dH * sqrt(dv) + H * (dvi + dvj));
+          }
         }
         if (eta[i] + eta[j] == 0.0) continue;
         double etaij = 2.0 * eta[i] * eta[j] / (eta[i] + eta[j]);
@@ -797,7 +804,9 @@ int orc_step(const orc_params *p, int64_t n, double *x, const int32_t *colour, i
       for (int c = 0; c < d; ++c) at[i * d + c] = ai[c];
       atabs[i] = A;
       if (out->at_kabs) out->at_kabs[i] = K;
-      if (out->at_prop) out->at_prop[i] = Pr;
+      if (out->at_prop) out->at_prop[i] = Pr[0];
+      if (out->at_prop_k) out->at_prop_k[i] = Pr[1];
+      if (out->at_prop_kn) out->at_prop_kn[i] = Pr[2];
     }
     free(cand.j);
   }
@@ -918,6 +927,7 @@ done:
   free(npair);
   free(nifc);
   free(nband);
+  free(kabs);
   free(type0);
   return rc;
 }

@@ -65,8 +65,11 @@ typedef struct {
    *   sum_j |g_ij| (dH_ij |v~_i - v~_j| + H_ij (dv_i + dv_j)),  dv_k = dt1 A_k / 2,
    *   dH_ij = 2 (c_i dv_i + c_j dv_j),  c_k = rho_t,k nu_coeff kappa h_k,
    * with A_k the sum of |pair terms| of a_k, H_ij the harmonic-mean viscosity and g_ij the
-   * rest of the pair coefficient */
-  double *at_prop;
+   * rest of the pair coefficient.  at_prop_k and at_prop_kn are the same sum with A_k replaced
+   * by K_k (the a_kabs sum of particle k) and by K_k / nn_k (nn_k its nearest interacting
+   * distance; 0 where it has none): the error bound of a is linear in these three weights, so
+   * its propagation into a~ is their combination */
+  double *at_prop, *at_prop_k, *at_prop_kn;
   /* scalars of the step */
   double dt1, dt2, sigma, residual_l2, residual_linf, kinetic;
   double elr_mean, elr_std, elr_min, elr_max;

@@ -57,13 +57,14 @@ _DP = C.POINTER(C.c_double)
 
 class Out(C.Structure):
     _fields_ = [(k, _DP) for k in ("rho", "rho_t", "h", "a", "a_abs", "vt", "at", "at_abs", "v",
-                                   "dr", "nn", "a_kabs", "at_kabs", "at_prop")] + [
+                                   "dr", "nn", "a_kabs", "at_kabs", "at_prop", "at_prop_k", "at_prop_kn")] + [
         (k, C.c_double) for k in ("dt1", "dt2", "sigma", "residual_l2", "residual_linf", "kinetic",
                                   "elr_mean", "elr_std", "elr_min", "elr_max")] + [
         (k, C.c_int64) for k in ("pairs", "interface_pairs", "band_pairs", "n_normal", "n_elr",
                                  "nonfinite", "interface_particles")]
 
 
+_N_ARRAYS = sum(1 for _, t in Out._fields_ if t is _DP)
 _lib = None
 
 
@@ -266,7 +267,7 @@ def level_set(op: OracleParams, x: np.ndarray) -> np.ndarray:
 
 def step(op: OracleParams, x: np.ndarray, colour: np.ndarray, ptype: np.ndarray, step_index: int,
          want: tuple = ("rho", "rho_t", "h", "a", "a_abs", "vt", "at", "at_abs", "v", "dr", "nn", "a_kabs",
-                        "at_kabs", "at_prop")):
+                        "at_kabs", "at_prop", "at_prop_k", "at_prop_kn")):
     """Run one step.  Returns (new_x, new_type, result dict)."""
     x = np.array(x, dtype=np.float64, order="C", copy=True)
     n, d = x.shape
@@ -274,7 +275,7 @@ def step(op: OracleParams, x: np.ndarray, colour: np.ndarray, ptype: np.ndarray,
     typ = np.array(ptype, dtype=np.int32, order="C", copy=True)
     out = Out()
     arrays = {}
-    for k in ("rho", "rho_t", "h", "a_abs", "at_abs", "nn", "a_kabs", "at_kabs", "at_prop"):
+    for k in ("rho", "rho_t", "h", "a_abs", "at_abs", "nn", "a_kabs", "at_kabs", "at_prop", "at_prop_k", "at_prop_kn"):
         if k in want:
             arrays[k] = np.zeros(n)
     for k in ("a", "vt", "at", "v", "dr"):
@@ -287,7 +288,7 @@ def step(op: OracleParams, x: np.ndarray, colour: np.ndarray, ptype: np.ndarray,
     if rc != 0:
         raise RuntimeError(f"orc_step failed with code {rc}")
     res = dict(arrays)
-    for k, _ in Out._fields_[14:]:
+    for k, _ in Out._fields_[_N_ARRAYS:]:
         res[k] = getattr(out, k)
     return x, typ, res
 

@@ -150,3 +150,45 @@ def test_batch_of_identical_domains(torch_cuda):
     ma, mb = B.domain_metrics()
     _metrics_agree(ma, mb)
     B.close()
+
+
+def test_batch_first_step_matches_oracle(torch_cuda):
+    """Every domain of a mixed batch (squares, annuli, cubes and balls in a shuffled order, an
+    empty domain among them, 2D and 3D interleaved) against the oracle directly: the first step
+    of each domain, read from the batched context, meets the single-step bounds of the parity
+    tests (fields, time steps, counts, positions and types)."""
+    torch = torch_cuda
+    from oracle import oracle as O
+    from paper_1906_07925_amd import mpsph as M
+    from tests import parity_util as PU
+    doms = _mixed_batch(scale=0.02, n_dom=8, seed=11)
+    x, col, typ = _concat(doms)
+    specs = [d[0] for d in doms]
+    ns = [d[1].shape[0] for d in doms]
+    s0s = [O.OracleParams(sp).s0 if sp["n"] > 0 else 0.03 for sp in specs]
+    B = M.Relaxer(specs, n=ns, s0=s0s, debug=True)
+    B.load(torch.from_numpy(x).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    B.step(1)
+    mb = B.domain_metrics()
+    fields = {}
+    for name in PU.FIELDS:
+        arr = B.field(name).cpu().numpy().astype(np.float64)
+        fields[name] = B.split(arr, vector=name in M.VECTOR_FIELDS)
+    xb, tb = B.store()
+    xb = B.split(xb.cpu().numpy().astype(np.float64))
+    tb = B.split(tb.cpu().numpy(), vector=False)
+    B.close()
+    kinds = set()
+    for k, (spec, xd, cd, td) in enumerate(doms):
+        if xd.shape[0] == 0:
+            continue
+        solo = M.Relaxer(spec, n=xd.shape[0], s0=s0s[k])
+        cell_log2 = solo.cell_log2()                  # a domain keeps its own grid in a batch
+        solo.close()
+        g = {name: fields[name][k] for name in PU.FIELDS}
+        g["x1"], g["t1"] = xb[k], tb[k]
+        op, x1, t1, r = PU.oracle_step(spec, s0s[k], xd, cd, td)
+        errs = PU.compare_step(spec, xd, x1, t1, r, mb[k], g, cell_log2)
+        kinds.add((spec["geometry"], spec["dim"]))
+        print(k, spec["geometry"], spec["dim"], xd.shape[0], {kk: f"{v:.1e}" for kk, v in errs.items()})
+    assert kinds == {("box", 2), ("annulus", 2), ("box", 3), ("ball", 3)}, kinds

@@ -220,15 +220,67 @@ def test_invalid_inputs_rejected(torch_cuda):
 
 
 @pytest.mark.slow
-def test_full_size_cube_inclusion_single_step(torch_cuda):
-    """Full 2,097,152-particle graded cube at the benchmark's launch configuration: the whole
-    step against the oracle (about 10-20 s of host time)."""
+@pytest.mark.parametrize("k,lanes", [(6, 8), (-1, 4)])
+def test_full_size_cube_inclusion_single_step(torch_cuda, k, lanes):
+    """Full 2,097,152-particle graded cube: the whole step against the oracle (about 10-20 s of
+    host time), at the benchmark's launch configuration (2^6 cells per axis with x sub-cells,
+    8 lanes per particle: what its autotuner picks for this input) and at the library's
+    defaults (size-rule cells, 4 lanes)."""
     cfg = W.config("cube_inclusion_2m")
     x32, col, typ = PU.state_f32(cfg)
     spec = dict(cfg["spec"], n=x32.shape[0])
     rep = {}
-    errs = PU.check_single_step(spec, _s0(spec), x32, col, typ, report=rep)
-    print("full C3", {kk: f"{v:.2e}" for kk, v in errs.items()}, rep["counts"])
+    errs = PU.check_single_step(spec, _s0(spec), x32, col, typ, cell_log2=k, lanes=lanes, report=rep)
+    if k > 0:
+        assert rep["k"] == k
+    print("full C3", k, lanes, {kk: f"{v:.2e}" for kk, v in errs.items()}, rep["counts"])
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3000), (3, 6000)])
+def test_ball_projection_and_retagging_single_step(torch_cuda, dim, n):
+    """Ball regions without seeded features (Eq. 32): normal particles that leave the ball are
+    moved radially onto the sphere (circle) and re-tagged as surface particles, whose forces
+    lose their radial component.  Random equal-mass initial state; the step must move some
+    particles across the boundary so that the projection and the re-tagging are exercised."""
+    cfg = dict(spec=W.ball(n, dim=dim, radius=0.45), seed=W.BASE_SEED + 90 + dim, init="random", n_colours=5)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    op, x1, t1, r = PU.oracle_step(spec, s0, x32, col, typ)
+    assert np.sum(t1 == O.SURFACE) > 0, "no particle crossed the sphere"
+    rep = {}
+    errs = PU.check_single_step(spec, s0, x32, col, typ, report=rep)
+    print("ball", dim, "crossed", int(np.sum(t1 == O.SURFACE)), {kk: f"{v:.2e}" for kk, v in errs.items()})
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3000), (3, 6000)])
+def test_ball_stepwise_parity_over_many_steps(torch_cuda, dim, n):
+    """Twenty steps of the same ball: every GPU step, started from the GPU's own state of the
+    step before (positions and types after store), matches the oracle's step from that state,
+    so the projection and one-way re-tagging are checked at every stage of the run without the
+    chaotic divergence of two independent trajectories.  At the end the surface particles lie
+    on the sphere to float32 rounding of the radius and their count has grown."""
+    cfg = dict(spec=W.ball(n, dim=dim, radius=0.45), seed=W.BASE_SEED + 92 + dim, init="random", n_colours=5)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    x, t = x32, typ
+    counts = []
+    worst = {}
+    for step in range(20):
+        op, x1, t1, r = PU.oracle_step(spec, s0, x, col, t)
+        m, g = PU.gpu_run(spec, s0, x, col, t)
+        errs = PU.compare_step(spec, x, x1, t1, r, m, g, g["k"])
+        for kk, v in errs.items():
+            worst[kk] = max(worst.get(kk, 0.0), v)
+        x, t = g["x1"].astype(np.float32), g["t1"].astype(np.int32)
+        counts.append(int(np.sum(t == O.SURFACE)))
+    rad = np.linalg.norm(x.astype(np.float64) - np.asarray(spec["centre"]), axis=1)
+    surf = t == O.SURFACE
+    assert counts[-1] >= counts[0] > 0
+    assert np.max(np.abs(rad[surf] - 0.45)) <= 8 * 2.0 ** -24
+    assert np.all(rad[~surf] <= 0.45 + 8 * 2.0 ** -24)
+    print("ball", dim, "surface counts", counts[0], counts[-1], {kk: f"{v:.2e}" for kk, v in worst.items()})
 
 
 def test_coincident_particles(torch_cuda):
