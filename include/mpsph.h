@@ -56,7 +56,9 @@ enum {
   MPSPH_E_DEVICE = 3,      /* a HIP call failed */
   MPSPH_E_STATE = 4,       /* context poisoned by an earlier error, or not loaded */
   MPSPH_E_NONFINITE = 5,   /* the last step produced a non-finite value */
-  MPSPH_E_UNSUPPORTED = 6  /* valid but unsupported configuration */
+  MPSPH_E_UNSUPPORTED = 6, /* valid but unsupported configuration */
+  MPSPH_E_SCRATCH = 7      /* needs more workspace than the static scratch array holds
+                              (mpsph_create_static) */
 };
 
 /* Meshing region: the positive phase of the level set (§3.1, Eq. 14).  MPSPH_LEVELSET: the
@@ -214,6 +216,25 @@ MPSPH_API size_t mpsph_workspace_bytes(const mpsph_params *params, int64_t n);
  * (cell grid too large, or a size field whose slope makes the neighbour bound diverge). */
 MPSPH_API int mpsph_create(const mpsph_params *params, int64_t n, void *d_workspace, size_t workspace_bytes,
                  void *hip_stream, mpsph_ctx **out);
+
+/* mpsph_create without any device allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * context's workspace is a static array of the library, 64 MiB per GPU (held from its first use
+ * on a device until the process ends; about 350,000 particles at the default cell size): the
+ * same kernels as a context of mpsph_create, on that array.  The caller still passes inputs and
+ * outputs (mpsph_load / mpsph_store, as for any context).  The device is the current one.
+ *
+ * One array per GPU is shared by every static context on it: at most one static context may exist
+ * per device at a time (a second creation before mpsph_destroy of the first returns
+ * MPSPH_E_STATE), and work enqueued on it from several streams or threads at once races.  The
+ * set-up zeroes the part of the array the context uses, so nothing of an earlier context's
+ * contents is read.  mpsph_configure / mpsph_autotune keep within the array (MPSPH_E_NOMEM for a
+ * configuration that does not fit); mpsph_grad, which allocates checkpoint memory, returns
+ * MPSPH_E_UNSUPPORTED.  load, step, metrics, store and destroy allocate nothing.
+ * Errors: MPSPH_E_INVALID (params, n), MPSPH_E_SCRATCH (the workspace mpsph_workspace_bytes
+ * reports for (params, n) exceeds 64 MiB), MPSPH_E_STATE (the device's array is in use),
+ * MPSPH_E_DEVICE, MPSPH_E_UNSUPPORTED (as mpsph_create, or a device index above 63). */
+MPSPH_API int mpsph_create_static(const mpsph_params *params, int64_t n, void *hip_stream, mpsph_ctx **out);
 
 /* Batched context: ndom >= 1 independent domains (one mpsph_params and particle count n[d]
  * each; 2D and 3D domains may be mixed; one debug flag for all) advanced together: each kernel

@@ -38,6 +38,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -825,7 +826,8 @@ struct Derived {
 };
 
 const char *kErr[] = {"ok", "invalid argument", "out of memory", "device error", "bad context state",
-                      "non-finite values", "unsupported configuration"};
+                      "non-finite values", "unsupported configuration",
+                      "the problem needs more workspace than the static scratch array holds"};
 
 bool valid_params(const mpsph_params *p) {
   if (!p) return false;
@@ -1815,6 +1817,8 @@ struct mpsph_ctx {
   // demand by mpsph_grad and freed with the context
   char *gmem = nullptr;
   size_t gbytes = 0;
+  // device whose static scratch array is the workspace (mpsph_create_static), -1 otherwise
+  int static_dev = -1;
   template <typename T>
   T *at(size_t off) {
     return reinterpret_cast<T *>(ws + off);
@@ -2416,10 +2420,27 @@ int grad_run(mpsph_ctx *ctx, int nsteps, int ckpt, double lam, double *loss_out,
 
 }  // namespace
 
+// Workspace of mpsph_create_static: one array per GPU, for callers that cannot allocate device
+// memory.  Host code never uses the array's name as an address: the device address of each
+// GPU's copy comes from hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+struct ScratchTable {
+  std::mutex mu;
+  char *ptr[kMaxDevices] = {};
+  bool busy[kMaxDevices] = {};
+};
+ScratchTable &scratch_table() {
+  static ScratchTable t;
+  return t;
+}
+
 extern "C" {
 
 const char *mpsph_strerror(int status) {
-  if (status < 0 || status > MPSPH_E_UNSUPPORTED) return "unknown status";
+  if (status < 0 || status > MPSPH_E_SCRATCH) return "unknown status";
   return kErr[status];
 }
 
@@ -2543,6 +2564,32 @@ int mpsph_batch_create(int32_t ndom, const mpsph_params *params, const int64_t *
 int mpsph_create(const mpsph_params *params, int64_t n, void *d_workspace, size_t workspace_bytes, void *hip_stream,
                  mpsph_ctx **out) {
   return mpsph_batch_create(1, params, &n, d_workspace, workspace_bytes, hip_stream, out);
+}
+
+int mpsph_create_static(const mpsph_params *params, int64_t n, void *hip_stream, mpsph_ctx **out) {
+  if (!out) return MPSPH_E_INVALID;
+  *out = nullptr;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MPSPH_E_DEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return MPSPH_E_UNSUPPORTED;
+  ScratchTable &t = scratch_table();
+  std::lock_guard<std::mutex> lock(t.mu);
+  if (!t.ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MPSPH_E_DEVICE;
+    t.ptr[dev] = static_cast<char *>(p);
+  }
+  if (t.busy[dev]) return MPSPH_E_STATE;
+  const size_t need = mpsph_workspace_bytes(params, n);
+  if (need == 0) return MPSPH_E_INVALID;
+  if (need > kScratchBytes) return MPSPH_E_SCRATCH;
+  // the workspace is zeroed by the set-up of the context, so nothing of an earlier context that
+  // used the array survives
+  const int rc = mpsph_batch_create(1, params, &n, t.ptr[dev], kScratchBytes, hip_stream, out);
+  if (rc != MPSPH_OK) return rc;
+  (*out)->static_dev = dev;
+  t.busy[dev] = true;
+  return MPSPH_OK;
 }
 
 int mpsph_configure(mpsph_ctx *ctx, int32_t cell_log2, int32_t lanes) {
@@ -2841,6 +2888,8 @@ int mpsph_grad(mpsph_ctx *ctx, int32_t nsteps, int32_t ckpt_every, double lambda
                double *grad_coeff_out, float *d_grad_pos) {
   if (!ctx || nsteps < 0 || ckpt_every < 1 || !std::isfinite(lambda)) return MPSPH_E_INVALID;
   if (ctx->poisoned || !ctx->loaded) return MPSPH_E_STATE;
+  // the gradient driver allocates its checkpoint memory; a static-scratch context must not
+  if (ctx->static_dev >= 0) return MPSPH_E_UNSUPPORTED;
   const Domain &dm = ctx->dom[0];
   if (ctx->L.ndom != 1 || dm.p.geometry != MPSPH_BOX || dm.p.t0 == -2 || dm.p.seeded ||
       (dm.p.field != MPSPH_RBF_EXP && dm.p.field != MPSPH_UNIFORM))
@@ -2879,6 +2928,11 @@ void mpsph_destroy(mpsph_ctx *ctx) {
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->owns && ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->gmem) (void)hipFree(ctx->gmem);
+  if (ctx->static_dev >= 0) {
+    ScratchTable &t = scratch_table();
+    std::lock_guard<std::mutex> lock(t.mu);
+    t.busy[ctx->static_dev] = false;
+  }
   delete ctx;
 }
 

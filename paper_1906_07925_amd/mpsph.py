@@ -20,7 +20,7 @@ FIELDS = {"rho": 0, "rho_t": 1, "h": 2, "a": 3, "a_abs": 4, "vt": 5, "at": 6, "v
           "x0": 10}
 VECTOR_FIELDS = {"a", "vt", "at", "v", "dr", "x0"}
 ERRORS = {1: "invalid argument", 2: "out of memory", 3: "device error", 4: "bad context state",
-          5: "non-finite values", 6: "unsupported configuration"}
+          5: "non-finite values", 6: "unsupported configuration", 7: "exceeds the static scratch array"}
 
 
 class MpsphError(RuntimeError):
@@ -84,6 +84,7 @@ def lib():
             "mpsph_workspace_bytes": (C.c_size_t, [P, I64]),
             "mpsph_batch_workspace_bytes": (C.c_size_t, [I32, P, C.POINTER(I64)]),
             "mpsph_create": (C.c_int, [P, I64, V, C.c_size_t, V, C.POINTER(V)]),
+            "mpsph_create_static": (C.c_int, [P, I64, V, C.POINTER(V)]),
             "mpsph_batch_create": (C.c_int, [I32, P, C.POINTER(I64), V, C.c_size_t, V, C.POINTER(V)]),
             "mpsph_domain_count": (C.c_int, [V, C.POINTER(I32), C.POINTER(I64)]),
             "mpsph_step_graph": (C.c_int, [V, I32]),
@@ -210,9 +211,11 @@ class Relaxer:
 
     ``spec`` is one workload spec (one domain of ``n`` particles) or a list of specs (a batch of
     independent domains advanced by the same launches; ``n`` and ``s0`` are then lists too, and
-    the particle arrays hold the domains one after the other)."""
+    the particle arrays hold the domains one after the other).  ``static`` creates a one-domain
+    context on the library's static scratch array (mpsph_create_static: no device allocation)."""
 
-    def __init__(self, spec, n=None, s0=None, cell_log2: int = -1, debug: bool = False, stream=None):
+    def __init__(self, spec, n=None, s0=None, cell_log2: int = -1, debug: bool = False, stream=None,
+                 static: bool = False):
         import torch
         self._torch = torch
         specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
@@ -233,6 +236,12 @@ class Relaxer:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self._ctx = C.c_void_p()
+        if static:
+            if self.ndom != 1:
+                raise ValueError("a static-scratch context holds one domain")
+            _check(lib().mpsph_create_static(C.byref(self.params[0]), ns[0], C.c_void_p(stream.cuda_stream),
+                                             C.byref(self._ctx)), "mpsph_create_static")
+            return
         cnt = (C.c_int64 * self.ndom)(*ns)
         _check(lib().mpsph_batch_create(self.ndom, self.params, cnt, None, 0, C.c_void_p(stream.cuda_stream),
                                         C.byref(self._ctx)), "mpsph_batch_create")
