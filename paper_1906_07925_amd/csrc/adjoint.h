@@ -27,10 +27,12 @@
 #include "pair_scan.h"
 
 // Waves per SIMD the viscous adjoint is compiled for; 0 leaves it to the compiler (5 waves in 3D).
-// 7 waves spill 68 bytes per lane yet make the reverse sweep of the 2^20-particle RBF cube about
-// 1 % faster than 6 waves or the compiler's choice (118.8 / 119.3 / 120.0 ms).
+// With the particle's own data scoped to the pair loop and its per-group values in LDS, 6 waves
+// (80 VGPRs) need no scratch memory; 7 waves still spill 28 bytes per lane in 3D.  Reverse sweep
+// of the 2^20-particle RBF cube over 50 steps: 116.4 ms at 6 waves, 115.2 ms at 7 (68 bytes of
+// spills before these changes: 116.3 ms).
 #ifndef MPSPH_ADJ_WAVES
-#define MPSPH_ADJ_WAVES 7
+#define MPSPH_ADJ_WAVES 6
 #endif
 #if MPSPH_ADJ_WAVES > 0
 #define MPSPH_ADJ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MPSPH_ADJ_WAVES, MPSPH_ADJ_WAVES)))
@@ -199,11 +201,26 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
   const int local = lb * kBlock + threadIdx.x;
   const int i = local / L, sub = local % L;
   __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
+  // per lane group, the particle's (v~, eta) and (a~-bar, d s^(2d)/ds): read from LDS by the
+  // pair terms instead of being held in registers across the pair loop
+  __shared__ float4 gdat[kBlock / L][2];
   const float dt1 = read_dt1(tp.dts);
   const float hdt = 0.5f * dt1;
   double part[1] = {0.0};
   const int ops[1] = {0};
+  if (i < dom->n && sub == 0) {
+    const float4 ai = tp.acc[i];
+    const float4 abi = abv[i];
+    const float si = tp.wpos[i].w * sp.inv_tau;
+    gdat[threadIdx.x / L][0] = make_float4(hdt * ai.x, hdt * ai.y, hdt * ai.z, hdt * ai.w);
+    gdat[threadIdx.x / L][1] = make_float4(abi.x, abi.y, abi.z, (2.f * (float)D) * pow2d<D>(si) / si);
+  }
+  __syncthreads();
   if (i < dom->n) {
+    float vb[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, eb = 0.f, sb = 0.f;
+    {
+    // the pair sum; the particle's own data is scoped to it (the epilogue reads it again), so
+    // that the kernel fits its register budget without spilling
     int ci[3];
     unpack_key<D>(tp.wkey[i], g, ci);
     const float4 pi = tp.wpos[i];
@@ -211,13 +228,10 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
     const int ti = (tp.wjaux[i] >> 12) & 3;
     const float hi = pi.w, si = hi * sp.inv_tau;
     const float s2di = pow2d<D>(si);
-    const float4 ai = tp.acc[i];
-    const float vti[3] = {hdt * ai.x, hdt * ai.y, hdt * ai.z};
-    const float ei = hdt * ai.w;
-    const float4 abi = abv[i];
+    const float4 *gd = gdat[threadIdx.x / L];
+    const float ei = gd[0].w;
     const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
     const float kh = 0.5f * sp.kappa, a5 = 5.f * sp.alpha, a75 = 7.5f * sp.alpha;
-    float vb[3] = {0.f, 0.f, 0.f}, xb[3] = {0.f, 0.f, 0.f}, eb = 0.f, sb = 0.f;
     if (ei > 0.f) {
       const BufRes rpos = buf_res(tp.wpos, 16, (uint32_t)g.n), raux = buf_res(tp.wjaux, 4, (uint32_t)g.n);
       scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
@@ -241,6 +255,8 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
         if (!(ej > 0.f)) return;  // eta_j = 0: the pair's K and every derivative of it vanish
         const float mkj = tj >= ti ? 1.f : 0.f, mjk = ti >= tj ? 1.f : 0.f;
         const float4 abj = abv[j];
+        const float4 vti = gd[0], abi = gd[1];
+        const float ds2i = abi.w;
         const float wv[3] = {mkj * abi.x - mjk * abj.x, mkj * abi.y - mjk * abj.y, mkj * abi.z - mjk * abj.z};
         const float rinv = fast_rsq(r2);
         const float r = r2 * rinv;
@@ -260,15 +276,16 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
         vb[0] = fmaf(K, wv[0], vb[0]);
         vb[1] = fmaf(K, wv[1], vb[1]);
         if constexpr (D == 3) vb[2] = fmaf(K, wv[2], vb[2]);
-        const float dvx = vti[0] - hdt * aj4.x, dvy = vti[1] - hdt * aj4.y, dvz = vti[2] - hdt * aj4.z;
+        const float dvx = vti.x - hdt * aj4.x, dvy = vti.y - hdt * aj4.y, dvz = vti.z - hdt * aj4.z;
         const float kb = wv[0] * dvx + wv[1] * dvy + (D == 3 ? wv[2] * dvz : 0.f);
         eb = fmaf(kb * (-S * gg) * 2.f * ej * ej, iesum * iesum, eb);
-        sb = fmaf(kb * (-hm), (2.f * (float)D) * s2di / si * gg + S * dgh * (0.5f * sp.tau), sb);
+        sb = fmaf(kb * (-hm), ds2i * gg + S * dgh * (0.5f * sp.tau), sb);
         const float cx = kb * (-hm * S * dgr) * rinv;
         xb[0] = fmaf(cx, dx, xb[0]);
         xb[1] = fmaf(cx, dy, xb[1]);
         if constexpr (D == 3) xb[2] = fmaf(cx, dz, xb[2]);
       });
+    }
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -278,7 +295,14 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
     eb = group_sum<L>(eb);
     sb = group_sum<L>(sb);
     if (sub == 0) {
-      const float4 vd = vtb[i];
+      // the particle's own data again, through an index the compiler cannot tie to i, so that
+      // neither values nor addresses stay live across the pair loop
+      const int io = __shfl(i, (int)(threadIdx.x & (kWave - 1)));
+      const float si = tp.wpos[io].w * sp.inv_tau;
+      const int ti = (tp.wjaux[io] >> 12) & 3;
+      const float4 ai = tp.acc[io];
+      const float vti[3] = {hdt * ai.x, hdt * ai.y, hdt * ai.z};
+      const float4 vd = vtb[io];
       float vt[3] = {vd.x + vb[0], vd.y + vb[1], vd.z + vb[2]};
       const float vm2 = vti[0] * vti[0] + vti[1] * vti[1] + (D == 3 ? vti[2] * vti[2] : 0.f);
       if (vm2 > 0.f && eb != 0.f) {
@@ -300,11 +324,11 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
           t1 += 0.5 * (double)av[a] * (double)vt[a];
         }
       }
-      abar[i] = make_float4(ab[0], ab[1], ab[2], 0.f);
-      sbar[i] = sb;
-      const float4 x0 = xacc[i];
-      xacc[i] = make_float4(x0.x + xb[0], x0.y + xb[1], x0.z + xb[2], 0.f);
-      if (__float_as_uint(dtc[i]) == *minbits) atomicMin(argmin, (uint32_t)i);
+      abar[io] = make_float4(ab[0], ab[1], ab[2], 0.f);
+      sbar[io] = sb;
+      const float4 x0 = xacc[io];
+      xacc[io] = make_float4(x0.x + xb[0], x0.y + xb[1], x0.z + xb[2], 0.f);
+      if (__float_as_uint(dtc[io]) == *minbits) atomicMin(argmin, (uint32_t)io);
       part[0] = t1;
     }
   }
