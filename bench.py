@@ -358,6 +358,66 @@ def features_run(torch, M, W, k: int, lanes: int, steps: int = 100, warmup: int 
             "types_kept": kept, "residual_l2": m["residual_l2"], "nonfinite": m["nonfinite"]}
 
 
+def variants_run(torch, M, W, steps: int = 100, warmup: int = 20, graph_steps: int = 10):
+    """The pair-kernel variants of mpsph_set_pair_variant on the headline workload (2^6 cells, 8
+    lanes; steps timed after a warm-up from the jittered lattice, HIP events on the library
+    stream) and on the 64-domain batch (graph replays).  Every variant computes the same step;
+    the final states are compared bit for bit."""
+    cfg = W.config(WORKLOAD)
+    x, col, typ = W.make_state(cfg)
+    dx, dc = torch.from_numpy(x.astype(np.float32)).cuda(), torch.from_numpy(col).cuda()
+    out = {"cube": {}, "batched": {}}
+    ref = None
+    for v in ("default", "persistent", "tile"):
+        R = M.Relaxer(cfg["spec"], n=x.shape[0])
+        R.configure(6, 8)
+        R.set_pair_variant(v)
+        R.load(dx, dc)
+        R.step(warmup)
+        torch.cuda.synchronize()
+        R.profile(True)
+        t0 = time.perf_counter()
+        R.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kern = R.profile_read()
+        R.profile(False)
+        xs = R.store()[0].cpu().numpy()
+        ref = xs if ref is None else ref
+        out["cube"][v] = {"ms_per_step": 1e3 * dt / steps,
+                          "pass_ms": {k: kv[1] / steps for k, kv in kern.items() if k.startswith("pass")},
+                          "same_state_as_default": bool(np.array_equal(xs, ref))}
+        R.close()
+        print(f"[bench] variants: cube {v} {1e3 * dt / steps:.3f} ms/step", file=sys.stderr, flush=True)
+    cfgs = W.batched_domains()
+    states = [W.make_state(c) for c in cfgs]
+    specs = [dict(c["spec"], n=st[0].shape[0]) for c, st in zip(cfgs, states)]
+    ns = [st[0].shape[0] for st in states]
+    xa = np.concatenate([st[0].astype(np.float32).reshape(-1) for st in states])
+    ca = np.concatenate([st[1] for st in states]).astype(np.int32)
+    ta = np.concatenate([st[2] for st in states]).astype(np.int32)
+    ref = None
+    for v in ("default", "persistent", "tile"):
+        B = M.Relaxer(specs, n=ns)
+        B.set_pair_variant(v)
+        B.load(torch.from_numpy(xa).cuda(), torch.from_numpy(ca).cuda(), torch.from_numpy(ta).cuda())
+        B.step(warmup)
+        B.step_graph(graph_steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps // graph_steps - 1):
+            B.step_graph(graph_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        timed = (steps // graph_steps - 1) * graph_steps
+        xs = B.store()[0].cpu().numpy()
+        ref = xs if ref is None else ref
+        out["batched"][v] = {"ms_per_step": 1e3 * dt / timed, "same_state_as_default": bool(np.array_equal(xs, ref))}
+        B.close()
+        print(f"[bench] variants: batch {v} {1e3 * dt / timed:.3f} ms/step", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,7 +433,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-mesh", action="store_true", help="skip the background-mesh workload")
     ap.add_argument("--no-features", action="store_true", help="skip the seeded-feature workload")
-    ap.add_argument("--leg", choices=("batched", "mesh", "adjoint"), default="",
+    ap.add_argument("--leg", choices=("batched", "mesh", "adjoint", "variants"), default="",
                     help="run only this secondary workload and print its record (for a kernel trace of it)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -389,7 +449,8 @@ def main():
     if args.leg:
         legs = {"batched": lambda: batched_run(torch, M, W, args.batched_steps, 10),
                 "mesh": lambda: mesh_run(torch, M, W),
-                "adjoint": lambda: adjoint_run(torch, M, W)}
+                "adjoint": lambda: adjoint_run(torch, M, W),
+                "variants": lambda: variants_run(torch, M, W)}
         print(json.dumps({"leg": args.leg, **legs[args.leg]()}))
         return
 

@@ -268,6 +268,26 @@ MPSPH_API int mpsph_load(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_co
  * workspace; the context is unchanged). */
 MPSPH_API int mpsph_configure(mpsph_ctx *ctx, int32_t cell_log2, int32_t lanes);
 
+/* Pair-kernel variants (mpsph_set_pair_variant).  Every variant computes the same step bit for bit;
+ * they differ in how the work reaches the GPU:
+ *   MPSPH_PAIRS_DEFAULT     one launch per pass and dimension group, a block per 256 threads;
+ *   MPSPH_PAIRS_PERSISTENT  one persistent launch per pass for all domains of both dimensions: a
+ *                           fixed grid (8 blocks per CU) takes the blocks from a work queue in
+ *                           device memory (one range per XCD, then stealing), so that uneven
+ *                           domains of a batch share every CU (the paper's parallel environment, §3.8, runs
+ *                           many sub-domains per node; here many domains per device);
+ *   MPSPH_PAIRS_TILE        the density pass of 3D regions without periodic wrap stages the
+ *                           neighbours of each block's particles in LDS once (the union of their
+ *                           candidate rows, at most 768 particles; larger blocks read through
+ *                           the caches) and reads them from there.
+ * Measured on MI355X: the default is the fastest on the graded cube and on a 64-domain
+ * batch; the others are kept selectable and tested. */
+enum { MPSPH_PAIRS_DEFAULT = 0, MPSPH_PAIRS_PERSISTENT = 1, MPSPH_PAIRS_TILE = 2 };
+
+/* Selects the pair-kernel variant of the context's steps (drops a captured step graph).  The
+ * state and the layout are kept.  Errors: MPSPH_E_INVALID (unknown variant), MPSPH_E_STATE. */
+MPSPH_API int mpsph_set_pair_variant(mpsph_ctx *ctx, int32_t variant);
+
 /* Autotuner of the cell size and of the lanes per particle of the pair kernels.  For every
  * candidate -- cell exponent of the size rule minus one, the rule's, plus one (for domains
  * whose cell_log2 is -1; a fixed cell_log2 is kept), times 2, 4 or 8 lanes per particle -- the

@@ -65,10 +65,18 @@ constexpr int row_table_stride() {
 // dz0 = ci[2] - cz (cell units); an invalid slot (past the chunk's end, or the particle itself)
 // may carry an index outside the arrays.  The return value is the group's candidate count
 // (the particle itself excluded), the same in every lane of the group.
-template <int D, int L, int C, bool PER = false, typename BodyF>
+// The row's base index goes through remap(cy, cz, a) (a: the global index of the row's first
+// candidate) before it enters the table, so that the slots can index a staged copy of the
+// neighbours; self is the particle's own index in that numbering.
+struct IdentityRemap {
+  __device__ __forceinline__ uint32_t operator()(int, int, uint32_t a) const { return a; }
+};
+template <int D, int L, int C, bool PER = false, typename BodyF, typename RemapF = IdentityRemap>
 __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab, int stride, const int *ci,
                                                      const float *oi, float rs, const GridDev &g, uint32_t cellbase,
-                                                     const uint32_t *__restrict__ cstart, BodyF &&body) {
+                                                     const uint32_t *__restrict__ cstart, BodyF &&body,
+                                                     RemapF remap = RemapF(), uint32_t self = 0xFFFFFFFFu) {
+  if (self == 0xFFFFFFFFu) self = (uint32_t)i;
   static_assert(C >= L, "a table chunk holds at least one round of rows");
   // one lane per particle is not supported: with no cross-lane operation in the loop nest the
   // compiler merged the chunk loop with the table loop and took the chunk loop's exit mask from a
@@ -161,7 +169,7 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
         const uint32_t end = run + incl;   // end of the row in the chunk's slot order
         const float dyr = (float)(ci[1] - cy), dzr = D == 3 ? (float)(ci[2] - cz) : 0.f;
         tab[(ne + nz - 1u) * (uint32_t)stride] =
-            make_uint4(a - (end - len), end, __float_as_uint(dyr), __float_as_uint(dzr));
+            make_uint4(remap(cy, cz, a) - (end - len), end, __float_as_uint(dyr), __float_as_uint(dzr));
       }
       run += __shfl(incl, L - 1, L);
       ne += __shfl(nz, L - 1, L);
@@ -177,7 +185,7 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
       const uint32_t j = cur.x + t;
       // slots past the end carry an index that may lie outside the arrays: bodies must load
       // through bounds-checked buffer loads or clamp it with the valid flag
-      body(j, __uint_as_float(cur.z), __uint_as_float(cur.w), t < run && j != (uint32_t)i);
+      body(j, __uint_as_float(cur.z), __uint_as_float(cur.w), t < run && j != self);
     }
   }
   return total > 0u ? total - 1u : 0u;

@@ -99,6 +99,7 @@ def lib():
             "mpsph_set_field_coeff": (C.c_int, [V, I32, C.POINTER(C.c_double)]),
             "mpsph_autotune": (C.c_int, [V, V, V, V, I32, I32, C.POINTER(I32), C.POINTER(I32)]),
             "mpsph_configure": (C.c_int, [V, I32, I32]),
+            "mpsph_set_pair_variant": (C.c_int, [V, I32]),
             "mpsph_grad": (C.c_int, [V, I32, I32, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double), V]),
             "mpsph_profile": (C.c_int, [V, I32]),
             "mpsph_profile_read": (C.c_int, [V, I32, C.POINTER(C.c_char_p), C.POINTER(I64),
@@ -295,6 +296,12 @@ class Relaxer:
         """Set the cell exponent (-1: size rule) and the lanes per particle; load again after."""
         _check(lib().mpsph_configure(self._ctx, int(cell_log2), int(lanes)), "mpsph_configure")
         self.lanes = int(lanes)
+
+    def set_pair_variant(self, variant: str):
+        """Pair-kernel variant: 'default', 'persistent' (work-queue launch over all domains) or
+        'tile' (LDS-staged density pass, 3D).  Every variant computes the same step."""
+        code = {"default": 0, "persistent": 1, "tile": 2}[variant]
+        _check(lib().mpsph_set_pair_variant(self._ctx, code), "mpsph_set_pair_variant")
 
     def autotune(self, x, colour, ptype=None, probe_steps: int = 5, warm_steps: int | None = None):
         """Pick the cell size and lanes per particle by timing probe_steps steps after warm_steps

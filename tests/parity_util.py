@@ -23,13 +23,15 @@ def oracle_step(spec, s0, x32, col, typ, step_index=0, search="grid"):
     return op, x1, t1, r
 
 
-def gpu_run(spec, s0, x32, col, typ, steps=1, cell_log2=-1, debug=True, fields=FIELDS, lanes=None):
+def gpu_run(spec, s0, x32, col, typ, steps=1, cell_log2=-1, debug=True, fields=FIELDS, lanes=None, variant=None):
     import torch
     from paper_1906_07925_amd import mpsph as M
     n = x32.shape[0]
     R = M.Relaxer(spec, n=n, s0=s0, cell_log2=cell_log2, debug=debug)
     if lanes is not None:
         R.configure(cell_log2, lanes)
+    if variant is not None:
+        R.set_pair_variant(variant)
     R.load(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
     R.step(steps)
     m = R.metrics(allow_nonfinite=True)
@@ -124,9 +126,9 @@ def compare_step(spec, x32, x1, t1, r, m, g, k, tol=1e-5, report=None):
     return errs
 
 
-def check_single_step(spec, s0, x32, col, typ, tol=1e-5, cell_log2=-1, report=None, lanes=None):
+def check_single_step(spec, s0, x32, col, typ, tol=1e-5, cell_log2=-1, report=None, lanes=None, variant=None):
     """Single step from identical FP32 inputs: GPU FP32 vs oracle FP64, per quantity (bounds in
     compare_step)."""
     op, x1, t1, r = oracle_step(spec, s0, x32, col, typ)
-    m, g = gpu_run(spec, s0, x32, col, typ, cell_log2=cell_log2, lanes=lanes)
+    m, g = gpu_run(spec, s0, x32, col, typ, cell_log2=cell_log2, lanes=lanes, variant=variant)
     return compare_step(spec, x32, x1, t1, r, m, g, g["k"], tol=tol, report=report)
