@@ -234,11 +234,15 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
     const float kh = 0.5f * sp.kappa, a5 = 5.f * sp.alpha, a75 = 7.5f * sp.alpha;
     if (ei > 0.f) {
       const BufRes rpos = buf_res(tp.wpos, 16, (uint32_t)g.n), raux = buf_res(tp.wjaux, 4, (uint32_t)g.n);
+      const BufRes racc = buf_res(tp.acc, 16, (uint32_t)g.n), rabv = buf_res(abv, 16, (uint32_t)g.n);
       scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
                                                  0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-        const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
+        // past the arrays for invalid slots: bounds-checked loads, all issued before the range
+        // test so that their latency overlaps it
         const float4 pj = buf_f4(rpos, jr);
         const uint32_t aj = buf_u32(raux, jr);
+        const float4 aj4 = buf_f4(racc, jr);
+        const float4 abj = buf_f4(rabv, jr);
         const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
         const float dy = dy0 + (oi[1] - pj.y);
         float dz = 0.f;
@@ -250,11 +254,9 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
         const float hij = kh * (hi + pj.w);
         if (!(v && r2 > 1e-30f && r2 < hij * hij)) return;
         const int tj = (aj >> 12) & 3;
-        const float4 aj4 = tp.acc[j];
         const float ej = hdt * aj4.w;
         if (!(ej > 0.f)) return;  // eta_j = 0: the pair's K and every derivative of it vanish
         const float mkj = tj >= ti ? 1.f : 0.f, mjk = ti >= tj ? 1.f : 0.f;
-        const float4 abj = abv[j];
         const float4 vti = gd[0], abi = gd[1];
         const float ds2i = abi.w;
         const float wv[3] = {mkj * abi.x - mjk * abj.x, mkj * abi.y - mjk * abj.y, mkj * abi.z - mjk * abj.z};
@@ -415,11 +417,13 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
   const float opb = 1.f + sigma_of(sp, tstep);   // surface tension of the step (Eq. 24-25)
   float xb[3] = {0.f, 0.f, 0.f}, sb = 0.f;
   const BufRes rpos = buf_res(tp.wpos, 16, (uint32_t)g.n), raux = buf_res(tp.wjaux, 4, (uint32_t)g.n);
+  const BufRes rfb = buf_res(fbar, 16, (uint32_t)g.n);
   scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
                                                  0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-    const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
+    // past the arrays for invalid slots: bounds-checked loads, all issued before the range test
     const float4 pj = buf_f4(rpos, jr);
     const uint32_t aj = buf_u32(raux, jr);
+    const float4 fj = buf_f4(rfb, jr);
     const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
     const float dy = dy0 + (oi[1] - pj.y);
     float dz = 0.f;
@@ -432,7 +436,6 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
     if (!(v && r2 > 1e-30f && r2 < hij * hij)) return;
     const int tj = (aj >> 12) & 3;
     const float mkj = tj >= ti ? 1.f : 0.f, mjk = ti >= tj ? 1.f : 0.f;
-    const float4 fj = fbar[j];
     const float wf[3] = {mkj * fi.x - mjk * fj.x, mkj * fi.y - mjk * fj.y, mkj * fi.z - mjk * fj.z};
     const float rinv = fast_rsq(r2);
     const float r = r2 * rinv;
