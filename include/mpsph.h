@@ -280,8 +280,8 @@ MPSPH_API int mpsph_configure(mpsph_ctx *ctx, int32_t cell_log2, int32_t lanes);
  *                           neighbours of each block's particles in LDS once (the union of their
  *                           candidate rows, at most 768 particles; larger blocks read through
  *                           the caches) and reads them from there.
- * Measured on MI355X: the default is the fastest on the graded cube and on a 64-domain
- * batch; the others are kept selectable and tested. */
+ * Measured on MI355X: the default is the fastest on the graded cube and on a 64-domain batch; the
+ * others are kept selectable and tested. */
 enum { MPSPH_PAIRS_DEFAULT = 0, MPSPH_PAIRS_PERSISTENT = 1, MPSPH_PAIRS_TILE = 2 };
 
 /* Selects the pair-kernel variant of the context's steps (drops a captured step graph).  The

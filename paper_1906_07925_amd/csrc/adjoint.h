@@ -244,11 +244,11 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
         const float4 aj4 = buf_f4(racc, jr);
         const float4 abj = buf_f4(rabv, jr);
         const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
-        const float dy = dy0 + (oi[1] - pj.y);
+        const float dy = dy0 - pj.y;
         float dz = 0.f;
         float r2 = dx * dx + dy * dy;
         if constexpr (D == 3) {
-          dz = dz0 + (oi[2] - pj.z);
+          dz = dz0 - pj.z;
           r2 += dz * dz;
         }
         const float hij = kh * (hi + pj.w);
@@ -425,11 +425,11 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
     const uint32_t aj = buf_u32(raux, jr);
     const float4 fj = buf_f4(rfb, jr);
     const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
-    const float dy = dy0 + (oi[1] - pj.y);
+    const float dy = dy0 - pj.y;
     float dz = 0.f;
     float r2 = dx * dx + dy * dy;
     if constexpr (D == 3) {
-      dz = dz0 + (oi[2] - pj.z);
+      dz = dz0 - pj.z;
       r2 += dz * dz;
     }
     const float hij = kh * (hi + pj.w);
@@ -570,10 +570,10 @@ __global__ __launch_bounds__(kBlock) void loss_density(const DomDev *__restrict_
       const float4 pj = buf_f4(rpos, jr);
       const uint32_t aj = buf_u32(raux, jr);
       const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
-      const float dy = dy0 + (oi[1] - pj.y);
+      const float dy = dy0 - pj.y;
       float r2 = dx * dx + dy * dy;
       if constexpr (D == 3) {
-        const float dz = dz0 + (oi[2] - pj.z);
+        const float dz = dz0 - pj.z;
         r2 += dz * dz;
       }
       if (!v) return;
@@ -637,11 +637,11 @@ __global__ __launch_bounds__(kBlock) void loss_grad(const DomDev *__restrict__ d
     const float4 pj = buf_f4(rpos, jr);
     const uint32_t aj = buf_u32(raux, jr);
     const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
-    const float dy = dy0 + (oi[1] - pj.y);
+    const float dy = dy0 - pj.y;
     float dz = 0.f;
     float r2 = dx * dx + dy * dy;
     if constexpr (D == 3) {
-      dz = dz0 + (oi[2] - pj.z);
+      dz = dz0 - pj.z;
       r2 += dz * dz;
     }
     if (!(v && r2 > 1e-30f)) return;

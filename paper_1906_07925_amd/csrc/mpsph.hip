@@ -288,7 +288,7 @@ __device__ bool stage_tile(TileLds *T, bool active, int sub, const int *ci, cons
       const float ey = ly > 0.f ? ly : (hy < 0.f ? -hy : 0.f);
       const float d2 = ey * ey + ez * ez;
       if (d2 < rs2) {
-        const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
+        const float wx = fast_sqrt(fmaxf(rs2 - d2, 0.f));
         const int x0 = max(0, (ci[0] << g.xe) + (int)floorf((oi[0] - wx) * fx));
         const int x1 = min(xlast, (ci[0] << g.xe) + (int)floorf((oi[0] + wx) * fx));
         const int r = (cz - T->z0) * W + (cy - T->y0);
@@ -414,11 +414,11 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
     const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
     const auto pair = [&](const float4 pj, const uint32_t aj, float dy0, float dz0, bool v) {
       const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
-      const float dy = dy0 + (oi[1] - pj.y);
+      const float dy = dy0 - pj.y;
       float r2 = dx * dx + dy * dy;
       float dz = 0.f;
       if constexpr (D == 3) {
-        dz = dz0 + (oi[2] - pj.z);
+        dz = dz0 - pj.z;
         r2 += dz * dz;
       }
       const float hs = hi + pj.w;                   // 2 h_ij
@@ -628,10 +628,10 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
           // issued with the position load so that its latency overlaps the range test
           const float4 accj = buf_f4(racc, j);
           const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
-          const float dy = dy0 + (oi[1] - pj.y);
+          const float dy = dy0 - pj.y;
           float r2 = dx * dx + dy * dy;
           if constexpr (D == 3) {
-            const float dz = dz0 + (oi[2] - pj.z);
+            const float dz = dz0 - pj.z;
             r2 += dz * dz;
           }
           const float hs = hi + pj.w;   // 2 h_ij
@@ -930,14 +930,15 @@ __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ 
   __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
   scan_group_table<D, L, row_table_rows<L>(), PER>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs,
                                                    g, dd.cellbase, cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-    const int j = v ? (int)jr : i;  // slots past the end carry an index outside the arrays
+    // a slot past the chunk's end may carry an index outside the arrays (and NaN offsets)
+    const int j = v && jr < (uint32_t)g.n ? (int)jr : i;
     const float4 pj = wpos[j];
     const uint32_t aj = wjaux[j];
     const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
-    const float dy = dy0 + (oi[1] - pj.y);
+    const float dy = dy0 - pj.y;
     float r2 = dx * dx + dy * dy;
     if constexpr (D == 3) {
-      const float dz = dz0 + (oi[2] - pj.z);
+      const float dz = dz0 - pj.z;
       r2 += dz * dz;
     }
     const float hij = kh * (hi + pj.w);

@@ -42,7 +42,7 @@ __device__ __forceinline__ float sep_x(const GridDev &g, int cxi, int cxj, float
 #endif
 template <int L>
 constexpr int row_table_rows() {
-  return MPSPH_ROW_TABLE * L / 4 < L ? L : MPSPH_ROW_TABLE * L / 4;
+  return MPSPH_ROW_TABLE * L / 4 < L + 1 ? L + 1 : MPSPH_ROW_TABLE * L / 4;
 }
 // Entries between two rows of one group's column (one more than the groups of a block, so that
 // the columns of a wave's groups start in different banks).
@@ -58,13 +58,20 @@ constexpr int row_table_stride() {
 // slot order of the particle's candidates, row offsets.  Then the group visits the slots L at a
 // time, lane l taking every L-th one and advancing through the table as its slot index passes
 // the end of a row.  A group's loop ends when its own candidates end (no wave-wide rounds of
-// rows).  A table holds at most C rows; a particle with more non-empty rows is scanned in
-// several chunks.
-// tab: the group's column of the table, entry e at tab[e * stride]; C >= L.
-// body(j, dy0, dz0, valid) is called for every slot with the row offsets dy0 = ci[1] - cy and
-// dz0 = ci[2] - cz (cell units); an invalid slot (past the chunk's end, or the particle itself)
-// may carry an index outside the arrays.  The return value is the group's candidate count
-// (the particle itself excluded), the same in every lane of the group.
+// rows).  A table holds at most C - 1 rows and an end marker; a particle with more non-empty
+// rows is scanned in several chunks.
+// The end marker (end of run 2^32 - 1, row offsets NaN) stops every lane's walk through the
+// table, so the slot loop tests neither the table's length nor the chunk's: a slot past the
+// chunk's end reaches the marker and gets the index t - run (in [0, L)) and NaN offsets, which
+// make its squared distance NaN and fail every range test of the bodies.
+// tab: the group's column of the table, entry e at tab[e * stride]; C > L.
+// body(j, dy0, dz0, valid) is called for every slot with the row offsets plus the particle's own
+// offsets, dy0 = ci[1] - cy + oi[1] and dz0 = ci[2] - cz + oi[2] (cell units; the y and z
+// separations are dy0 - oj[1] and dz0 - oj[2]); valid is false for the particle itself.  A slot
+// past the chunk's end carries NaN offsets and an index below L that may still lie outside the
+// arrays (fewer than L particles): bodies load through bounds-checked buffer loads or clamp the
+// index, and must fail their range tests on a NaN distance.  The return value is the group's
+// candidate count (the particle itself excluded), the same in every lane of the group.
 // The row's base index goes through remap(cy, cz, a) (a: the global index of the row's first
 // candidate) before it enters the table, so that the slots can index a staged copy of the
 // neighbours; self is the particle's own index in that numbering.
@@ -77,7 +84,7 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
                                                      const uint32_t *__restrict__ cstart, BodyF &&body,
                                                      RemapF remap = RemapF(), uint32_t self = 0xFFFFFFFFu) {
   if (self == 0xFFFFFFFFu) self = (uint32_t)i;
-  static_assert(C >= L, "a table chunk holds at least one round of rows");
+  static_assert(C > L, "a table chunk holds at least one round of rows and the end marker");
   // one lane per particle is not supported: with no cross-lane operation in the loop nest the
   // compiler merged the chunk loop with the table loop and took the chunk loop's exit mask from a
   // compare of the divergent inner loop, and such a build listed some candidates twice (the same
@@ -120,7 +127,7 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
   while (q0 < nrows) {
     // table of the next chunk of rows: whole rounds of L rows while a round surely fits
     uint32_t ne = 0, run = 0;
-    while (q0 < nrows && ne + L <= (uint32_t)C) {
+    while (q0 < nrows && ne + L < (uint32_t)C) {
       const int q = q0 + sub;
       const int qz = (int)(((float)q + 0.5f) * inv_ny);   // q / ny (q, ny < 2^12)
       const int cz = z0 + qz, cy = y0 + (q - qz * ny);
@@ -133,7 +140,9 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
       const float ey = lo > 0.f ? lo : (hi < 0.f ? -hi : 0.f);
       const float d2 = ey * ey + ez * ez;
       const bool hit = q < nrows && d2 < rs2;
-      const float wx = sqrtf(fmaxf(rs2 - d2, 0.f));
+      // the hardware square root (about 1 ulp) is enough: the callers' reach rs exceeds every
+      // range test of the bodies by a relative 1e-4
+      const float wx = fast_sqrt(fmaxf(rs2 - d2, 0.f));
       int x0 = (ci[0] << g.xe) + (int)floorf((oi[0] - wx) * fx);
       int x1 = (ci[0] << g.xe) + (int)floorf((oi[0] + wx) * fx);
       if (per && (x0 < 0 || x1 > xlast)) {
@@ -167,25 +176,25 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
       }
       if (len > 0u) {
         const uint32_t end = run + incl;   // end of the row in the chunk's slot order
-        const float dyr = (float)(ci[1] - cy), dzr = D == 3 ? (float)(ci[2] - cz) : 0.f;
+        const float dyo = (float)(ci[1] - cy) + oi[1], dzo = D == 3 ? (float)(ci[2] - cz) + oi[2] : 0.f;
         tab[(ne + nz - 1u) * (uint32_t)stride] =
-            make_uint4(remap(cy, cz, a) - (end - len), end, __float_as_uint(dyr), __float_as_uint(dzr));
+            make_uint4(remap(cy, cz, a) - (end - len), end, __float_as_uint(dyo), __float_as_uint(dzo));
       }
       run += __shfl(incl, L - 1, L);
       ne += __shfl(nz, L - 1, L);
       q0 += L;
     }
+    // end marker (ne < C): base -run, so that slot t past the end maps to index t - run
+    if (sub == 0) tab[ne * (uint32_t)stride] = make_uint4(0u - run, 0xFFFFFFFFu, 0x7FC00000u, 0x7FC00000u);
     total += run;
     // the chunk's slots, L at a time; slot t of row e is candidate base_e + t
     uint32_t e = 0;
     uint4 cur = tab[0];
     for (uint32_t t0 = 0; t0 < run; t0 += L) {
       const uint32_t t = t0 + (uint32_t)sub;
-      while (t >= cur.y && e + 1u < ne) cur = tab[++e * (uint32_t)stride];
+      while (t >= cur.y) cur = tab[++e * (uint32_t)stride];
       const uint32_t j = cur.x + t;
-      // slots past the end carry an index that may lie outside the arrays: bodies must load
-      // through bounds-checked buffer loads or clamp it with the valid flag
-      body(j, __uint_as_float(cur.z), __uint_as_float(cur.w), t < run && j != self);
+      body(j, __uint_as_float(cur.z), __uint_as_float(cur.w), j != self);
     }
   }
   return total > 0u ? total - 1u : 0u;

@@ -1,7 +1,7 @@
 """HIP path vs the FP64 oracle: single-step parity on every configuration, bit-exact cell
 keys / cell table, invariances that must hold bit for bit, edge cases, and full-size checks.
 
-Tolerances (derived in the design doc): the GPU computes in FP32 from the same FP32 inputs; sums
+Tolerances: the GPU computes in FP32 from the same FP32 inputs; sums
 of <= ~10^3 terms carry a relative rounding error of at most a few 1e-6 of the sum of the
 absolute terms, so each accumulated quantity is compared against 1e-5 times its own
 condition scale (the oracle's sum of |pair terms|), normwise quantities against 1e-5.
