@@ -6,6 +6,12 @@
 
 #include "mpsph_device.h"
 
+// The candidate scan ends each chunk with NaN row offsets and relies on every range test failing
+// on a NaN distance, which finite-only floating-point modes would not keep.
+#if defined(__FAST_MATH__) || (defined(__FINITE_MATH_ONLY__) && __FINITE_MATH_ONLY__)
+#error "the pair kernels need IEEE NaN semantics: build without -ffast-math / -ffinite-math-only"
+#endif
+
 namespace mpsph {
 
 // Neighbour candidates
