@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
         const uint32_t aj = buf_u32(raux, jr);
         const float4 aj4 = buf_f4(racc, jr);
         const float4 abj = buf_f4(rabv, jr);
-        const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+        const float dx = ((float)ci[0] - cell_x<D>(aj)) + (oi[0] - pj.x);
         const float dy = dy0 - pj.y;
         float dz = 0.f;
         float r2 = dx * dx + dy * dy;
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
     const float4 pj = buf_f4(rpos, jr);
     const uint32_t aj = buf_u32(raux, jr);
     const float4 fj = buf_f4(rfb, jr);
-    const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+    const float dx = ((float)ci[0] - cell_x<D>(aj)) + (oi[0] - pj.x);
     const float dy = dy0 - pj.y;
     float dz = 0.f;
     float r2 = dx * dx + dy * dy;
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void loss_density(const DomDev *__restrict_
       // jr lies past the arrays for invalid slots: bounds-checked loads first
       const float4 pj = buf_f4(rpos, jr);
       const uint32_t aj = buf_u32(raux, jr);
-      const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+      const float dx = ((float)ci[0] - cell_x<D>(aj)) + (oi[0] - pj.x);
       const float dy = dy0 - pj.y;
       float r2 = dx * dx + dy * dy;
       if constexpr (D == 3) {
@@ -636,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void loss_grad(const DomDev *__restrict__ d
     const int j = (int)jr;  // past the arrays for invalid slots: bounds-checked loads first
     const float4 pj = buf_f4(rpos, jr);
     const uint32_t aj = buf_u32(raux, jr);
-    const float dx = (float)(ci[0] - (int)(aj & 0xFFFu)) + (oi[0] - pj.x);
+    const float dx = ((float)ci[0] - cell_x<D>(aj)) + (oi[0] - pj.x);
     const float dy = dy0 - pj.y;
     float dz = 0.f;
     float r2 = dx * dx + dy * dy;

@@ -413,7 +413,7 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
     uint32_t npair = 0, nifc = 0;
     const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
     const auto pair = [&](const float4 pj, const uint32_t aj, float dy0, float dz0, bool v) {
-      const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
+      const float dx = sep_x<PER, D>(g, (float)ci[0], aj, oi[0], pj.x);
       const float dy = dy0 - pj.y;
       float r2 = dx * dx + dy * dy;
       float dz = 0.f;
@@ -425,19 +425,22 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       const float hij = kh * hs;                    // kappa h_ij
       const bool dens = v && r2 < rci2;
       const bool inter = v && r2 < hij * hij;
-      if (!(dens || inter)) return;
-      // coincident particles (two particles clamped into one corner): r = 0, no direction
-      const bool apart = r2 > 1e-30f;
-      const float r = fast_sqrt(r2);
-      const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
-      wsum += dens ? u2 * u2 * fmaf(2.f, q, 1.f) : 0.f;
+      // the counts and the nearest distance in every lane, so that the branch below is taken
+      // only for the kernel sums
       const uint32_t colj = aj >> 14;
       const bool diff = colj != coli;
       const bool feel = inter && (int)((aj >> 12) & 3) >= ti;
       nifc += (inter && diff) ? 1u : 0u;
       npair += feel ? 1u : 0u;
       if (inter && r2 < nn2) nn2 = r2;
-      if (!(feel && apart)) return;
+      // coincident particles (two particles clamped into one corner): r = 0, no direction
+      const bool apart = r2 > 1e-30f;
+      const bool force = feel && apart;
+      if (!(dens || force)) return;
+      const float r = fast_sqrt(r2);
+      const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
+      wsum += dens ? u2 * u2 * fmaf(2.f, q, 1.f) : 0.f;
+      if (!force) return;
       const float rh = fast_rcp(hs);                // 1 / (2 h_ij)
       const float uu = fmaf(-r, rh, 1.f);           // 1 - q/2, q = r / h_ij
       const float rh2 = rh * rh;
@@ -627,7 +630,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
           const uint32_t aj = buf_u32(raux, j);
           // issued with the position load so that its latency overlaps the range test
           const float4 accj = buf_f4(racc, j);
-          const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
+          const float dx = sep_x<PER, D>(g, (float)ci[0], aj, oi[0], pj.x);
           const float dy = dy0 - pj.y;
           float r2 = dx * dx + dy * dy;
           if constexpr (D == 3) {
@@ -934,7 +937,7 @@ __global__ __launch_bounds__(kBlock) void dump_pairs(const DomDev *__restrict__ 
     const int j = v && jr < (uint32_t)g.n ? (int)jr : i;
     const float4 pj = wpos[j];
     const uint32_t aj = wjaux[j];
-    const float dx = sep_x<PER>(g, ci[0], (int)(aj & 0xFFFu), oi[0], pj.x);
+    const float dx = sep_x<PER, D>(g, (float)ci[0], aj, oi[0], pj.x);
     const float dy = dy0 - pj.y;
     float r2 = dx * dx + dy * dy;
     if constexpr (D == 3) {

@@ -28,12 +28,20 @@ namespace mpsph {
 #define MPSPH_LANES 4
 #endif
 
+// x cell of a particle from its flags word (bits 0-11).  A 3D grid has at most 2^8 cells per
+// axis, so there the low byte holds it and converts to float in one instruction.
+template <int D>
+__device__ __forceinline__ float cell_x(uint32_t aux) {
+  return D == 3 ? (float)(aux & 0xFFu) : (float)(aux & 0xFFFu);
+}
+
 // x separation in cell units with the minimum image of a periodic box (period P cells); the
-// y and z separations come from unwrapped row offsets and need none.
+// y and z separations come from unwrapped row offsets and need none.  fcxi: the particle's x
+// cell as a float (exact); auxj: the neighbour's flags word.
 // PER: the launch may contain periodic domains (otherwise the periodic code is compiled out).
-template <bool PER>
-__device__ __forceinline__ float sep_x(const GridDev &g, int cxi, int cxj, float oxi, float oxj) {
-  float dx = (float)(cxi - cxj) + (oxi - oxj);
+template <bool PER, int D>
+__device__ __forceinline__ float sep_x(const GridDev &g, float fcxi, uint32_t auxj, float oxi, float oxj) {
+  float dx = (fcxi - cell_x<D>(auxj)) + (oxi - oxj);
   if (PER && g.geometry == 0) {
     const float P = (float)(g.gmax + 1);
     dx = dx > 0.5f * P ? dx - P : (dx < -0.5f * P ? dx + P : dx);
