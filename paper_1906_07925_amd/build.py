@@ -14,6 +14,10 @@ SOURCES = ["mpsph.hip", "sort.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # multiply-adds fused only within one expression (as written), never across statements, so
+    # that every kernel built from the same arithmetic (the pair-kernel variants, the batched and
+    # single-domain launches) rounds it the same way
+    "-ffp-contract=on",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-function",

@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
       part[0] = t1;
     }
   }
-  block_reduce_write<1>(part, ops, partials + (size_t)lb * kNumPartials);
+  block_reduce_write<1, L>(part, ops, partials + (size_t)lb * kNumPartials);   // first lanes of the groups
 }
 
 // Sum of the time-step adjoints: out[0] = T1-bar + f T2-bar (fixed order, one block).
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void loss_density(const DomDev *__restrict_
       part[1] = (double)wi;
     }
   }
-  block_reduce_write<2>(part, ops, partials + (size_t)lb * kNumPartials);
+  block_reduce_write<2, L>(part, ops, partials + (size_t)lb * kNumPartials);   // first lanes of the groups
 }
 
 // Loss, gradient pass: with ebar = 2 e / n and the interface weight cl = lambda / n,

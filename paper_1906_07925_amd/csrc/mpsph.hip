@@ -358,8 +358,6 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
   const float sigma = sigma_of(sp, (float)*stepctr, metrics[(size_t)d * 32 + kAutoT0]);
   double part[12];
   double ifcp[1] = {0.0};
-  const int ops1[1] = {0};
-  const int ops[12] = {0, 2, 0, 0, 0, 1, 2, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int s = 0; s < 12; ++s) part[s] = 0.0;
   part[5] = INFINITY;
@@ -447,7 +445,7 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       const float rhp = D == 3 ? rh2 * rh2 * rh : rh2 * rh2;  // (2 h_ij)^-(d+2)
       const float hj2 = pj.w * pj.w;
       // (P_i + P_j) (-dW/dr / r) over the common factor fscale (>= 0)
-      const float s = (diff ? opb : 1.f) * (Phi + powd<D>(hj2)) * (rhp * uu * uu * uu);
+      const float s = (diff ? opb : 1.f) * powd_add<D>(hj2, Phi) * (rhp * uu * uu * uu);
       ax = fmaf(s, dx, ax);
       ay = fmaf(s, dy, ay);
       az = fmaf(s, dz, az);
@@ -518,9 +516,22 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       ifcp[0] = nifc > 0 ? 1.0 : 0.0;
     }
   }
-  block_min_to_slots(dtc, lb, dtslots + d * kDtSlots);
-  block_reduce_write<12>(part, ops, partials + (size_t)lb * kNumPartials);
-  block_reduce_write<1>(ifcp, ops1, partials + (size_t)lb * kNumPartials + P_IFCP);
+  // block results through the row table's LDS: the first lane of each particle's group holds
+  // the partials, the interface flag and the time-step candidate
+  double red[14];
+#pragma unroll
+  for (int s = 0; s < 12; ++s) red[s] = part[s];
+  red[12] = ifcp[0];
+  red[13] = (double)dtc;
+  static_assert((kBlock / L + 1) * 14 * sizeof(double) <= row_table_rows<L>() * row_table_stride<L>() * sizeof(uint4),
+                "the block reduction fits in the row table");
+  constexpr uint32_t kMinSlots = (1u << P_ELRMIN) | (1u << 13), kMaxSlots = (1u << P_EMAX) | (1u << P_ELRMAX);
+  double *out = partials + (size_t)lb * kNumPartials;
+  block_reduce_lds<14, L>(red, kMinSlots, kMaxSlots, reinterpret_cast<double *>(rowtab), [&](int s, double x) {
+    if (s < 12) out[s] = x;
+    else if (s == 12) out[P_IFCP] = x;
+    else if (x < INFINITY) atomic_min_pos(&dtslots[d * kDtSlots + (lb & (kDtSlots - 1))], (float)x);   // one atomic per block
+  });
 }
 
 // The pass over the logical blocks b0 + [0, gridDim.x) (one dimension group).
@@ -595,7 +606,6 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
   const int li = local / L, sub = local % L;
   const int i = doms[d].off + li;
   double part[3] = {0.0, 0.0, 0.0};
-  const int ops[3] = {0, 0, 0};
   // dt1 is published in LDS and read again after the pair sum, so that no copy of it stays live
   // across the pair loop
   __shared__ float sdt1;
@@ -649,7 +659,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
           const float rh2 = rh * rh;
           const float rhp = D == 3 ? rh2 * rh2 * rh : rh2 * rh2;  // (2 h_ij)^-(d+2)
           const float hj2 = pj.w * pj.w;
-          const float s = eh * (invi + powd<D>(hj2)) * (rhp * uu * uu * uu);
+          const float s = eh * powd_add<D>(hj2, invi) * (rhp * uu * uu * uu);
           bx = fmaf(s, acci.x - accj.x, bx);
           by = fmaf(s, acci.y - accj.y, by);
           if constexpr (D == 3) bz = fmaf(s, acci.z - accj.z, bz);
@@ -824,7 +834,9 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
       part[2] = ti != 0 ? 1.0 : 0.0;
     }
   }
-  block_reduce_write<3>(part, ops, partials + (size_t)lb * kNumPartials + P_KE);
+  // block sums through the row table's LDS (first lanes of the groups)
+  double *out = partials + (size_t)lb * kNumPartials + P_KE;
+  block_reduce_lds<3, L>(part, 0u, 0u, reinterpret_cast<double *>(rowtab), [&](int s, double x) { out[s] = x; });
 }
 
 template <int D, int L, bool PER>

@@ -227,6 +227,11 @@ __device__ __forceinline__ float powd(float s) {  // s^D
   if constexpr (D == 2) return s * s;
   else return s * s * s;
 }
+template <int D>
+__device__ __forceinline__ float powd_add(float s, float c) {  // s^D + c with one rounding of the sum
+  if constexpr (D == 2) return fmaf(s, s, c);
+  else return fmaf(s, s * s, c);
+}
 
 // Spacing of the size field at a position given as cell + offset (cell units).
 template <int D>
@@ -369,15 +374,21 @@ __device__ __forceinline__ void project_feature(const GridDev &g, int type, cons
 
 // Deterministic block reduction of NP doubles (sum / min / max chosen per slot by op[]).
 // op: 0 sum, 1 min, 2 max.  Writes the block result to out[0..NP).
-template <int NP>
+// S: only lanes whose index is a multiple of S hold values (the first lane of each group of S
+// lanes), the others the identity of each slot (0 for sums and maxima of non-negative values,
+// +inf for minima).  The butterfly then starts at distance S: the skipped steps would only
+// combine a value with identities, which leaves it unchanged, so the result is the same bit
+// for bit.
+template <int NP, int S = 1>
 __device__ __forceinline__ void block_reduce_write(double (&v)[NP], const int (&op)[NP], double *out) {
+  static_assert(S >= 1 && S <= kWave && (S & (S - 1)) == 0, "S is a power of two within a wave");
   __shared__ double red[kBlock / kWave][NP];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
   for (int s = 0; s < NP; ++s) {
     double x = v[s];
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
+    for (int off = kWave / 2; off >= S; off >>= 1) {
       double y = __shfl_xor(x, off, kWave);
       x = op[s] == 0 ? x + y : (op[s] == 1 ? fmin(x, y) : fmax(x, y));
     }
@@ -392,6 +403,48 @@ __device__ __forceinline__ void block_reduce_write(double (&v)[NP], const int (&
       x = op[s] == 0 ? x + y : (op[s] == 1 ? fmin(x, y) : fmax(x, y));
     }
     out[s] = x;
+  }
+}
+
+// Block reduction through LDS of NP doubles held by the first lane of each group of S lanes (the
+// other lanes' values are not read), for the pair passes, whose row table is free by then.
+// Those lanes store their values; then the first wave combines slot s in four threads, each over
+// a quarter of the groups in group order, and joins the four in a fixed butterfly, so that the
+// result does not depend on timing.  Slots in minmask combine by min, in maxmask by max, the
+// others by sums.  emit(s, x) is called once per slot with its block result (in one thread).
+// lds: (kBlock / S + 1) * NP doubles; the function starts with a barrier, so that every wave of
+// the block is done with that memory, and the caller must not reuse it before the next barrier.
+template <int NP, int S, typename EmitF>
+__device__ __forceinline__ void block_reduce_lds(const double (&v)[NP], uint32_t minmask, uint32_t maxmask,
+                                                 double *lds, EmitF &&emit) {
+  constexpr int kGroups = kBlock / S, kStride = kGroups + 1, kPer = kGroups / 4;
+  static_assert(NP * 4 <= kWave && kGroups % 4 == 0, "one wave combines the slots, four threads each");
+  __syncthreads();
+  if (threadIdx.x % S == 0) {
+    const int k = threadIdx.x / S;
+#pragma unroll
+    for (int s = 0; s < NP; ++s) lds[s * kStride + k] = v[s];
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    const int s = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const bool live = s < NP;
+    const bool mn = live && ((minmask >> s) & 1u), mx = live && ((maxmask >> s) & 1u);
+    const double *row = lds + (live ? s : 0) * kStride + q * kPer;
+    double x = row[0];
+    if (mn) {
+      for (int k = 1; k < kPer; ++k) x = fmin(x, row[k]);
+    } else if (mx) {
+      for (int k = 1; k < kPer; ++k) x = fmax(x, row[k]);
+    } else {
+      for (int k = 1; k < kPer; ++k) x += row[k];
+    }
+#pragma unroll
+    for (int off = 1; off < 4; off <<= 1) {
+      const double y = __shfl_xor(x, off, kWave);
+      x = mn ? fmin(x, y) : (mx ? fmax(x, y) : x + y);
+    }
+    if (live && q == 0) emit(s, x);
   }
 }
 

@@ -234,20 +234,6 @@ __device__ __forceinline__ float group_min(float x) {
   return x;
 }
 
-// Minimum of the first time step: one atomic per block, spread over the kDtSlots words of the
-// block's domain.
-__device__ __forceinline__ void block_min_to_slots(float v, int lb, uint32_t *slots) {
-  __shared__ float wmin[kBlock / kWave];
-  for (int off = kWave / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0) wmin[threadIdx.x / kWave] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float m = wmin[0];
-    for (int w = 1; w < kBlock / kWave; ++w) m = fminf(m, wmin[w]);
-    if (m < INFINITY) atomic_min_pos(&slots[lb & (kDtSlots - 1)], m);
-  }
-}
-
 // First time step (Eq. 29 with v = 0): minimum over the domain's slots, every lane gets it.
 __device__ __forceinline__ float read_dt1(const uint32_t *slots) {
   float v = __uint_as_float(slots[threadIdx.x & (kDtSlots - 1)]);
