@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void adj_drift(const DomDev *__restrict__ d
     // candidate of the first time step (as in the forward pass, from the stored a)
     const float4 a4 = tp.acc[i];
     const float am2 = a4.x * a4.x + a4.y * a4.y + (D == 3 ? a4.z * a4.z : 0.f);
-    if (ti != 3 && am2 > 0.f) c1 = sp.c_acc * sqrtf(sp.kappa * pi.w * fast_rsq(am2));
+    if (ti != 3 && am2 > 0.f) c1 = sp.c_acc * fast_sqrt(sp.kappa * pi.w * fast_rsq(am2));   // as the density pass
     dtc[i] = c1;
   }
   block_min_atomic(c1, minbits);

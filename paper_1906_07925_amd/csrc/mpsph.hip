@@ -487,13 +487,14 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       float a[3] = {ax, ay, az};
       project_feature<D>(g, ti, ci, oi, a);
       const float am2 = a[0] * a[0] + a[1] * a[1] + (D == 3 ? a[2] * a[2] : 0.f);
-      const float am = sqrtf(am2);
+      // the hardware square roots below (about 1 ulp) are well inside the step's FP32 error
+      const float am = fast_sqrt(am2);
       const float ehat = sp.nu_coeff * rci * am / powd<D>(si);  // rho_t nu_coeff r_c |a|
       acc[i] = make_float4(a[0], a[1], D == 3 ? a[2] : 0.f, ehat);
       if (rho_out) rho_out[i] = rho;
       if (nn_out) nn_out[i] = sqrtf(nn2);
       if (aabs_out) aabs_out[i] = A;
-      if (ti != 3 && am2 > 0.f) dtc = sp.c_acc * sqrtf(rci * fast_rsq(am2));
+      if (ti != 3 && am2 > 0.f) dtc = sp.c_acc * fast_sqrt(rci * fast_rsq(am2));
       const bool fin = isfinite(am2) && isfinite(rho);
       if (ti == 0) {
         const double e = (double)(rho * powd<D>(si)) - 1.0;   // rho / rho_t - 1
@@ -501,7 +502,7 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
         part[1] = fabs(e);
         part[2] = 1.0;
         if (nn2 < INFINITY) {
-          const double elr = (double)sqrtf(nn2) / (double)si;
+          const double elr = (double)fast_sqrt(nn2) / (double)si;
           part[3] = elr;
           part[4] = elr * elr;
           part[5] = elr;

@@ -214,23 +214,43 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
   return total > 0u ? total - 1u : 0u;
 }
 
-// Sum / minimum across the L lanes of a group (fixed butterfly order).
+// Sum / minimum across the L lanes of a group (fixed butterfly order: lane l combines with lane
+// l ^ o for o = L/2, ..., 1).  The partner's value comes through ds_swizzle in its bit-mask mode
+// (and-mask 31, xor-mask o), which needs no per-lane address arithmetic; groups never straddle
+// the 32-lane halves the swizzle works in (L <= 32).
+template <int O>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  static_assert(O > 0 && O < 32, "swizzle xor masks stay within 32 lanes");
+  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (O << 10));
+}
 template <int L>
 __device__ __forceinline__ float group_sum(float x) {
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, L);
+  static_assert(L <= 32, "a group fits in 32 lanes");
+  if constexpr (L >= 32) x += __uint_as_float(xor_lane<16>(__float_as_uint(x)));
+  if constexpr (L >= 16) x += __uint_as_float(xor_lane<8>(__float_as_uint(x)));
+  if constexpr (L >= 8) x += __uint_as_float(xor_lane<4>(__float_as_uint(x)));
+  if constexpr (L >= 4) x += __uint_as_float(xor_lane<2>(__float_as_uint(x)));
+  if constexpr (L >= 2) x += __uint_as_float(xor_lane<1>(__float_as_uint(x)));
   return x;
 }
 template <int L>
 __device__ __forceinline__ uint32_t group_sum_u(uint32_t x) {
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, L);
+  static_assert(L <= 32, "a group fits in 32 lanes");
+  if constexpr (L >= 32) x += xor_lane<16>(x);
+  if constexpr (L >= 16) x += xor_lane<8>(x);
+  if constexpr (L >= 8) x += xor_lane<4>(x);
+  if constexpr (L >= 4) x += xor_lane<2>(x);
+  if constexpr (L >= 2) x += xor_lane<1>(x);
   return x;
 }
 template <int L>
 __device__ __forceinline__ float group_min(float x) {
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, L));
+  static_assert(L <= 32, "a group fits in 32 lanes");
+  if constexpr (L >= 32) x = fminf(x, __uint_as_float(xor_lane<16>(__float_as_uint(x))));
+  if constexpr (L >= 16) x = fminf(x, __uint_as_float(xor_lane<8>(__float_as_uint(x))));
+  if constexpr (L >= 8) x = fminf(x, __uint_as_float(xor_lane<4>(__float_as_uint(x))));
+  if constexpr (L >= 4) x = fminf(x, __uint_as_float(xor_lane<2>(__float_as_uint(x))));
+  if constexpr (L >= 2) x = fminf(x, __uint_as_float(xor_lane<1>(__float_as_uint(x))));
   return x;
 }
 
