@@ -356,12 +356,9 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
   const int i = doms[d].off + li;
   const bool active = li < doms[d].n;
   const float sigma = sigma_of(sp, (float)*stepctr, metrics[(size_t)d * 32 + kAutoT0]);
-  double part[12];
-  double ifcp[1] = {0.0};
-#pragma unroll
-  for (int s = 0; s < 12; ++s) part[s] = 0.0;
-  part[5] = INFINITY;
-  float dtc = INFINITY;
+  // the group's sums (wsum, a, nearest distance, counts), valid in lane 0 of each group
+  float gw = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, gA = 0.f, gn = INFINITY;
+  uint32_t gp = 0u, gi = 0u, gc = 0u;
   bool staged = false;
   uint32_t self_t = 0u;
   int tw = 0;
@@ -396,7 +393,6 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
     const int ti = (ai >> 12) & 3;
     const uint32_t coli = ai >> 14;
     const float hi = pi.w;
-    const float si = hi * sp.inv_tau;                 // target spacing, rho_t = s^-d
     // P = p0 / rho_t^2 = p0 tau^-2d h^2d and -dW/dr / r = 5 alpha 2^(d+2) (h_i + h_j)^-(d+2) (1 - q/2)^3
     // for the pair's h_ij: the pair sum takes h^2d and (h_i + h_j)^-(d+2), and the factors
     // common to every pair are applied once to the group's total
@@ -473,62 +469,100 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       ncand = scan_group_table<D, L, row_table_rows<L>(), PER>(
           i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g, cellbase, cstart, body);
     }
-    wsum = group_sum<L>(wsum);
-    ax = fscale * group_sum<L>(ax);
-    ay = fscale * group_sum<L>(ay);
-    if constexpr (D == 3) az = fscale * group_sum<L>(az);
-    if constexpr (DBG) A = fscale * group_sum<L>(A);
-    nn2 = group_min<L>(nn2);
-    npair = group_sum_u<L>(npair);
-    nifc = group_sum_u<L>(nifc);
-    if (sub == 0) {
-      const float ihd = D == 3 ? ihi * ihi * ihi : ihi * ihi;
-      const float rho = sp.alpha * ihd * (1.f + wsum);
-      float a[3] = {ax, ay, az};
-      project_feature<D>(g, ti, ci, oi, a);
-      const float am2 = a[0] * a[0] + a[1] * a[1] + (D == 3 ? a[2] * a[2] : 0.f);
-      // the hardware square roots below (about 1 ulp) are well inside the step's FP32 error
-      const float am = fast_sqrt(am2);
-      const float ehat = sp.nu_coeff * rci * am / powd<D>(si);  // rho_t nu_coeff r_c |a|
-      acc[i] = make_float4(a[0], a[1], D == 3 ? a[2] : 0.f, ehat);
-      if (rho_out) rho_out[i] = rho;
-      if (nn_out) nn_out[i] = sqrtf(nn2);
-      if (aabs_out) aabs_out[i] = A;
-      if (ti != 3 && am2 > 0.f) dtc = sp.c_acc * fast_sqrt(rci * fast_rsq(am2));
-      const bool fin = isfinite(am2) && isfinite(rho);
-      if (ti == 0) {
-        const double e = (double)(rho * powd<D>(si)) - 1.0;   // rho / rho_t - 1
-        part[0] = e * e;
-        part[1] = fabs(e);
-        part[2] = 1.0;
-        if (nn2 < INFINITY) {
-          const double elr = (double)fast_sqrt(nn2) / (double)si;
-          part[3] = elr;
-          part[4] = elr * elr;
-          part[5] = elr;
-          part[6] = elr;
-          part[7] = 1.0;
-        }
-      }
-      part[8] = (double)npair;
-      part[9] = (double)nifc;
-      part[10] = (double)ncand;
-      part[11] = fin ? 0.0 : 1.0;
-      ifcp[0] = nifc > 0 ? 1.0 : 0.0;
-    }
+    gw = group_sum<L>(wsum);
+    gx = fscale * group_sum<L>(ax);
+    gy = fscale * group_sum<L>(ay);
+    if constexpr (D == 3) gz = fscale * group_sum<L>(az);
+    if constexpr (DBG) gA = fscale * group_sum<L>(A);
+    gn = group_min<L>(nn2);
+    gp = group_sum_u<L>(npair);
+    gi = group_sum_u<L>(nifc);
+    gc = ncand;
   }
-  // block results through the row table's LDS: the first lane of each particle's group holds
-  // the partials, the interface flag and the time-step candidate
-  double red[14];
+  // Per-particle epilogue at one thread per particle: the groups' sums pass through the row
+  // table's LDS to the block's first P threads, so that the epilogue does not run in every wave
+  // with one lane in L busy.
+  constexpr int P = kBlock / L;                  // particles per block
+  constexpr int kEp = DBG ? 9 : 8;               // values per particle
+  float *ep = reinterpret_cast<float *>(rowtab);
+  __syncthreads();                               // every wave is done with the row table
+  if (active && sub == 0) {
+    const int p = threadIdx.x / L;
+    ep[0 * P + p] = gw;
+    ep[1 * P + p] = gx;
+    ep[2 * P + p] = gy;
+    ep[3 * P + p] = gz;
+    ep[4 * P + p] = gn;
+    ep[5 * P + p] = __uint_as_float(gp);
+    ep[6 * P + p] = __uint_as_float(gi);
+    ep[7 * P + p] = __uint_as_float(gc);
+    if constexpr (DBG) ep[8 * P + p] = gA;
+  }
+  __syncthreads();
+  double red[14];                                // the metrics' partials, interface flag, time-step candidate
 #pragma unroll
-  for (int s = 0; s < 12; ++s) red[s] = part[s];
-  red[12] = ifcp[0];
-  red[13] = (double)dtc;
-  static_assert((kBlock / L + 1) * 14 * sizeof(double) <= row_table_rows<L>() * row_table_stride<L>() * sizeof(uint4),
-                "the block reduction fits in the row table");
+  for (int s = 0; s < 14; ++s) red[s] = 0.0;
+  red[P_ELRMIN] = INFINITY;
+  red[13] = INFINITY;
+  const int lp = (lb - doms[d].blk0) * P + (int)threadIdx.x;   // the thread's particle of the domain
+  if (threadIdx.x < P && lp < doms[d].n) {
+    const int ip = doms[d].off + lp;
+    const int p = threadIdx.x;
+    int ci[3];
+    unpack_key<D>(wkey[ip] - cellbase, g, ci);
+    const float4 pi = wpos[ip];
+    const float oi[3] = {pi.x, pi.y, pi.z};
+    const int ti = (wjaux[ip] >> 12) & 3;
+    const float hi = pi.w, ihi = fast_rcp(hi), si = hi * sp.inv_tau, rci = sp.kappa * hi;
+    const float wsum = ep[0 * P + p], nn2 = ep[4 * P + p];
+    const uint32_t npair = __float_as_uint(ep[5 * P + p]), nifc = __float_as_uint(ep[6 * P + p]);
+    const uint32_t ncand = __float_as_uint(ep[7 * P + p]);
+    const float ihd = D == 3 ? ihi * ihi * ihi : ihi * ihi;
+    const float rho = sp.alpha * ihd * (1.f + wsum);
+    float a[3] = {ep[1 * P + p], ep[2 * P + p], ep[3 * P + p]};
+    project_feature<D>(g, ti, ci, oi, a);
+    const float am2 = a[0] * a[0] + a[1] * a[1] + (D == 3 ? a[2] * a[2] : 0.f);
+    // the hardware square roots below (about 1 ulp) are well inside the step's FP32 error
+    const float am = fast_sqrt(am2);
+    const float ehat = sp.nu_coeff * rci * am / powd<D>(si);  // rho_t nu_coeff r_c |a|
+    acc[ip] = make_float4(a[0], a[1], D == 3 ? a[2] : 0.f, ehat);
+    if (rho_out) rho_out[ip] = rho;
+    if (nn_out) nn_out[ip] = sqrtf(nn2);
+    if constexpr (DBG) {
+      if (aabs_out) aabs_out[ip] = ep[8 * P + p];
+    }
+    if (ti != 3 && am2 > 0.f) red[13] = (double)(sp.c_acc * fast_sqrt(rci * fast_rsq(am2)));
+    const bool fin = isfinite(am2) && isfinite(rho);
+    if (ti == 0) {
+      const double e = (double)(rho * powd<D>(si)) - 1.0;   // rho / rho_t - 1
+      red[P_E2] = e * e;
+      red[P_EMAX] = fabs(e);
+      red[P_NNORM] = 1.0;
+      if (nn2 < INFINITY) {
+        const double elr = (double)fast_sqrt(nn2) / (double)si;
+        red[P_ELR] = elr;
+        red[P_ELR2] = elr * elr;
+        red[P_ELRMIN] = elr;
+        red[P_ELRMAX] = elr;
+        red[P_NELR] = 1.0;
+      }
+    }
+    red[P_PAIRS] = (double)npair;
+    red[P_IFC] = (double)nifc;
+    red[P_CAND] = (double)ncand;
+    red[P_NONFIN1] = fin ? 0.0 : 1.0;
+    red[12] = nifc > 0 ? 1.0 : 0.0;
+  }
+  // block results through LDS (after the epilogue's values when both fit in the row table)
+  constexpr size_t kEpBytes = (size_t)kEp * P * sizeof(float), kRedBytes = (size_t)(P + 1) * 14 * sizeof(double);
+  constexpr size_t kTableBytes = (size_t)row_table_rows<L>() * row_table_stride<L>() * sizeof(uint4);
+  constexpr bool kApart = kEpBytes + kRedBytes <= kTableBytes;
+  static_assert(kRedBytes <= kTableBytes && kEpBytes <= kTableBytes, "the epilogue and the reduction fit in the row table");
+  double *rb = reinterpret_cast<double *>(reinterpret_cast<char *>(rowtab) + (kApart ? (kEpBytes + 15) / 16 * 16 : 0));
   constexpr uint32_t kMinSlots = (1u << P_ELRMIN) | (1u << 13), kMaxSlots = (1u << P_EMAX) | (1u << P_ELRMAX);
   double *out = partials + (size_t)lb * kNumPartials;
-  block_reduce_lds<14, L>(red, kMinSlots, kMaxSlots, reinterpret_cast<double *>(rowtab), [&](int s, double x) {
+  block_reduce_lds<14, P, !kApart>(red, threadIdx.x < P ? (int)threadIdx.x : -1, kMinSlots, kMaxSlots, rb,
+                                   [&](int s, double x) {
     if (s < 12) out[s] = x;
     else if (s == 12) out[P_IFCP] = x;
     else if (x < INFINITY) atomic_min_pos(&dtslots[d * kDtSlots + (lb & (kDtSlots - 1))], (float)x);   // one atomic per block
@@ -837,7 +871,8 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
   }
   // block sums through the row table's LDS (first lanes of the groups)
   double *out = partials + (size_t)lb * kNumPartials + P_KE;
-  block_reduce_lds<3, L>(part, 0u, 0u, reinterpret_cast<double *>(rowtab), [&](int s, double x) { out[s] = x; });
+  block_reduce_lds<3, kBlock / L, true>(part, threadIdx.x % L == 0 ? (int)(threadIdx.x / L) : -1, 0u, 0u,
+                                        reinterpret_cast<double *>(rowtab), [&](int s, double x) { out[s] = x; });
 }
 
 template <int D, int L, bool PER>

@@ -406,22 +406,22 @@ __device__ __forceinline__ void block_reduce_write(double (&v)[NP], const int (&
   }
 }
 
-// Block reduction through LDS of NP doubles held by the first lane of each group of S lanes (the
-// other lanes' values are not read), for the pair passes, whose row table is free by then.
-// Those lanes store their values; then the first wave combines slot s in four threads, each over
-// a quarter of the groups in group order, and joins the four in a fixed butterfly, so that the
-// result does not depend on timing.  Slots in minmask combine by min, in maxmask by max, the
-// others by sums.  emit(s, x) is called once per slot with its block result (in one thread).
-// lds: (kBlock / S + 1) * NP doubles; the function starts with a barrier, so that every wave of
-// the block is done with that memory, and the caller must not reuse it before the next barrier.
-template <int NP, int S, typename EmitF>
-__device__ __forceinline__ void block_reduce_lds(const double (&v)[NP], uint32_t minmask, uint32_t maxmask,
+// Block reduction through LDS of NP doubles from G writer slots, for the pair passes (whose row
+// table is free by then): the thread with slot k in [0, G) stores its values (k < 0: the thread
+// holds none); then the first wave combines slot s in four threads, each over a quarter of the
+// writer slots in slot order, and joins the four in a fixed butterfly, so that the result does
+// not depend on timing.  Slots in minmask combine by min, in maxmask by max, the others by sums.
+// emit(s, x) is called once per slot with its block result (in one thread).
+// lds: (G + 1) * NP doubles of LDS.  SYNC: start with a barrier, for memory that other waves
+// may still read; without it the caller guarantees that nobody reads that memory any more.  The
+// caller must not reuse it before the next barrier.
+template <int NP, int G, bool SYNC, typename EmitF>
+__device__ __forceinline__ void block_reduce_lds(const double (&v)[NP], int k, uint32_t minmask, uint32_t maxmask,
                                                  double *lds, EmitF &&emit) {
-  constexpr int kGroups = kBlock / S, kStride = kGroups + 1, kPer = kGroups / 4;
-  static_assert(NP * 4 <= kWave && kGroups % 4 == 0, "one wave combines the slots, four threads each");
-  __syncthreads();
-  if (threadIdx.x % S == 0) {
-    const int k = threadIdx.x / S;
+  constexpr int kStride = G + 1, kPer = G / 4;
+  static_assert(NP * 4 <= kWave && G % 4 == 0, "one wave combines the slots, four threads each");
+  if constexpr (SYNC) __syncthreads();
+  if (k >= 0) {
 #pragma unroll
     for (int s = 0; s < NP; ++s) lds[s * kStride + k] = v[s];
   }
@@ -433,11 +433,11 @@ __device__ __forceinline__ void block_reduce_lds(const double (&v)[NP], uint32_t
     const double *row = lds + (live ? s : 0) * kStride + q * kPer;
     double x = row[0];
     if (mn) {
-      for (int k = 1; k < kPer; ++k) x = fmin(x, row[k]);
+      for (int t = 1; t < kPer; ++t) x = fmin(x, row[t]);
     } else if (mx) {
-      for (int k = 1; k < kPer; ++k) x = fmax(x, row[k]);
+      for (int t = 1; t < kPer; ++t) x = fmax(x, row[t]);
     } else {
-      for (int k = 1; k < kPer; ++k) x += row[k];
+      for (int t = 1; t < kPer; ++t) x += row[t];
     }
 #pragma unroll
     for (int off = 1; off < 4; off <<= 1) {
