@@ -640,7 +640,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
   const int local = (lb - doms[d].blk0) * kBlock + threadIdx.x;
   const int li = local / L, sub = local % L;
   const int i = doms[d].off + li;
-  double part[3] = {0.0, 0.0, 0.0};
+  float gbx = 0.f, gby = 0.f, gbz = 0.f;   // the group's pair sums, valid in lane 0 of each group
   // dt1 is published in LDS and read again after the pair sum, so that no copy of it stays live
   // across the pair loop
   __shared__ float sdt1;
@@ -703,19 +703,34 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
                                                           ci, oi, rs, g, cellbase, cstart, body);
       }
     }
-    const float hdt = 0.5f * sdt1;
-    const float dt2 = sdt1 * sp.dt2_factor;
-    // the factors left out of the pair sum: 2 of the harmonic mean, -5 alpha 2^(d+2), tau^-2d and
-    // (dt1/2)^2
-    const float vscale = (-2.f * 5.f * sp.alpha * (D == 3 ? 32.f : 16.f)) * powd<D>(sp.inv_tau * sp.inv_tau) * hdt * hdt;
-    bx = vscale * group_sum<L>(bx);
-    by = vscale * group_sum<L>(by);
-    if constexpr (D == 3) bz = vscale * group_sum<L>(bz);
-    if (sub == 0) {
-      // the particle's own data is read again rather than kept in registers across the pair
-      // loop, through an index the compiler cannot tie to i, so that neither values nor
-      // addresses stay live across it (this keeps the pass free of register spills)
-      const int io = __shfl(i, (int)(threadIdx.x & (kWave - 1)));
+    gbx = group_sum<L>(bx);
+    gby = group_sum<L>(by);
+    if constexpr (D == 3) gbz = group_sum<L>(bz);
+  }
+  // Per-particle epilogue at one thread per particle: the groups' sums pass through the row
+  // table's LDS to the block's first P threads, so that the epilogue does not run in every wave
+  // with one lane in L busy.
+  constexpr int P = kBlock / L;                  // particles per block
+  float *ep = reinterpret_cast<float *>(rowtab);
+  __syncthreads();                               // every wave is done with the row table
+  if (li < doms[d].n && sub == 0) {
+    const int p = threadIdx.x / L;
+    ep[0 * P + p] = gbx;
+    ep[1 * P + p] = gby;
+    ep[2 * P + p] = gbz;
+  }
+  __syncthreads();
+  double part[3] = {0.0, 0.0, 0.0};
+  const int lp = (lb - doms[d].blk0) * P + (int)threadIdx.x;   // the thread's particle of the domain
+  if (threadIdx.x < P && lp < doms[d].n) {
+    {
+      const int io = doms[d].off + lp;
+      const int p = threadIdx.x;
+      const float hdt = 0.5f * sdt1;
+      const float dt2 = sdt1 * sp.dt2_factor;
+      // the factors left out of the pair sum: 2 of the harmonic mean, -5 alpha 2^(d+2), tau^-2d and
+      // (dt1/2)^2
+      const float vscale = (-2.f * 5.f * sp.alpha * (D == 3 ? 32.f : 16.f)) * powd<D>(sp.inv_tau * sp.inv_tau) * hdt * hdt;
       int ci[3];
       unpack_key<D>(wkey[io] - cellbase, g, ci);
       const float4 pe = wpos[io];
@@ -724,7 +739,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
       int ti = (ai >> 12) & 3;
       const float4 acce = acc[io];
       const float vix = hdt * acce.x, viy = hdt * acce.y, viz = hdt * acce.z;
-      float b[3] = {bx, by, bz};
+      float b[3] = {vscale * ep[0 * P + p], vscale * ep[1 * P + p], D == 3 ? vscale * ep[2 * P + p] : 0.f};
       project_feature<D>(g, ti, ci, oi, b);
       float v[3] = {vix + 0.5f * b[0] * dt2, viy + 0.5f * b[1] * dt2, viz + 0.5f * b[2] * dt2};
       if (ti == 3) v[0] = v[1] = v[2] = 0.f;
@@ -869,10 +884,14 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
       part[2] = ti != 0 ? 1.0 : 0.0;
     }
   }
-  // block sums through the row table's LDS (first lanes of the groups)
+  // block sums through LDS, after the epilogue's values
+  constexpr size_t kEpBytes = (size_t)3 * P * sizeof(float), kRedBytes = (size_t)(P + 1) * 3 * sizeof(double);
+  static_assert((kEpBytes + 15) / 16 * 16 + kRedBytes <= (size_t)row_table_rows<L>() * row_table_stride<L>() * sizeof(uint4),
+                "the epilogue and the reduction fit in the row table");
+  double *rb = reinterpret_cast<double *>(reinterpret_cast<char *>(rowtab) + (kEpBytes + 15) / 16 * 16);
   double *out = partials + (size_t)lb * kNumPartials + P_KE;
-  block_reduce_lds<3, kBlock / L, true>(part, threadIdx.x % L == 0 ? (int)(threadIdx.x / L) : -1, 0u, 0u,
-                                        reinterpret_cast<double *>(rowtab), [&](int s, double x) { out[s] = x; });
+  block_reduce_lds<3, P, false>(part, threadIdx.x < P ? (int)threadIdx.x : -1, 0u, 0u, rb,
+                                [&](int s, double x) { out[s] = x; });
 }
 
 template <int D, int L, bool PER>
