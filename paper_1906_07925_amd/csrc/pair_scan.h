@@ -49,6 +49,26 @@ __device__ __forceinline__ float sep_x(const GridDev &g, float fcxi, uint32_t au
   return dx;
 }
 
+// Value of lane l - o (o < 16) within the lane's row of 16 lanes, through a DPP row shift (no
+// LDS round trip and no lane arithmetic); lanes l < o of the row get 0.  Used for prefix sums
+// inside groups of at most 16 lanes, where the lanes that would read across the group's start
+// discard the value.
+__device__ __forceinline__ uint32_t lane_up(uint32_t x, int o) {
+  switch (o) {   // the shift is an immediate of the instruction
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);
+    case 4: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);
+    default: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);
+  }
+}
+// The value of the group's last lane (L lanes, L <= 16), in every lane of the group, through
+// ds_swizzle in its bit-mask mode: source lane = (lane & ~(L - 1)) | (L - 1) within 32 lanes.
+template <int L>
+__device__ __forceinline__ uint32_t group_last(uint32_t x) {
+  static_assert(L >= 2 && L <= 16 && (L & (L - 1)) == 0, "groups of 2 to 16 lanes");
+  return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (0x1F & ~(L - 1)) | ((L - 1) << 5));
+}
+
 // Rows per chunk of the LDS row table at 4 lanes per particle (scaled with the lanes, so that
 // the table of a 256-thread block stays below 19 KB and 8 blocks fit a CU's LDS).
 #ifndef MPSPH_ROW_TABLE
@@ -182,7 +202,7 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
       uint32_t incl = len, nz = len > 0u ? 1u : 0u;
 #pragma unroll
       for (int o = 1; o < L; o <<= 1) {
-        const uint32_t v = __shfl_up(incl, o, L), w = __shfl_up(nz, o, L);
+        const uint32_t v = lane_up(incl, o), w = lane_up(nz, o);
         if (sub >= o) {
           incl += v;
           nz += w;
@@ -194,8 +214,8 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
         tab[(ne + nz - 1u) * (uint32_t)stride] =
             make_uint4(remap(cy, cz, a) - (end - len), end, __float_as_uint(dyo), __float_as_uint(dzo));
       }
-      run += __shfl(incl, L - 1, L);
-      ne += __shfl(nz, L - 1, L);
+      run += group_last<L>(incl);
+      ne += group_last<L>(nz);
       q0 += L;
     }
     // end marker (ne < C): base -run, so that slot t past the end maps to index t - run
