@@ -184,6 +184,31 @@ def test_small_and_ragged_sizes(torch_cuda, n):
     PU.check_single_step(spec, s0, x32, col, typ)
 
 
+@pytest.mark.parametrize("dim,n", [(2, 1), (2, 3), (3, 1), (3, 2), (3, 7)])
+def test_fewer_particles_than_lanes(torch_cuda, dim, n):
+    """Fewer particles than the 8 lanes of a group: slots past a chunk's end map to indices up to
+    7, beyond the arrays, and must load nothing (bounds-checked loads, NaN separations) and add
+    nothing.  Single step within the oracle's bounds at 8 lanes, and the pair dump (2 lanes)
+    lists the oracle's ordered pairs."""
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    rng = np.random.Generator(np.random.PCG64(100 * dim + n))
+    spec = dict((W.unit_square if dim == 2 else W.unit_cube)(n), n=n)
+    x32 = rng.uniform(0.35, 0.65, size=(n, dim)).astype(np.float32)   # close enough to interact
+    col = rng.integers(0, 2, size=n).astype(np.int32)
+    typ = np.zeros(n, np.int32)
+    s0 = 0.2
+    PU.check_single_step(spec, s0, x32, col, typ, lanes=8)
+    R = M.Relaxer(spec, n=n, s0=s0)
+    R.load(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    R.step(1)
+    gi, gj = R.pairs()
+    R.close()
+    got = sorted(zip(gi.cpu().numpy().tolist(), gj.cpu().numpy().tolist()))
+    pi, pj = O.pairs(O.OracleParams(spec, s0=s0), x32.astype(np.float64))
+    assert got == sorted(zip(pi.tolist(), pj.tolist()))
+
+
 def test_feature_particles_after_many_steps(torch_cuda):
     """Walls: particles that leave the box are clamped and retagged; a run of 30 steps on the
     GPU and on the oracle from the same input ends with the same types (one-way retagging) and
