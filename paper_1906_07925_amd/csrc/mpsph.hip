@@ -184,7 +184,8 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
 // P = p0 / rho_t^2, h_ij = (h_i + h_j)/2, over j with r_ij < kappa h_ij that particle i feels.
 // Writes acc = (a after the force mapping of Eq. 30-31, e_i) with e_i = rho_t nu_coeff r_c |a_i|,
 // the viscosity of Eq. 21-22 per unit of dt1/2, and the first time-step candidate (Eq. 29).
-// L lanes per particle (group); lane 0 of the group writes the particle's results.
+// L lanes per particle (group) sum its pairs; the block's first 256/L threads then finish one
+// particle each (the epilogue) and the first wave combines the block's metric partials.
 // LDS-staged density pass (3D; pair-kernel variant MPSPH_PAIRS_TILE): the targets of a block share one
 // copy of their neighbours in LDS.  The union of the targets' candidate rows (y, z) and, per row,
 // of their x-runs is formed with LDS atomics; every union row's particles (offsets and h, flags)
