@@ -124,6 +124,7 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
   // compare of the divergent inner loop, and such a build listed some candidates twice (the same
   // build with the chunk bound passed through a width-1 shuffle listed each once)
   static_assert(L >= 2, "at least two lanes per particle");
+  static_assert(L <= 16, "a group's prefix sums use row shifts within 16 lanes");
   rs = fminf(fmaxf(rs, 0.f), 2.f * (float)g.gmax + 2.f);
   const float rs2 = rs * rs;
   const bool per = PER && g.geometry == 0;
