@@ -424,7 +424,7 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       // only for the kernel sums
       const uint32_t colj = aj >> 14;
       const bool diff = colj != coli;
-      const bool feel = inter && (int)((aj >> 12) & 3) >= ti;
+      const bool feel = inter && type_at_least(aj, ti);
       nifc += (inter && diff) ? 1u : 0u;
       npair += feel ? 1u : 0u;
       if (inter && r2 < nn2) nn2 = r2;
@@ -685,7 +685,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
           }
           const float hs = hi + pj.w;   // 2 h_ij
           const float hij = kh * hs;
-          if (!(v && r2 > 1e-30f && r2 < hij * hij && (int)((aj >> 12) & 3) >= ti)) return;
+          if (!(v && r2 > 1e-30f && r2 < hij * hij && type_at_least(aj, ti))) return;
           const float r = fast_sqrt(r2);
           // e_i e_j / (e_i + e_j), half the harmonic mean; e_i > 0 here and e_j >= 0, so the sum
           // is positive

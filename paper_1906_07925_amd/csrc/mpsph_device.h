@@ -222,6 +222,10 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }  // x >= 0; sqrt(0) = 0
 
+// Whether the particle of flags word aux (type in bits 12-13) has a type of at least t: the type
+// field is compared in place, one and plus one compare.
+__device__ __forceinline__ bool type_at_least(uint32_t aux, int t) { return (aux & 0x3000u) >= ((uint32_t)t << 12); }
+
 template <int D>
 __device__ __forceinline__ float powd(float s) {  // s^D
   if constexpr (D == 2) return s * s;
