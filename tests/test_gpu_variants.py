@@ -38,7 +38,7 @@ def _run(torch, specs, ns, x, col, typ, steps, variant, k=-1, lanes=None):
     return xs.cpu().numpy(), ts.cpu().numpy(), m
 
 
-@pytest.mark.parametrize("lanes", [4, 8])
+@pytest.mark.parametrize("lanes", [2, 4, 8])
 def test_variants_equal_default_on_graded_cube(torch_cuda, lanes):
     """The graded cube (3D; coarse blocks overflow the staged copy and read through the caches,
     fine ones are staged): every variant ends bit-identical to the default after 5 steps."""
