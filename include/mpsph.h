@@ -256,7 +256,7 @@ MPSPH_API int mpsph_batch_create(int32_t ndom, const mpsph_params *params, const
 MPSPH_API int mpsph_domain_count(mpsph_ctx *ctx, int32_t *ndom, int64_t *n_total);
 
 /* Load the particle set: d_pos (n x dim float32, domain units), d_colour (n int32 in
- * [0, 2^18)), d_type (n int32 in [0,3], or NULL for all normal).  Resets the step counter.
+ * [0, 2^16)), d_type (n int32 in [0,3], or NULL for all normal).  Resets the step counter.
  * Every position must lie inside the bounding box [lo, hi] (MPSPH_E_INVALID otherwise). */
 MPSPH_API int mpsph_load(mpsph_ctx *ctx, const float *d_pos, const int32_t *d_colour, const int32_t *d_type);
 

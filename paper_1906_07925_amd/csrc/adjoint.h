@@ -48,7 +48,7 @@ constexpr int kMaxRbf = 64;
 struct TapeView {
   const uint32_t *wkey;
   const float4 *wpos;    // offsets, h
-  const uint32_t *wjaux; // cx | type << 12 | colour << 14
+  const uint32_t *wjaux; // colour | cx << 16 | type << 30
   const uint32_t *cstart;
   const uint32_t *perm;  // state index of each sorted index
   const float4 *acc;     // a (after the force mapping), e = rho_t nu_coeff r_c |a|
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void adj_drift(const DomDev *__restrict__ d
     unpack_key<D>(tp.wkey[i], g, ci);
     const float4 pi = tp.wpos[i];
     const float oi[3] = {pi.x, pi.y, pi.z};
-    const int ti = (tp.wjaux[i] >> 12) & 3;
+    const int ti = aux_type(tp.wjaux[i]);
     const float4 xb4 = xbar_next[i], v4 = tp.v[i], at4 = tp.at[i];
     const float xb[3] = {xb4.x, xb4.y, xb4.z}, vv[3] = {v4.x, v4.y, v4.z}, av[3] = {at4.x, at4.y, at4.z};
     float xd[3] = {0.f, 0.f, 0.f}, db[3] = {0.f, 0.f, 0.f}, ab[3] = {0.f, 0.f, 0.f};
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
     unpack_key<D>(tp.wkey[i], g, ci);
     const float4 pi = tp.wpos[i];
     const float oi[3] = {pi.x, pi.y, pi.z};
-    const int ti = (tp.wjaux[i] >> 12) & 3;
+    const int ti = aux_type(tp.wjaux[i]);
     const float hi = pi.w, si = hi * sp.inv_tau;
     const float s2di = pow2d<D>(si);
     const float4 *gd = gdat[threadIdx.x / L];
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
         }
         const float hij = kh * (hi + pj.w);
         if (!(v && r2 > 1e-30f && r2 < hij * hij)) return;
-        const int tj = (aj >> 12) & 3;
+        const int tj = aux_type(aj);
         const float ej = hdt * aj4.w;
         if (!(ej > 0.f)) return;  // eta_j = 0: the pair's K and every derivative of it vanish
         const float mkj = tj >= ti ? 1.f : 0.f, mjk = ti >= tj ? 1.f : 0.f;
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
       // neither values nor addresses stay live across the pair loop
       const int io = __shfl(i, (int)(threadIdx.x & (kWave - 1)));
       const float si = tp.wpos[io].w * sp.inv_tau;
-      const int ti = (tp.wjaux[io] >> 12) & 3;
+      const int ti = aux_type(tp.wjaux[io]);
       const float4 ai = tp.acc[io];
       const float vti[3] = {hdt * ai.x, hdt * ai.y, hdt * ai.z};
       const float4 vd = vtb[io];
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void adj_fbar(const DomDev *__restrict__ do
   unpack_key<D>(tp.wkey[i], g, ci);
   const float4 pi = tp.wpos[i];
   const float oi[3] = {pi.x, pi.y, pi.z};
-  const int ti = (tp.wjaux[i] >> 12) & 3;
+  const int ti = aux_type(tp.wjaux[i]);
   const float4 ab4 = abar[i];
   float f[3] = {ab4.x, ab4.y, ab4.z};
   if ((uint32_t)i == *argmin) {
@@ -406,8 +406,7 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
   const float4 pi = tp.wpos[i];
   const float oi[3] = {pi.x, pi.y, pi.z};
   const uint32_t ai = tp.wjaux[i];
-  const int ti = (ai >> 12) & 3;
-  const uint32_t coli = ai >> 14;
+  const int ti = aux_type(ai);
   const float hi = pi.w, si = hi * sp.inv_tau;
   const float Pi = sp.p0c * pow2d<D>(si);
   const float dPi = (2.f * (float)D) * Pi / si;
@@ -434,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
     }
     const float hij = kh * (hi + pj.w);
     if (!(v && r2 > 1e-30f && r2 < hij * hij)) return;
-    const int tj = (aj >> 12) & 3;
+    const int tj = aux_type(aj);
     const float mkj = tj >= ti ? 1.f : 0.f, mjk = ti >= tj ? 1.f : 0.f;
     const float wf[3] = {mkj * fi.x - mjk * fj.x, mkj * fi.y - mjk * fj.y, mkj * fi.z - mjk * fj.z};
     const float rinv = fast_rsq(r2);
@@ -446,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
     const float gg = a5 * p2 * u * u * u;
     const float dgr = -a75 * p3 * u * u;
     const float dgh = a5 * p3 * u * u * (1.5f * q - (float)(D + 2) * u);
-    const float B = (aj >> 14) != coli ? opb : 1.f;
+    const float B = colour_differs(aj, ai) ? opb : 1.f;
     const float sj = pj.w * sp.inv_tau;
     const float Psum = Pi + sp.p0c * pow2d<D>(sj);
     const float w = B * Psum * gg;
@@ -557,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void loss_density(const DomDev *__restrict_
     unpack_key<D>(wkey[i], g, ci);
     const float4 pi = wpos[i];
     const float oi[3] = {pi.x, pi.y, pi.z};
-    const uint32_t coli = wjaux[i] >> 14;
+    const uint32_t ai = wjaux[i];
     const float hi = pi.w, ihi = fast_rcp(hi);
     const float rci = sp.kappa * hi, rci2 = rci * rci;
     const float rs = fminf(sp.search_fac * hi, sp.kappa * 0.5f * (hi + sp.hmax)) * 1.0001f;
@@ -583,7 +582,7 @@ __global__ __launch_bounds__(kBlock) void loss_density(const DomDev *__restrict_
         ws += u * u * u * u * fmaf(2.f, q, 1.f);
       }
       const float hij = kh * (hi + pj.w);
-      if ((aj >> 14) != coli && r2 < hij * hij) {
+      if (colour_differs(aj, ai) && r2 < hij * hij) {
         const float q = r * sp.kappa * fast_rcp(hij), u = fmaf(-0.5f, q, 1.f);
         wi += u * u * u * u * fmaf(2.f, q, 1.f);
       }
@@ -623,7 +622,7 @@ __global__ __launch_bounds__(kBlock) void loss_grad(const DomDev *__restrict__ d
   unpack_key<D>(wkey[i], g, ci);
   const float4 pi = wpos[i];
   const float oi[3] = {pi.x, pi.y, pi.z};
-  const uint32_t coli = wjaux[i] >> 14;
+  const uint32_t ai = wjaux[i];
   const float hi = pi.w, ihi = fast_rcp(hi);
   const float A = sp.alpha * (D == 3 ? sp.inv_tau * sp.inv_tau * sp.inv_tau : sp.inv_tau * sp.inv_tau);
   const float ebi = ebar_scale * e[i];
@@ -659,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void loss_grad(const DomDev *__restrict__ d
       cx += ebar_scale * e[j] * A * u * u * u * ihj * ihj;
     }
     const float hij = kh * (hi + pj.w);
-    if ((aj >> 14) != coli && r2 < hij * hij) {
+    if (colour_differs(aj, ai) && r2 < hij * hij) {
       const float ih = sp.kappa * fast_rcp(hij), q = r * ih, u = fmaf(-0.5f, q, 1.f), u3 = u * u * u;
       cx += cl * u3 * ih * ih;
       sb = fmaf(cl * 2.5f * q * q * u3 * ih, sp.tau, sb);

@@ -10,7 +10,7 @@
 //   state  (order of the previous step's sort): key u32 (domain cell base + packed cell), off
 //          float4 (cell offsets), ct u32 (type | colour << 2), id u32 (index at load)
 //   work   (order of this step's sort): key u32, pos float4 (offsets, h), jaux u32
-//          (cx | type << 12 | colour << 14), id u32
+//          (colour | cx << 16 | type << 30), id u32
 //   per step: acc float4 (a, e = rho_t nu_coeff r_c |a|), cell table u32[ncells+1]; rho, sum|term|,
 //             a~, v, dr, nearest distance only in debug mode
 // Positions are an integer cell coordinate per axis (packed in the key: x fastest and at
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void load_kernel(const DomDev *__restrict__
   }
   const int col = colour[u];
   const int t = type ? type[u] : 0;
-  if (col < 0 || col >= (1 << 18) || t < 0 || t > 3) ok = false;
+  if (col < 0 || col >= (1 << 16) || t < 0 || t > 3) ok = false;
   if (!ok) atomicOr(bad, 1);
   key[i] = dd.cellbase + pack_key<D>(c, o, dd.g);
   off[i] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void reorder_field(
   const float spc = field_spacing<D>(dd.f, c, o);
   wkey[i] = key;
   wpos[i] = make_float4(o4.x, o4.y, o4.z, dd.sp.tau * spc);
-  wjaux[i] = (uint32_t)c[0] | ((ct & 3u) << 12) | ((ct >> 2) << 14);
+  wjaux[i] = pack_aux((uint32_t)c[0], ct & 3u, ct >> 2);
   wid[i] = sid[s];
 }
 
@@ -337,7 +337,9 @@ __device__ bool stage_tile(TileLds *T, bool active, int sub, const int *ci, cons
 
 // One logical block lb of the pass (blocks of a domain are consecutive; doms is the table the
 // block numbers refer to); rowtab is the block's LDS row table, tile the LDS copy of the
-// neighbours of the TILE variant (unused otherwise).
+// neighbours of the TILE variant (unused otherwise).  With PIPE the scan issues the neighbour
+// loads of a lane's next slot before the arithmetic of the current one (same arithmetic, same
+// order: the results do not depend on it).
 #define MPSPH_PASS1_PARAMS                                                                                   \
   const DomDev *__restrict__ doms, int ndom, const int64_t *__restrict__ stepctr,                            \
       const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos, const uint32_t *__restrict__ wjaux, \
@@ -346,7 +348,7 @@ __device__ bool stage_tile(TileLds *T, bool active, int sub, const int *ci, cons
       const double *__restrict__ metrics, double *__restrict__ partials
 #define MPSPH_PASS1_ARGS \
   doms, ndom, stepctr, wkey, wpos, wjaux, cstart, acc, rho_out, nn_out, aabs_out, dtslots, metrics, partials
-template <int D, int L, bool PER, bool DBG, bool TILE = false>
+template <int D, int L, bool PER, bool DBG, bool TILE, bool PIPE>
 __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileLds *tile, MPSPH_PASS1_PARAMS) {
   const int d = domain_of_block(doms, ndom, lb);
   const GridDev g = doms[d].g;
@@ -391,8 +393,7 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
     const float4 pi = wpos[i];
     const float oi[3] = {pi.x, pi.y, pi.z};
     const uint32_t ai = wjaux[i];
-    const int ti = (ai >> 12) & 3;
-    const uint32_t coli = ai >> 14;
+    const int ti = aux_type(ai);
     const float hi = pi.w;
     // P = p0 / rho_t^2 = p0 tau^-2d h^2d and -dW/dr / r = 5 alpha 2^(d+2) (h_i + h_j)^-(d+2) (1 - q/2)^3
     // for the pair's h_ij: the pair sum takes h^2d and (h_i + h_j)^-(d+2), and the factors
@@ -422,11 +423,14 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       const bool inter = v && r2 < hij * hij;
       // the counts and the nearest distance in every lane, so that the branch below is taken
       // only for the kernel sums
-      const uint32_t colj = aj >> 14;
-      const bool diff = colj != coli;
+      const bool diff = colour_differs(aj, ai);
       const bool feel = inter && type_at_least(aj, ti);
       nifc += (inter && diff) ? 1u : 0u;
       npair += feel ? 1u : 0u;
+      // an empty statement that reads and writes both counts keeps their additions here, beside
+      // the compares, where each becomes one add-with-carry of the compare's lane mask instead
+      // of a select and an add after the branch
+      asm volatile("" : "+v"(npair), "+v"(nifc));
       if (inter && r2 < nn2) nn2 = r2;
       // coincident particles (two particles clamped into one corner): r = 0, no direction
       const bool apart = r2 > 1e-30f;
@@ -448,9 +452,12 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       az = fmaf(s, dz, az);
       if constexpr (DBG) A = fmaf(s, r, A);        // sum of |pair terms| (debug export only)
     };
-    const auto body = [&](uint32_t j, float dy0, float dz0, bool v) {
-      pair(buf_f4(rpos, j), buf_u32(raux, j), dy0, dz0, v);
+    struct Nb {
+      float4 p;
+      uint32_t a;
     };
+    const auto body = pair_body<PIPE>([&](uint32_t j) { return Nb{buf_f4(rpos, j), buf_u32(raux, j)}; },
+                                      [&](const Nb &nb, float dy0, float dz0, bool v) { pair(nb.p, nb.a, dy0, dz0, v); });
     uint32_t ncand;
     if constexpr (TILE) {
       if (staged) {
@@ -513,7 +520,7 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
     unpack_key<D>(wkey[ip] - cellbase, g, ci);
     const float4 pi = wpos[ip];
     const float oi[3] = {pi.x, pi.y, pi.z};
-    const int ti = (wjaux[ip] >> 12) & 3;
+    const int ti = aux_type(wjaux[ip]);
     const float hi = pi.w, ihi = fast_rcp(hi), si = hi * sp.inv_tau, rci = sp.kappa * hi;
     const float wsum = ep[0 * P + p], nn2 = ep[4 * P + p];
     const uint32_t npair = __float_as_uint(ep[5 * P + p]), nifc = __float_as_uint(ep[6 * P + p]);
@@ -574,7 +581,7 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
 template <int D, int L, bool PER, bool DBG>
 __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_force(int b0, MPSPH_PASS1_PARAMS) {
   __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
-  density_force_block<D, L, PER, DBG>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, nullptr, MPSPH_PASS1_ARGS);
+  density_force_block<D, L, PER, DBG, false, !PER>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, nullptr, MPSPH_PASS1_ARGS);
 }
 
 // The staged copy limits a CU to 4 blocks (4 waves per SIMD), which the register budget follows.
@@ -583,7 +590,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     int b0, MPSPH_PASS1_PARAMS) {
   __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
   __shared__ TileLds tile;
-  density_force_block<3, L, false, DBG, true>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, &tile, MPSPH_PASS1_ARGS);
+  density_force_block<3, L, false, DBG, true, false>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, &tile, MPSPH_PASS1_ARGS);
 }
 
 
@@ -632,7 +639,8 @@ __device__ __forceinline__ int type_from_faces(int nf, int d) {
       float4 *__restrict__ v_out, float4 *__restrict__ dr_out, double *__restrict__ partials
 #define MPSPH_PASS2_ARGS \
   doms, ndom, wkey, wpos, wjaux, wid, cstart, acc, dtslots, skey, soff, sct, sid, at_out, v_out, dr_out, partials
-template <int D, int L, bool PER>
+// One logical block lb of the pass; PIPE as for density_force_block.
+template <int D, int L, bool PER, bool PIPE>
 __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, MPSPH_PASS2_PARAMS) {
   const int d = domain_of_block(doms, ndom, lb);
   const GridDev g = doms[d].g;
@@ -656,7 +664,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
       unpack_key<D>(wkey[i] - cellbase, g, ci);
       const float4 pi = wpos[i];
       const float oi[3] = {pi.x, pi.y, pi.z};
-      const int ti = (wjaux[i] >> 12) & 3;
+      const int ti = aux_type(wjaux[i]);
       const float hi = pi.w;
       // 1 / rho_t^2 = tau^-2d h^2d, v = (dt1/2) a, eta = (dt1/2) e and dW/dr / r =
       // -5 alpha 2^(d+2) (h_i + h_j)^-(d+2) (1 - q/2)^3 for the pair's h_ij: the pair sum takes h^2d,
@@ -671,11 +679,14 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
       if (ei > 0.f) {
         const BufRes rpos = buf_res(wpos, 16, (uint32_t)g.n), raux = buf_res(wjaux, 4, (uint32_t)g.n);
         const BufRes racc = buf_res(acc, 16, (uint32_t)g.n);
-        const auto body = [&](uint32_t j, float dy0, float dz0, bool v) {
-          const float4 pj = buf_f4(rpos, j);
-          const uint32_t aj = buf_u32(raux, j);
-          // issued with the position load so that its latency overlaps the range test
-          const float4 accj = buf_f4(racc, j);
+        struct Nb {
+          float4 p, acc;
+          uint32_t a;
+        };
+        const auto fetch = [&](uint32_t j) { return Nb{buf_f4(rpos, j), buf_f4(racc, j), buf_u32(raux, j)}; };
+        const auto use = [&](const Nb &nb, float dy0, float dz0, bool) {
+          const float4 pj = nb.p, accj = nb.acc;
+          const uint32_t aj = nb.a;
           const float dx = sep_x<PER, D>(g, (float)ci[0], aj, oi[0], pj.x);
           const float dy = dy0 - pj.y;
           float r2 = dx * dx + dy * dy;
@@ -685,7 +696,9 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
           }
           const float hs = hi + pj.w;   // 2 h_ij
           const float hij = kh * hs;
-          if (!(v && r2 > 1e-30f && r2 < hij * hij && type_at_least(aj, ti))) return;
+          // the particle itself (r = 0 exactly: its own offsets are subtracted from themselves)
+          // and coincident particles fail r^2 > 0, so the slot's self flag v is not needed
+          if (!(r2 > 1e-30f && r2 < hij * hij && type_at_least(aj, ti))) return;
           const float r = fast_sqrt(r2);
           // e_i e_j / (e_i + e_j), half the harmonic mean; e_i > 0 here and e_j >= 0, so the sum
           // is positive
@@ -701,7 +714,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
           if constexpr (D == 3) bz = fmaf(s, acci.z - accj.z, bz);
         };
         scan_group_table<D, L, row_table_rows<L>(), PER>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(),
-                                                          ci, oi, rs, g, cellbase, cstart, body);
+                                                          ci, oi, rs, g, cellbase, cstart, pair_body<PIPE>(fetch, use));
       }
     }
     gbx = group_sum<L>(bx);
@@ -737,7 +750,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
       const float4 pe = wpos[io];
       const float oi[3] = {pe.x, pe.y, pe.z};
       const uint32_t ai = wjaux[io];
-      int ti = (ai >> 12) & 3;
+      int ti = aux_type(ai);
       const float4 acce = acc[io];
       const float vix = hdt * acce.x, viy = hdt * acce.y, viz = hdt * acce.z;
       float b[3] = {vscale * ep[0 * P + p], vscale * ep[1 * P + p], D == 3 ? vscale * ep[2 * P + p] : 0.f};
@@ -875,7 +888,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
       }
       skey[io] = cellbase + pack_key<D>(c, o, g);
       soff[io] = make_float4(o[0], o[1], D == 3 ? o[2] : 0.f, 0.f);
-      sct[io] = (uint32_t)ti | ((ai >> 14) << 2);
+      sct[io] = (uint32_t)ti | (aux_colour(ai) << 2);
       sid[io] = wid[io];
       if (at_out) at_out[io] = make_float4(b[0], b[1], b[2], 0.f);
       if (v_out) v_out[io] = make_float4(v[0], v[1], v[2], 0.f);
@@ -898,7 +911,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
 template <int D, int L, bool PER>
 __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_integrate(int b0, MPSPH_PASS2_PARAMS) {
   __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
-  viscous_integrate_block<D, L, PER>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, MPSPH_PASS2_ARGS);
+  viscous_integrate_block<D, L, PER, !PER>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, MPSPH_PASS2_ARGS);
 }
 
 
@@ -940,10 +953,10 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_forc
     const int it = __builtin_amdgcn_readfirstlane(sitem);   // the same in every lane
     if (it >= nb) break;
     if constexpr (DM == 5) {
-      if (it < nb2) density_force_block<2, L, PER, DBG>(b0 + it, rowtab, nullptr, MPSPH_PASS1_ARGS);
-      else density_force_block<3, L, PER, DBG>(b0 + it, rowtab, nullptr, MPSPH_PASS1_ARGS);
+      if (it < nb2) density_force_block<2, L, PER, DBG, false, false>(b0 + it, rowtab, nullptr, MPSPH_PASS1_ARGS);
+      else density_force_block<3, L, PER, DBG, false, false>(b0 + it, rowtab, nullptr, MPSPH_PASS1_ARGS);
     } else {
-      density_force_block<DM, L, PER, DBG>(b0 + it, rowtab, nullptr, MPSPH_PASS1_ARGS);
+      density_force_block<DM, L, PER, DBG, false, false>(b0 + it, rowtab, nullptr, MPSPH_PASS1_ARGS);
     }
   }
   if (threadIdx.x == 0) queue_done(queue);
@@ -962,10 +975,10 @@ __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_inte
     const int it = __builtin_amdgcn_readfirstlane(sitem);   // the same in every lane
     if (it >= nb) break;
     if constexpr (DM == 5) {
-      if (it < nb2) viscous_integrate_block<2, L, PER>(b0 + it, rowtab, MPSPH_PASS2_ARGS);
-      else viscous_integrate_block<3, L, PER>(b0 + it, rowtab, MPSPH_PASS2_ARGS);
+      if (it < nb2) viscous_integrate_block<2, L, PER, false>(b0 + it, rowtab, MPSPH_PASS2_ARGS);
+      else viscous_integrate_block<3, L, PER, false>(b0 + it, rowtab, MPSPH_PASS2_ARGS);
     } else {
-      viscous_integrate_block<DM, L, PER>(b0 + it, rowtab, MPSPH_PASS2_ARGS);
+      viscous_integrate_block<DM, L, PER, false>(b0 + it, rowtab, MPSPH_PASS2_ARGS);
     }
   }
   if (threadIdx.x == 0) queue_done(queue);

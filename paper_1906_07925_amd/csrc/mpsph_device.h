@@ -222,9 +222,18 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }  // x >= 0; sqrt(0) = 0
 
-// Whether the particle of flags word aux (type in bits 12-13) has a type of at least t: the type
-// field is compared in place, one and plus one compare.
-__device__ __forceinline__ bool type_at_least(uint32_t aux, int t) { return (aux & 0x3000u) >= ((uint32_t)t << 12); }
+// Flags word of a particle in the sorted order: colour in bits 0-15, x (sub-)cell in bits 16-27
+// (16-23 in 3D), type in bits 30-31.  The pair loops test the fields in place: colours with one
+// 16-bit compare of the low halves, the type (the top field) with one compare of the whole word,
+// and a 3D x cell converts from its byte in one instruction.
+__device__ __forceinline__ uint32_t pack_aux(uint32_t cx, uint32_t type, uint32_t colour) {
+  return colour | (cx << 16) | (type << 30);
+}
+__device__ __forceinline__ int aux_type(uint32_t aux) { return (int)(aux >> 30); }
+__device__ __forceinline__ uint32_t aux_colour(uint32_t aux) { return aux & 0xFFFFu; }
+__device__ __forceinline__ bool colour_differs(uint32_t a, uint32_t b) { return (uint16_t)a != (uint16_t)b; }
+// whether the particle of flags word aux has a type of at least t
+__device__ __forceinline__ bool type_at_least(uint32_t aux, int t) { return aux >= ((uint32_t)t << 30); }
 
 template <int D>
 __device__ __forceinline__ float powd(float s) {  // s^D

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "mpsph_device.h"
 
 // The candidate scan ends each chunk with NaN row offsets and relies on every range test failing
@@ -28,11 +30,11 @@ namespace mpsph {
 #define MPSPH_LANES 4
 #endif
 
-// x cell of a particle from its flags word (bits 0-11).  A 3D grid has at most 2^8 cells per
-// axis, so there the low byte holds it and converts to float in one instruction.
+// x cell of a particle from its flags word (bits 16-27).  A 3D grid has at most 2^8 cells per
+// axis, so there the word's third byte holds it and converts to float in one instruction.
 template <int D>
 __device__ __forceinline__ float cell_x(uint32_t aux) {
-  return D == 3 ? (float)(aux & 0xFFu) : (float)(aux & 0xFFFu);
+  return D == 3 ? (float)((aux >> 16) & 0xFFu) : (float)((aux >> 16) & 0xFFFu);
 }
 
 // x separation in cell units with the minimum image of a periodic box (period P cells); the
@@ -109,8 +111,35 @@ constexpr int row_table_stride() {
 // The row's base index goes through remap(cy, cz, a) (a: the global index of the row's first
 // candidate) before it enters the table, so that the slots can index a staged copy of the
 // neighbours; self is the particle's own index in that numbering.
+// A body may also come in two parts, fetch(j) -> payload (the slot's neighbour loads) and
+// use(payload, dy0, dz0, valid) (its arithmetic): the scan then issues the loads of the group's
+// next slot round before the arithmetic of the current one, so that their latency overlaps it.
+// A fetch past the chunk's end gets an index below 2L (bounds-checked loads again).
 struct IdentityRemap {
   __device__ __forceinline__ uint32_t operator()(int, int, uint32_t a) const { return a; }
+};
+template <typename FetchF, typename UseF>
+struct SplitBody {
+  FetchF fetch;
+  UseF use;
+};
+// The two-part body when PIPE, else one body that loads and computes in turn (fewer registers
+// live across the loop: the kernels that could not hold a second round's loads in 64 registers
+// without spilling take it).
+template <bool PIPE, typename FetchF, typename UseF>
+__device__ __forceinline__ auto pair_body(FetchF fetch, UseF use) {
+  if constexpr (PIPE)
+    return SplitBody<FetchF, UseF>{fetch, use};
+  else
+    return [=](uint32_t j, float dy0, float dz0, bool v) { use(fetch(j), dy0, dz0, v); };
+}
+template <typename T>
+struct IsSplitBody {
+  static constexpr bool value = false;
+};
+template <typename F, typename U>
+struct IsSplitBody<SplitBody<F, U>> {
+  static constexpr bool value = true;
 };
 template <int D, int L, int C, bool PER = false, typename BodyF, typename RemapF = IdentityRemap>
 __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab, int stride, const int *ci,
@@ -225,11 +254,38 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
     // the chunk's slots, L at a time; slot t of row e is candidate base_e + t
     uint32_t e = 0;
     uint4 cur = tab[0];
-    for (uint32_t t0 = 0; t0 < run; t0 += L) {
-      const uint32_t t = t0 + (uint32_t)sub;
+    if constexpr (IsSplitBody<typename std::decay<BodyF>::type>::value) {
+      // one round ahead: the loads of slot t + L are issued before the arithmetic of slot t
+      uint32_t t = (uint32_t)sub;
       while (t >= cur.y) cur = tab[++e * (uint32_t)stride];
-      const uint32_t j = cur.x + t;
-      body(j, __uint_as_float(cur.z), __uint_as_float(cur.w), j != self);
+      uint32_t j = cur.x + t;
+      float dy = __uint_as_float(cur.z), dz = __uint_as_float(cur.w);
+      // two payloads used in turn (the loop is unrolled twice), so that none is copied
+      auto pa = body.fetch(j);
+      decltype(pa) pb;
+      const auto round = [&](const auto &now, auto &next) {
+        const uint32_t tn = t + L;
+        while (tn >= cur.y) cur = tab[++e * (uint32_t)stride];
+        const uint32_t jn = cur.x + tn;
+        next = body.fetch(jn);
+        body.use(now, dy, dz, j != self);
+        j = jn;
+        t = tn;
+        dy = __uint_as_float(cur.z);
+        dz = __uint_as_float(cur.w);
+      };
+      for (uint32_t t0 = 0; t0 < run; t0 += 2 * L) {
+        round(pa, pb);
+        if (t0 + L >= run) break;
+        round(pb, pa);
+      }
+    } else {
+      for (uint32_t t0 = 0; t0 < run; t0 += L) {
+        const uint32_t t = t0 + (uint32_t)sub;
+        while (t >= cur.y) cur = tab[++e * (uint32_t)stride];
+        const uint32_t j = cur.x + t;
+        body(j, __uint_as_float(cur.z), __uint_as_float(cur.w), j != self);
+      }
     }
   }
   return total > 0u ? total - 1u : 0u;

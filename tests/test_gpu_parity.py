@@ -154,6 +154,38 @@ def test_single_colour_ignores_sigma(torch_cuda):
     assert np.array_equal(ga["x1"], gb["x1"])
 
 
+def test_colour_labels_compare_by_equality_only(torch_cuda):
+    """Colours are labels in [0, 2^16): relabelling them one to one (up to the largest label)
+    leaves the steps bit for bit unchanged; labels outside the range and types outside [0, 3]
+    are rejected on load."""
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    cfg = W.config("square_4k", scale=0.25)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    s0 = _s0(spec)
+    relabel = np.array([65535, 0, 40000, 1], dtype=np.int32)
+    assert col.max() < relabel.size
+    ma, ga = PU.gpu_run(spec, s0, x32, col, typ, steps=3, fields=())
+    mb, gb = PU.gpu_run(spec, s0, x32, relabel[col], typ, steps=3, fields=())
+    assert ma["interface_pairs"] > 0
+    assert np.array_equal(ga["x1"], gb["x1"])
+    assert {k: ma[k] for k in ("pairs", "interface_pairs", "dt1")} == {k: mb[k] for k in ("pairs", "interface_pairs", "dt1")}
+    R = M.Relaxer(spec, n=x32.shape[0], s0=s0)
+    xd = torch.from_numpy(x32).cuda()
+    for bad_col, bad_typ in ((65536, 0), (-1, 0), (0, 4), (0, -1)):
+        c = torch.from_numpy(col).cuda()
+        t = torch.from_numpy(typ).cuda()
+        c[7] = bad_col
+        t[9] = bad_typ
+        with pytest.raises(M.MpsphError) as e:
+            R.load(xd, c, t)
+        assert e.value.code == 1, (bad_col, bad_typ)
+    R.load(xd, torch.from_numpy(relabel[col]).cuda(), torch.from_numpy(typ).cuda())
+    R.step(1)
+    R.close()
+
+
 def test_momentum_conservation(torch_cuda):
     cfg = W.config("cube_inclusion_2m", scale=0.01)
     x32, col, typ = PU.state_f32(cfg)
