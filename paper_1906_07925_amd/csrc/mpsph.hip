@@ -440,13 +440,9 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
       wsum += dens ? u2 * u2 * fmaf(2.f, q, 1.f) : 0.f;
       if (!force) return;
-      const float rh = fast_rcp(hs);                // 1 / (2 h_ij)
-      const float uu = fmaf(-r, rh, 1.f);           // 1 - q/2, q = r / h_ij
-      const float rh2 = rh * rh;
-      const float rhp = D == 3 ? rh2 * rh2 * rh : rh2 * rh2;  // (2 h_ij)^-(d+2)
       const float hj2 = pj.w * pj.w;
       // (P_i + P_j) (-dW/dr / r) over the common factor fscale (>= 0)
-      const float s = (diff ? opb : 1.f) * powd_add<D>(hj2, Phi) * (rhp * uu * uu * uu);
+      const float s = (diff ? opb : 1.f) * powd_add<D>(hj2, Phi) * kernel_slope_factor<D>(r, fast_rcp(hs));
       ax = fmaf(s, dx, ax);
       ay = fmaf(s, dy, ay);
       az = fmaf(s, dz, az);
@@ -700,21 +696,21 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
           // and coincident particles fail r^2 > 0, so the slot's self flag v is not needed
           if (!(r2 > 1e-30f && r2 < hij * hij && type_at_least(aj, ti))) return;
           const float r = fast_sqrt(r2);
-          // e_i e_j / (e_i + e_j), half the harmonic mean; e_i > 0 here and e_j >= 0, so the sum
-          // is positive
-          const float eh = acci.w * accj.w * fast_rcp(acci.w + accj.w);
-          const float rh = fast_rcp(hs);
-          const float uu = fmaf(-r, rh, 1.f);  // 1 - q/2, q = r / h_ij
-          const float rh2 = rh * rh;
-          const float rhp = D == 3 ? rh2 * rh2 * rh : rh2 * rh2;  // (2 h_ij)^-(d+2)
+          // e_j / (e_i + e_j): half the harmonic mean e_i e_j / (e_i + e_j) over e_i, which
+          // multiplies the sum once; e_i > 0 here and e_j >= 0, so the sum is positive
+          const float eh = accj.w * fast_rcp(acci.w + accj.w);
           const float hj2 = pj.w * pj.w;
-          const float s = eh * powd_add<D>(hj2, invi) * (rhp * uu * uu * uu);
+          const float s = eh * powd_add<D>(hj2, invi) * kernel_slope_factor<D>(r, fast_rcp(hs));
           bx = fmaf(s, acci.x - accj.x, bx);
           by = fmaf(s, acci.y - accj.y, by);
           if constexpr (D == 3) bz = fmaf(s, acci.z - accj.z, bz);
         };
         scan_group_table<D, L, row_table_rows<L>(), PER>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(),
                                                           ci, oi, rs, g, cellbase, cstart, pair_body<PIPE>(fetch, use));
+        // the factor e_i of every pair term
+        bx *= acci.w;
+        by *= acci.w;
+        bz *= acci.w;
       }
     }
     gbx = group_sum<L>(bx);

@@ -235,6 +235,15 @@ __device__ __forceinline__ bool colour_differs(uint32_t a, uint32_t b) { return 
 // whether the particle of flags word aux has a type of at least t
 __device__ __forceinline__ bool type_at_least(uint32_t aux, int t) { return aux >= ((uint32_t)t << 30); }
 
+// (2 h_ij)^-(d+2) (1 - q/2)^3 with q = r / h_ij, from rh = 1 / (2 h_ij): with
+// a = rh (1 - r rh) = (1 - q/2) / (2 h_ij) it is a^3 rh^(d-1) (five multiplies and adds).
+template <int D>
+__device__ __forceinline__ float kernel_slope_factor(float r, float rh) {
+  const float rh2 = rh * rh;
+  const float a = fmaf(-r, rh2, rh);
+  return D == 3 ? a * a * a * rh2 : a * a * a * rh;
+}
+
 template <int D>
 __device__ __forceinline__ float powd(float s) {  // s^D
   if constexpr (D == 2) return s * s;
