@@ -705,8 +705,9 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
           by = fmaf(s, acci.y - accj.y, by);
           if constexpr (D == 3) bz = fmaf(s, acci.z - accj.z, bz);
         };
-        scan_group_table<D, L, row_table_rows<L>(), PER>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(),
-                                                          ci, oi, rs, g, cellbase, cstart, pair_body<PIPE>(fetch, use));
+        scan_group_table<D, L, row_table_rows<L>(), PER, false>(i, sub, rowtab + threadIdx.x / L,
+                                                                 row_table_stride<L>(), ci, oi, rs, g, cellbase, cstart,
+                                                                 pair_body<PIPE>(fetch, use));
         // the factor e_i of every pair term
         bx *= acci.w;
         by *= acci.w;

@@ -141,13 +141,13 @@ template <typename F, typename U>
 struct IsSplitBody<SplitBody<F, U>> {
   static constexpr bool value = true;
 };
-template <int D, int L, int C, bool PER = false, typename BodyF, typename RemapF = IdentityRemap>
+template <int D, int L, int C, bool PER = false, bool CUT = true, typename BodyF, typename RemapF = IdentityRemap>
 __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab, int stride, const int *ci,
                                                      const float *oi, float rs, const GridDev &g, uint32_t cellbase,
                                                      const uint32_t *__restrict__ cstart, BodyF &&body,
                                                      RemapF remap = RemapF(), uint32_t self = 0xFFFFFFFFu) {
   if (self == 0xFFFFFFFFu) self = (uint32_t)i;
-  static_assert(C > L, "a table chunk holds at least one round of rows and the end marker");
+  static_assert(C > L + 1, "a table chunk holds at least one round of rows (one of them split) and the end marker");
   // one lane per particle is not supported: with no cross-lane operation in the loop nest the
   // compiler merged the chunk loop with the table loop and took the chunk loop's exit mask from a
   // compare of the divergent inner loop, and such a build listed some candidates twice (the same
@@ -186,12 +186,12 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
   const float fx = (float)(1u << g.xe);
   const int xlast = ((g.gmax + 1) << g.xe) - 1;
   const uint32_t kx = g.k + g.xe;
-  uint32_t total = 0;   // candidates of the group, the particle itself included
+  uint32_t total = 0;   // candidates of the group (the particle itself only without CUT)
   int q0 = 0;
   while (q0 < nrows) {
     // table of the next chunk of rows: whole rounds of L rows while a round surely fits
     uint32_t ne = 0, run = 0;
-    while (q0 < nrows && ne + L < (uint32_t)C) {
+    while (q0 < nrows && ne + L + 1u < (uint32_t)C) {
       const int q = q0 + sub;
       const int qz = (int)(((float)q + 0.5f) * inv_ny);   // q / ny (q, ny < 2^12)
       const int cz = z0 + qz, cy = y0 + (q - qz * ny);
@@ -228,8 +228,20 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
         b = min(cstart[kb + (uint32_t)(x1 - x0) + 1u], nmax);
       }
       const uint32_t len = b > a ? b - a : 0u;
-      // prefix sums over the group of the run lengths and of the non-empty flags
-      uint32_t incl = len, nz = len > 0u ? 1u : 0u;
+      // the particle's own slot is cut out of its row, which becomes the runs before and after it
+      // (len1 and len2 candidates; a row without the particle keeps len1 = len)
+      uint32_t base = 0u, len1 = len, len2 = 0u;
+      if (len > 0u) {
+        base = remap(cy, cz, a);
+        const uint32_t o = self - base;   // >= len unless the particle lies in this run
+        if (CUT && o < len) {
+          len1 = o;
+          len2 = len - o - 1u;
+        }
+      }
+      const uint32_t lsum = len1 + len2, nl = (len1 > 0u ? 1u : 0u) + (len2 > 0u ? 1u : 0u);
+      // prefix sums over the group of the candidates and of the table entries
+      uint32_t incl = lsum, nz = nl;
 #pragma unroll
       for (int o = 1; o < L; o <<= 1) {
         const uint32_t v = lane_up(incl, o), w = lane_up(nz, o);
@@ -238,11 +250,18 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
           nz += w;
         }
       }
-      if (len > 0u) {
-        const uint32_t end = run + incl;   // end of the row in the chunk's slot order
+      if (nl > 0u) {
         const float dyo = (float)(ci[1] - cy) + oi[1], dzo = D == 3 ? (float)(ci[2] - cz) + oi[2] : 0.f;
-        tab[(ne + nz - 1u) * (uint32_t)stride] =
-            make_uint4(remap(cy, cz, a) - (end - len), end, __float_as_uint(dyo), __float_as_uint(dzo));
+        uint32_t end = run + incl - lsum, en = ne + nz - nl;   // the lane's first slot and entry
+        if (len1 > 0u) {
+          end += len1;
+          tab[en++ * (uint32_t)stride] = make_uint4(base - (end - len1), end, __float_as_uint(dyo), __float_as_uint(dzo));
+        }
+        if (len2 > 0u) {
+          end += len2;
+          tab[en * (uint32_t)stride] =
+              make_uint4(base + len1 + 1u - (end - len2), end, __float_as_uint(dyo), __float_as_uint(dzo));
+        }
       }
       run += group_last<L>(incl);
       ne += group_last<L>(nz);
@@ -268,27 +287,32 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
         while (tn >= cur.y) cur = tab[++e * (uint32_t)stride];
         const uint32_t jn = cur.x + tn;
         next = body.fetch(jn);
-        body.use(now, dy, dz, j != self);
+        body.use(now, dy, dz, CUT || j != self);
         j = jn;
         t = tn;
         dy = __uint_as_float(cur.z);
         dz = __uint_as_float(cur.w);
       };
-      for (uint32_t t0 = 0; t0 < run; t0 += 2 * L) {
-        round(pa, pb);
-        if (t0 + L >= run) break;
-        round(pb, pa);
+      // the lane's rounds end when its next slot t reaches the chunk's end (run + sub)
+      const uint32_t tend = run + (uint32_t)sub;
+      if (t < tend) {
+        while (true) {
+          round(pa, pb);
+          if (t >= tend) break;
+          round(pb, pa);
+          if (t >= tend) break;
+        }
       }
     } else {
       for (uint32_t t0 = 0; t0 < run; t0 += L) {
         const uint32_t t = t0 + (uint32_t)sub;
         while (t >= cur.y) cur = tab[++e * (uint32_t)stride];
         const uint32_t j = cur.x + t;
-        body(j, __uint_as_float(cur.z), __uint_as_float(cur.w), j != self);
+        body(j, __uint_as_float(cur.z), __uint_as_float(cur.w), CUT || j != self);
       }
     }
   }
-  return total > 0u ? total - 1u : 0u;
+  return CUT ? total : (total > 0u ? total - 1u : 0u);
 }
 
 // Sum / minimum across the L lanes of a group (fixed butterfly order: lane l combines with lane
