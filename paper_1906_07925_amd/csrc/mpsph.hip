@@ -437,8 +437,10 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
       const bool force = feel && apart;
       if (!(dens || force)) return;
       const float r = fast_sqrt(r2);
-      const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
-      wsum += dens ? u2 * u2 * fmaf(2.f, q, 1.f) : 0.f;
+      if (dens) {
+        const float q = r * ihi, u = fmaf(-0.5f, q, 1.f), u2 = u * u;
+        wsum += u2 * u2 * fmaf(2.f, q, 1.f);
+      }
       if (!force) return;
       const float hj2 = pj.w * pj.w;
       // (P_i + P_j) (-dW/dr / r) over the common factor fscale (>= 0)
