@@ -108,7 +108,7 @@ typedef struct {
   const double *rbf_centre;/* host, n_rbf x dim, copied at create */
   const double *rbf_coeff; /* host, n_rbf, copied at create */
   double rbf_width;
-  double tau, kappa;       /* h = tau s; cut-off r_c = kappa h (support of the kernel) */
+  double tau, kappa;       /* h = tau s; cut-off r_c = kappa h, kappa in (0, 2] (the kernel's support is 2h) */
   double p0, sigma0;       /* EOS constant (Eq. 18); initial surface-tension strength (Eq. 25) */
   int64_t t0, t1;          /* ramp of sigma over steps (t0, t1]; t0 = -1: sigma constant; t0 = -2:
                               automatic (t0 detected, t1 = t0 + max(1, round(theta t0)), §3.3) */

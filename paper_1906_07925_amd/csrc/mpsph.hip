@@ -1231,7 +1231,9 @@ bool valid_params(const mpsph_params *p) {
   if (p->field == MPSPH_RBF_EXP && (p->n_rbf < 0 || p->n_rbf > 64 || (p->n_rbf > 0 && (!p->rbf_centre || !p->rbf_coeff)) ||
                                     !(p->rbf_width > 0)))
     return false;
-  if (!(p->tau > 0) || !(p->kappa > 0) || !(p->p0 > 0) || !(p->sigma0 >= 0)) return false;
+  // the kernel's support is 2h: a cut-off beyond it would only add zero terms, and the pair
+  // kernels evaluate the kernel's polynomial without clamping it to its support
+  if (!(p->tau > 0) || !(p->kappa > 0 && p->kappa <= 2) || !(p->p0 > 0) || !(p->sigma0 >= 0)) return false;
   if (p->t0 < -2 || (p->t0 >= 0 && p->t1 < p->t0)) return false;
   if (!(p->nu_coeff >= 0) || !(p->c_acc > 0) || !(p->c_vel > 0) || !(p->c_visc > 0)) return false;
   if ((p->geometry == MPSPH_ANNULUS || p->geometry == MPSPH_BALL) && !(p->r_out > 0)) return false;

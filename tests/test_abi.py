@@ -114,4 +114,7 @@ def test_batch_workspace(lib):
     assert M.batch_workspace_bytes([], []) == 0
     bad = dict(specs[1], tau=-1.0)
     assert M.batch_workspace_bytes([specs[0], bad], ns[:2]) == 0
+    # cut-offs beyond the kernel's support 2h are refused, smaller ones accepted
+    assert M.batch_workspace_bytes([specs[0], dict(specs[1], kappa=2.5)], ns[:2]) == 0
+    assert M.batch_workspace_bytes([specs[0], dict(specs[1], kappa=1.5)], ns[:2]) > 0
     assert M.batch_workspace_bytes(specs[:2], [ns[0], -1]) == 0
