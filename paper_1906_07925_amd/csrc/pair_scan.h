@@ -271,27 +271,38 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
     if (sub == 0) tab[ne * (uint32_t)stride] = make_uint4(0u - run, 0xFFFFFFFFu, 0x7FC00000u, 0x7FC00000u);
     total += run;
     // the chunk's slots, L at a time; slot t of row e is candidate base_e + t
-    uint32_t e = 0;
-    uint4 cur = tab[0];
     if constexpr (IsSplitBody<typename std::decay<BodyF>::type>::value) {
-      // one round ahead: the loads of slot t + L are issued before the arithmetic of slot t
+      // one round ahead: the loads of slot t + L are issued before the arithmetic of slot t.  A
+      // slot's row is found by walking the rows' ends, and its base and offsets are then read from
+      // the table into the slot's own registers, so that none is copied
+      using Payload = decltype(body.fetch(0u));
+      struct Slot {
+        Payload p;
+        float dy, dz;
+        uint32_t j;
+      };
+      const uint4 *rp = tab;   // row of the last located slot
+      uint32_t y = rp->y;      // its end
+      const auto locate = [&](uint32_t tt, Slot &sl) {
+        while (tt >= y) {
+          rp += stride;
+          y = rp->y;
+        }
+        const uint4 row = *rp;
+        sl.j = row.x + tt;
+        sl.dy = __uint_as_float(row.z);
+        sl.dz = __uint_as_float(row.w);
+        sl.p = body.fetch(sl.j);
+      };
       uint32_t t = (uint32_t)sub;
-      while (t >= cur.y) cur = tab[++e * (uint32_t)stride];
-      uint32_t j = cur.x + t;
-      float dy = __uint_as_float(cur.z), dz = __uint_as_float(cur.w);
-      // two payloads used in turn (the loop is unrolled twice), so that none is copied
-      auto pa = body.fetch(j);
-      decltype(pa) pb;
-      const auto round = [&](const auto &now, auto &next) {
+      // two slots used in turn (the loop is unrolled twice)
+      Slot pa, pb;
+      locate(t, pa);
+      const auto round = [&](const Slot &now, Slot &next) {
         const uint32_t tn = t + L;
-        while (tn >= cur.y) cur = tab[++e * (uint32_t)stride];
-        const uint32_t jn = cur.x + tn;
-        next = body.fetch(jn);
-        body.use(now, dy, dz, CUT || j != self);
-        j = jn;
+        locate(tn, next);
+        body.use(now.p, now.dy, now.dz, CUT || now.j != self);
         t = tn;
-        dy = __uint_as_float(cur.z);
-        dz = __uint_as_float(cur.w);
       };
       // the lane's rounds end when its next slot t reaches the chunk's end (run + sub)
       const uint32_t tend = run + (uint32_t)sub;
@@ -304,6 +315,8 @@ __device__ __forceinline__ uint32_t scan_group_table(int i, int sub, uint4 *tab,
         }
       }
     } else {
+      uint32_t e = 0;
+      uint4 cur = tab[0];
       for (uint32_t t0 = 0; t0 < run; t0 += L) {
         const uint32_t t = t0 + (uint32_t)sub;
         while (t >= cur.y) cur = tab[++e * (uint32_t)stride];
