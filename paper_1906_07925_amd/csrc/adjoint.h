@@ -26,13 +26,14 @@
 #include "mpsph_device.h"
 #include "pair_scan.h"
 
-// Waves per SIMD the viscous adjoint is compiled for; 0 leaves it to the compiler (5 waves in 3D).
-// With the particle's own data scoped to the pair loop and its per-group values in LDS, 6 waves
-// (80 VGPRs) need no scratch memory; 7 waves still spill 28 bytes per lane in 3D.  Reverse sweep
-// of the 2^20-particle RBF cube over 50 steps: 116.4 ms at 6 waves, 115.2 ms at 7 (68 bytes of
-// spills before these changes: 116.3 ms).
+// Waves per SIMD the viscous adjoint is compiled for; 0 leaves it to the compiler.  With the
+// particle's own data scoped to the pair loop and its per-group values in LDS, and the neighbour
+// loads issued one slot round ahead (four loads held for the next round), 5 waves (88 VGPRs in
+// 3D) need no scratch memory; at 6 waves it spills 10 registers.  Reverse sweep of the
+// 2^20-particle RBF cube over 50 steps: 106.7 ms at 5 waves, 109.4 ms at 6 with the spills,
+// 107.4 ms with one round of loads at 6 waves.
 #ifndef MPSPH_ADJ_WAVES
-#define MPSPH_ADJ_WAVES 6
+#define MPSPH_ADJ_WAVES 5
 #endif
 #if MPSPH_ADJ_WAVES > 0
 #define MPSPH_ADJ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MPSPH_ADJ_WAVES, MPSPH_ADJ_WAVES)))
@@ -235,14 +236,18 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
     if (ei > 0.f) {
       const BufRes rpos = buf_res(tp.wpos, 16, (uint32_t)g.n), raux = buf_res(tp.wjaux, 4, (uint32_t)g.n);
       const BufRes racc = buf_res(tp.acc, 16, (uint32_t)g.n), rabv = buf_res(abv, 16, (uint32_t)g.n);
-      scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
-                                                 0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-        // past the arrays for invalid slots: bounds-checked loads, all issued before the range
-        // test so that their latency overlaps it
-        const float4 pj = buf_f4(rpos, jr);
-        const uint32_t aj = buf_u32(raux, jr);
-        const float4 aj4 = buf_f4(racc, jr);
-        const float4 abj = buf_f4(rabv, jr);
+      struct Nb {
+        float4 p, a4, ab;
+        uint32_t a;
+      };
+      // the neighbour's loads (bounds-checked: slots past the arrays read zeros) are issued one
+      // slot round ahead of the pair's arithmetic
+      const auto fetch = [&](uint32_t jr) {
+        return Nb{buf_f4(rpos, jr), buf_f4(racc, jr), buf_f4(rabv, jr), buf_u32(raux, jr)};
+      };
+      const auto use = [&](const Nb &nb, float dy0, float dz0, bool v) {
+        const float4 pj = nb.p, aj4 = nb.a4, abj = nb.ab;
+        const uint32_t aj = nb.a;
         const float dx = ((float)ci[0] - cell_x<D>(aj)) + (oi[0] - pj.x);
         const float dy = dy0 - pj.y;
         float dz = 0.f;
@@ -286,7 +291,9 @@ __global__ __launch_bounds__(kBlock) MPSPH_ADJ_OCCUPANCY void adj_visc(const Dom
         xb[0] = fmaf(cx, dx, xb[0]);
         xb[1] = fmaf(cx, dy, xb[1]);
         if constexpr (D == 3) xb[2] = fmaf(cx, dz, xb[2]);
-      });
+      };
+      scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs,
+                                                  g, 0u, tp.cstart, pair_body<true>(fetch, use));
     }
     }
 #pragma unroll
@@ -417,12 +424,16 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
   float xb[3] = {0.f, 0.f, 0.f}, sb = 0.f;
   const BufRes rpos = buf_res(tp.wpos, 16, (uint32_t)g.n), raux = buf_res(tp.wjaux, 4, (uint32_t)g.n);
   const BufRes rfb = buf_res(fbar, 16, (uint32_t)g.n);
-  scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
-                                                 0u, tp.cstart, [&](uint32_t jr, float dy0, float dz0, bool v) {
-    // past the arrays for invalid slots: bounds-checked loads, all issued before the range test
-    const float4 pj = buf_f4(rpos, jr);
-    const uint32_t aj = buf_u32(raux, jr);
-    const float4 fj = buf_f4(rfb, jr);
+  struct Nb {
+    float4 p, f;
+    uint32_t a;
+  };
+  // the neighbour's loads (bounds-checked: slots past the arrays read zeros) are issued one slot
+  // round ahead of the pair's arithmetic
+  const auto fetch = [&](uint32_t jr) { return Nb{buf_f4(rpos, jr), buf_f4(rfb, jr), buf_u32(raux, jr)}; };
+  const auto use = [&](const Nb &nb, float dy0, float dz0, bool v) {
+    const float4 pj = nb.p, fj = nb.f;
+    const uint32_t aj = nb.a;
     const float dx = ((float)ci[0] - cell_x<D>(aj)) + (oi[0] - pj.x);
     const float dy = dy0 - pj.y;
     float dz = 0.f;
@@ -455,7 +466,9 @@ __global__ __launch_bounds__(kBlock) void adj_force(const DomDev *__restrict__ d
     xb[1] += w * wf[1] + cr * dy;
     if constexpr (D == 3) xb[2] += w * wf[2] + cr * dz;
     sb = fmaf(uw * B, dPi * gg + Psum * dgh * (0.5f * sp.tau), sb);
-  });
+  };
+  scan_group_table<D, L, row_table_rows<L>()>(i, sub, rowtab + threadIdx.x / L, row_table_stride<L>(), ci, oi, rs, g,
+                                              0u, tp.cstart, pair_body<true>(fetch, use));
 #pragma unroll
   for (int a = 0; a < 3; ++a) xb[a] = group_sum<L>(xb[a]);
   sb = group_sum<L>(sb);

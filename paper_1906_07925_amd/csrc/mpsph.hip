@@ -2642,7 +2642,7 @@ struct GradRun {
   hipStream_t st;
   const Group *gr;
   int nb1;
-  int nbp;  // blocks of the adjoint pair kernels (MPSPH_LANES lanes per particle)
+  int nbp;  // blocks of the adjoint pair kernels (MPSPH_ADJ_LANES lanes per particle)
   char *g;
   template <typename T>
   T *at(size_t off) {
@@ -2732,7 +2732,7 @@ int loss_backward(GradRun &R, double lam) {
     return fail(ctx, MPSPH_E_DEVICE);
   launch_group<D>(ctx, *R.gr, skeys, perm, kDtSlots, R.st, nullptr);
   const int nbp = R.nbp;
-  loss_density<D, MPSPH_LANES><<<nbp, kBlock, 0, R.st>>>(dom, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
+  loss_density<D, MPSPH_ADJ_LANES><<<nbp, kBlock, 0, R.st>>>(dom, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
                                                        ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart),
                                                        R.at<float>(R.P.e), R.at<double>(R.P.pb));
   loss_value<<<1, 256, 0, R.st>>>(R.at<double>(R.P.pb), nbp, 1.0 / n, lam, R.at<double>(R.P.scal) + 1);
@@ -2740,7 +2740,7 @@ int loss_backward(GradRun &R, double lam) {
   const double Lh = dm.p.tau * dm.d.lip;
   const double kl = dm.p.kappa * Lh;
   const float reach = kl < 0.95 ? (float)(dm.p.kappa / (1.0 - kl) * (1.0 + 1e-4)) : 1e30f;
-  loss_grad<D, MPSPH_LANES><<<nbp, kBlock, 0, R.st>>>(dom, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
+  loss_grad<D, MPSPH_ADJ_LANES><<<nbp, kBlock, 0, R.st>>>(dom, ctx->at<uint32_t>(L.w_key), ctx->at<float4>(L.w_pos),
                                                     ctx->at<uint32_t>(L.w_jaux), ctx->at<uint32_t>(L.cstart),
                                                     R.at<float>(R.P.e), (float)(2.0 / n), (float)(lam / n), reach,
                                                     R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar));
@@ -2773,7 +2773,7 @@ int step_backward(GradRun &R, int m, int64_t t) {
   adj_drift<D><<<R.nb1, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.xbar), R.at<float4>(R.P.xacc),
                                            R.at<float4>(R.P.abv), R.at<float4>(R.P.vtb), R.at<float>(R.P.dtc), minbits,
                                            R.at<double>(R.P.pa));
-  adj_visc<D, MPSPH_LANES><<<nbp, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.abv), R.at<float4>(R.P.vtb),
+  adj_visc<D, MPSPH_ADJ_LANES><<<nbp, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.abv), R.at<float4>(R.P.vtb),
                                                    R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar),
                                                    R.at<float4>(R.P.abar), R.at<float>(R.P.dtc), minbits, argmin,
                                                    R.at<double>(R.P.pb));
@@ -2781,7 +2781,7 @@ int step_backward(GradRun &R, int m, int64_t t) {
                                   (float)dt2_factor(&dm.p), t1bar);
   adj_fbar<D><<<R.nb1, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.abar), t1bar, argmin, R.at<float>(R.P.sbar),
                                           R.at<float4>(R.P.fbar));
-  adj_force<D, MPSPH_LANES><<<nbp, kBlock, 0, R.st>>>(dom, tv, (float)t, R.at<float4>(R.P.fbar),
+  adj_force<D, MPSPH_ADJ_LANES><<<nbp, kBlock, 0, R.st>>>(dom, tv, (float)t, R.at<float4>(R.P.fbar),
                                                     R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar));
   adj_field<D><<<R.nb1, kBlock, 0, R.st>>>(dom, tv, R.at<float4>(R.P.xacc), R.at<float>(R.P.sbar),
                                            R.at<float4>(R.P.xbar), R.at<double>(R.P.cpart));
@@ -2803,7 +2803,7 @@ int grad_run(mpsph_ctx *ctx, int nsteps, int ckpt, double lam, double *loss_out,
   R.st = ctx->stream;
   R.gr = &L.grp[D - 2];
   R.nb1 = (n + kBlock - 1) / kBlock;
-  R.nbp = (int)(((int64_t)n * MPSPH_LANES + kBlock - 1) / kBlock);
+  R.nbp = (int)(((int64_t)n * MPSPH_ADJ_LANES + kBlock - 1) / kBlock);
   const int nseg = nsteps > 0 ? (nsteps + ckpt - 1) / ckpt : 0;
   const int seg_len = std::min(ckpt, std::max(nsteps, 1));
   R.P = grad_plan(n, L.ncells, nseg + 1, seg_len, R.nb1, R.nbp);

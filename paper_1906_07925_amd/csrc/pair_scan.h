@@ -24,10 +24,14 @@ namespace mpsph {
 // one particle (scan_group_table below).
 // ------------------------------------------------------------------------------------------
 // Lanes per particle of the pair kernels of a context that is not tuned (mpsph_configure and
-// mpsph_autotune choose 2, 4 or 8) and of the adjoint kernels.  Measured: 8 lanes are the fastest
-// on the 2M-particle graded cube, 4 on the 64-domain batch and on the RBF cube's gradient.
+// mpsph_autotune choose 2, 4 or 8), and of the adjoint's pair kernels.  Measured: 8 lanes are the
+// fastest on the 2M-particle graded cube, 4 on the RBF cube's forward steps (8 lanes: 4 % slower)
+// and equal on the 64-domain batch; the adjoint's pair kernels run faster at 8.
 #ifndef MPSPH_LANES
 #define MPSPH_LANES 4
+#endif
+#ifndef MPSPH_ADJ_LANES
+#define MPSPH_ADJ_LANES 8
 #endif
 
 // x cell of a particle from its flags word (bits 16-27).  A 3D grid has at most 2^8 cells per
