@@ -99,15 +99,17 @@ constexpr int row_table_stride() {
 // time, lane l taking every L-th one and advancing through the table as its slot index passes
 // the end of a row.  A group's loop ends when its own candidates end (no wave-wide rounds of
 // rows).  A table holds at most C - 1 rows and an end marker; a particle with more non-empty
-// rows is scanned in several chunks.
+// rows is scanned in several chunks.  With CUT the particle's own slot is cut out of its row
+// (the row becomes the runs before and after it), so the particle itself is never a slot.
 // The end marker (end of run 2^32 - 1, row offsets NaN) stops every lane's walk through the
 // table, so the slot loop tests neither the table's length nor the chunk's: a slot past the
 // chunk's end reaches the marker and gets the index t - run (in [0, L)) and NaN offsets, which
 // make its squared distance NaN and fail every range test of the bodies.
-// tab: the group's column of the table, entry e at tab[e * stride]; C > L.
+// tab: the group's column of the table, entry e at tab[e * stride]; C > L + 1.
 // body(j, dy0, dz0, valid) is called for every slot with the row offsets plus the particle's own
 // offsets, dy0 = ci[1] - cy + oi[1] and dz0 = ci[2] - cz + oi[2] (cell units; the y and z
-// separations are dy0 - oj[1] and dz0 - oj[2]); valid is false for the particle itself.  A slot
+// separations are dy0 - oj[1] and dz0 - oj[2]); valid is false for the particle itself (always
+// true with CUT).  A slot
 // past the chunk's end carries NaN offsets and an index below L that may still lie outside the
 // arrays (fewer than L particles): bodies load through bounds-checked buffer loads or clamp the
 // index, and must fail their range tests on a NaN distance.  The return value is the group's
@@ -116,7 +118,7 @@ constexpr int row_table_stride() {
 // candidate) before it enters the table, so that the slots can index a staged copy of the
 // neighbours; self is the particle's own index in that numbering.
 // A body may also come in two parts, fetch(j) -> payload (the slot's neighbour loads) and
-// use(payload, dy0, dz0, valid) (its arithmetic): the scan then issues the loads of the group's
+// use(payload, dy0, dz0, valid) (its arithmetic): the scan then issues the loads of a lane's
 // next slot round before the arithmetic of the current one, so that their latency overlaps it.
 // A fetch past the chunk's end gets an index below 2L (bounds-checked loads again).
 struct IdentityRemap {
