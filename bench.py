@@ -8,7 +8,8 @@ tension, both time steps, viscous pass, integrator, FP64 metrics) on that partic
 
 Prints one JSON line: pair interactions per second over the timed steps (ordered pairs
 i != j inside the cut-off that pass the type mask, counted on the device each step), the step
-rate, per-kernel times measured with HIP events on the library's stream, the roofline entry of
+rate, per-kernel times measured with HIP events on the library's stream (around the two pair
+passes in the timed steps, around every kernel in the 20 steps after them), the roofline entry of
 the dominant kernel (and per kernel: HBM fraction on algorithmic bytes, FP32 fraction of the pair
 passes on algorithmic FLOPs; the whole step against HBM), the early and late 100-step windows of
 1000-step runs (median of 5), the CPU oracle timed on the host on a bounded sample, and (object
@@ -171,7 +172,7 @@ def windows(torch, R, dev_x, dev_c, runs: int, early: int = 100, warm: int = 10,
 
 
 def kernel_rooflines(kern: dict, steps: int, n: int, ncells: int, pairs: int) -> dict:
-    """Per-kernel figures over the timed region: HBM fraction on algorithmic bytes for the
+    """Per-kernel figures over `steps` profiled steps: HBM fraction on algorithmic bytes for the
     memory-bound kernels, FP32 fraction on algorithmic FLOPs for the pair passes."""
     out = {}
     for name, (launches, ms) in kern.items():
@@ -423,6 +424,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--kernel-steps", type=int, default=20,
+                    help="steps after the timed ones with every kernel launch timed (per-kernel figures)")
     ap.add_argument("--config", type=str, default="",
                     help="K,L: cells per axis 2^K and L lanes per particle instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -486,13 +489,20 @@ def main():
     R.step(args.warmup)
     m0 = R.metrics()
     torch.cuda.synchronize()
-    R.profile(True)
+    # the timed steps record HIP events around the two pair passes only (events around every
+    # launch slow a step by a few per cent); every kernel is timed over the steps that follow
+    R.profile("pairs")
     t0 = time.perf_counter()
     R.step(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     m1 = R.metrics()
     kern = R.profile_read()
+    R.profile(True)
+    R.step(args.kernel_steps)
+    torch.cuda.synchronize()
+    m2 = R.metrics()
+    kern_all = R.profile_read()
     R.profile(False)
     elapsed = t1 - t0
     pairs = m1["pairs_total"] - m0["pairs_total"]
@@ -505,7 +515,7 @@ def main():
     launches, ms = kern[kname]
     avg_s = ms / launches / 1e3
     ncells = R.ncells()
-    per_kernel = kernel_rooflines(kern, args.steps, n, ncells, pairs)
+    per_kernel = kernel_rooflines(kern_all, args.kernel_steps, n, ncells, m2["pairs_total"] - m1["pairs_total"])
     roof = {"kernel": kname}
     if kname in FLOPS_PER_PAIR:
         flops = FLOPS_PER_PAIR[kname] * pairs / launches
@@ -553,7 +563,7 @@ def main():
         "pairs_per_step": pairs / args.steps,
         "candidates_per_s": cands / elapsed,
         "adjoint_forward_ratio": None,
-        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])},
+        "kernels_ms_per_step": {k: v[1] / args.kernel_steps for k, v in sorted(kern_all.items(), key=lambda kv: -kv[1][1])},
         "roofline": roof,
         "pair_passes": pair_passes,
         "hbm_whole_step": hbm_step,

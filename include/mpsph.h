@@ -385,8 +385,11 @@ MPSPH_API int mpsph_grad(mpsph_ctx *ctx, int32_t nsteps, int32_t ckpt_every, dou
                          double *grad_coeff_out, float *d_grad_pos);
 
 /* Per-kernel timing with HIP events on the context's stream.  enable = 1 starts recording
- * (resets the accumulators), 0 stops.  mpsph_profile_read() synchronises and returns, for up
- * to cap kernels, the name, the number of launches and the summed milliseconds. */
+ * every kernel, 2 only the pair passes (the kernels named pass_*: two events per launch slow a
+ * step by a few per cent, so a throughput measurement records only the kernels it needs), 0
+ * stops; 1 and 2 reset the accumulators.  mpsph_profile_read() synchronises and returns, for up
+ * to cap kernels, the name, the number of launches and the summed milliseconds.
+ * Errors: MPSPH_E_INVALID (enable outside [0, 2]), MPSPH_E_STATE. */
 MPSPH_API int mpsph_profile(mpsph_ctx *ctx, int32_t enable);
 MPSPH_API int mpsph_profile_read(mpsph_ctx *ctx, int32_t cap, const char **names, int64_t *launches,
                        double *ms, int32_t *count);

@@ -1742,6 +1742,8 @@ struct EventHook : LaunchHook {
   };
   hipStream_t stream = nullptr;
   bool on = false;
+  bool pairs_only = false;   // record only the pair passes (kernels named pass_*)
+  bool open = false;         // the last begin() recorded an event
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
   std::vector<std::string> names;
@@ -1758,13 +1760,15 @@ struct EventHook : LaunchHook {
     return e;
   }
   void begin(const char *name) override {
-    if (!on) return;
+    open = on && (!pairs_only || std::strncmp(name, "pass_", 5) == 0);
+    if (!open) return;
     Rec r{name, get(), get()};
     (void)hipEventRecord(r.a, stream);
     pending.push_back(r);
   }
   void end() override {
-    if (!on) return;
+    if (!open) return;
+    open = false;
     (void)hipEventRecord(pending.back().b, stream);
   }
   void collect() {
@@ -3361,11 +3365,12 @@ int mpsph_grad(mpsph_ctx *ctx, int32_t nsteps, int32_t ckpt_every, double lambda
 }
 
 int mpsph_profile(mpsph_ctx *ctx, int32_t enable) {
-  if (!ctx) return MPSPH_E_INVALID;
+  if (!ctx || enable < 0 || enable > 2) return MPSPH_E_INVALID;
   if (ctx->poisoned) return MPSPH_E_STATE;
   ctx->hook.collect();
   if (enable) ctx->hook.reset();
   ctx->hook.on = enable != 0;
+  ctx->hook.pairs_only = enable == 2;
   return MPSPH_OK;
 }
 

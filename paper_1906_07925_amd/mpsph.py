@@ -410,8 +410,9 @@ class Relaxer:
                                 C.c_void_p(gx.data_ptr()) if gx is not None else None), "mpsph_grad")
         return loss.value, gc[:int(n_rbf)], gx
 
-    def profile(self, on: bool):
-        _check(lib().mpsph_profile(self._ctx, 1 if on else 0), "mpsph_profile")
+    def profile(self, on):
+        """True: time every kernel launch; "pairs": only the pair passes; False: stop."""
+        _check(lib().mpsph_profile(self._ctx, 2 if on == "pairs" else (1 if on else 0)), "mpsph_profile")
 
     def profile_read(self) -> dict:
         cap = 64

@@ -186,6 +186,32 @@ def test_colour_labels_compare_by_equality_only(torch_cuda):
     R.close()
 
 
+def test_profile_modes(torch_cuda):
+    """mpsph_profile: 1 times every kernel launch, 2 only the pair passes (same launch counts for
+    those), and values outside [0, 2] are refused."""
+    torch = torch_cuda
+    from paper_1906_07925_amd import mpsph as M
+    cfg = W.config("square_4k", scale=0.25)
+    x32, col, typ = PU.state_f32(cfg)
+    spec = dict(cfg["spec"], n=x32.shape[0])
+    R = M.Relaxer(spec, n=x32.shape[0], s0=_s0(spec))
+    R.load(torch.from_numpy(x32).cuda(), torch.from_numpy(col).cuda(), torch.from_numpy(typ).cuda())
+    R.profile(True)
+    R.step(3)
+    every = R.profile_read()
+    R.profile("pairs")
+    R.step(3)
+    pairs = R.profile_read()
+    R.profile(False)
+    assert sorted(pairs) == sorted(k for k in every if k.startswith("pass_")) and len(pairs) == 2
+    assert len(every) > len(pairs)
+    assert all(pairs[k][0] == every[k][0] == 3 for k in pairs)
+    with pytest.raises(M.MpsphError) as e:
+        M._check(M.lib().mpsph_profile(R._ctx, 3), "mpsph_profile")
+    assert e.value.code == 1
+    R.close()
+
+
 def test_momentum_conservation(torch_cuda):
     cfg = W.config("cube_inclusion_2m", scale=0.01)
     x32, col, typ = PU.state_f32(cfg)
