@@ -339,7 +339,9 @@ __device__ bool stage_tile(TileLds *T, bool active, int sub, const int *ci, cons
 // block numbers refer to); rowtab is the block's LDS row table, tile the LDS copy of the
 // neighbours of the TILE variant (unused otherwise).  With PIPE the scan issues the neighbour
 // loads of a lane's next slot before the arithmetic of the current one (same arithmetic, same
-// order: the results do not depend on it).
+// order: the results do not depend on it).  The single-domain passes take it except in 3D
+// periodic boxes, where the minimum image's extra registers would spill; the persistent and
+// staged variants keep the one-round body.
 #define MPSPH_PASS1_PARAMS                                                                                   \
   const DomDev *__restrict__ doms, int ndom, const int64_t *__restrict__ stepctr,                            \
       const uint32_t *__restrict__ wkey, const float4 *__restrict__ wpos, const uint32_t *__restrict__ wjaux, \
@@ -579,7 +581,7 @@ __device__ __forceinline__ void density_force_block(int lb, uint4 *rowtab, TileL
 template <int D, int L, bool PER, bool DBG>
 __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_density_force(int b0, MPSPH_PASS1_PARAMS) {
   __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
-  density_force_block<D, L, PER, DBG, false, !PER>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, nullptr, MPSPH_PASS1_ARGS);
+  density_force_block<D, L, PER, DBG, false, !PER || D == 2>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, nullptr, MPSPH_PASS1_ARGS);
 }
 
 // The staged copy limits a CU to 4 blocks (4 waves per SIMD), which the register budget follows.
@@ -910,7 +912,7 @@ __device__ __forceinline__ void viscous_integrate_block(int lb, uint4 *rowtab, M
 template <int D, int L, bool PER>
 __global__ __launch_bounds__(kBlock) MPSPH_PAIR_OCCUPANCY void pass_viscous_integrate(int b0, MPSPH_PASS2_PARAMS) {
   __shared__ uint4 rowtab[row_table_rows<L>() * row_table_stride<L>()];
-  viscous_integrate_block<D, L, PER, !PER>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, MPSPH_PASS2_ARGS);
+  viscous_integrate_block<D, L, PER, !PER || D == 2>(b0 + xcd_block(blockIdx.x, gridDim.x), rowtab, MPSPH_PASS2_ARGS);
 }
 
 
