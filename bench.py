@@ -376,7 +376,7 @@ def variants_run(torch, M, W, steps: int = 100, warmup: int = 20, graph_steps: i
         R.load(dx, dc)
         R.step(warmup)
         torch.cuda.synchronize()
-        R.profile(True)
+        R.profile("pairs")
         t0 = time.perf_counter()
         R.step(steps)
         torch.cuda.synchronize()
