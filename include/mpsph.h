@@ -334,7 +334,7 @@ MPSPH_API int mpsph_debug_fields(mpsph_ctx *ctx, int32_t which, float *d_out);
  * original order: cellbase + xf + 2^(k+xe) row, where cellbase is 0 for a single domain and in a
  * batch the first cell of the domain's range of the global cell table; xf = cx 2^xe + floor(ox 2^xe)
  * is the x cell at 2^xe sub-cells per cell (ox the float32 offset in [0, 1) within the cell,
- * xe the largest of 0..3 with dim k + xe <= 26 and 2^(dim k + xe) <= 4 n for the domain's n
+ * xe the largest of 0..4 with dim k + xe <= 26 and 2^(dim k + xe) <= 4 n for the domain's n
  * particles, so a domain has 2^(dim k + xe) cells); row = cy in 2D, and in 3D the
  * rows are numbered in tiles of 2^ly x 2^lz rows, ly = min(4, k), lz = min(4, k):
  * row = (cy mod 2^ly) + 2^ly (cz mod 2^lz) + 2^(ly+lz) floor(cy / 2^ly) + 2^(k+lz) floor(cz / 2^lz)),

@@ -36,9 +36,10 @@ enum : int {
 // an integer cell coordinate per axis plus a float offset in [0, 1).
 // Most sub-cells per cell along x in the cell key (log2).  Measured on the 2M-particle graded
 // cube at 2^6 cells: 0 / 1 / 2 / 3 / 4 bits give 4.49 / 4.03 / 3.84 / 3.76 / 3.79 ms per step
-// (4 lanes, before the row-table scan; with it and 8 lanes 4 bits gain only 0.3 % over 3).
+// (4 lanes, before the row-table scan; with it and 8 lanes 4 bits gain only 0.3 % over 3); with
+// the neighbour loads one slot round ahead 3 / 4 / 5 bits give 2.516 / 2.496 / 2.510 ms.
 #ifndef MPSPH_XSUB
-#define MPSPH_XSUB 3
+#define MPSPH_XSUB 4
 #endif
 
 // Row tiles of the 3D cell key (log2 of the tile's rows along y and z).  Measured on the

@@ -83,7 +83,7 @@ def test_keys_and_cell_table_bit_exact(torch_cuda):
         xe = int(np.log2(ncells)) - d * k
         n = x32.shape[0]
         expect_xe = 0
-        while expect_xe < 3 and d * k + expect_xe < 26 and 2 ** (d * k + expect_xe + 1) <= 4 * n:
+        while expect_xe < 4 and d * k + expect_xe < 26 and 2 ** (d * k + expect_xe + 1) <= 4 * n:
             expect_xe += 1
         assert ncells == 2 ** (d * k + xe) and xe == expect_xe
         xf = (c[:, 0] << xe) | np.floor(frac[:, 0] * np.float32(2 ** xe)).astype(np.int64)
