@@ -498,11 +498,13 @@ def main():
     t1 = time.perf_counter()
     m1 = R.metrics()
     kern = R.profile_read()
-    R.profile(True)
-    R.step(args.kernel_steps)
-    torch.cuda.synchronize()
-    m2 = R.metrics()
-    kern_all = R.profile_read()
+    kern_all, m2 = {}, m1
+    if args.kernel_steps > 0:
+        R.profile(True)
+        R.step(args.kernel_steps)
+        torch.cuda.synchronize()
+        m2 = R.metrics()
+        kern_all = R.profile_read()
     R.profile(False)
     elapsed = t1 - t0
     pairs = m1["pairs_total"] - m0["pairs_total"]
